@@ -1,0 +1,54 @@
+"""H1-seminorm and L2 errors of a discrete solution against an exact one,
+integrated by Gauss quadrature with p+3 points per element in physical
+coordinates (the error measure of Section 4, Table 1).  CPU oracle, test
+infrastructure only."""
+from __future__ import annotations
+
+import numpy as np
+
+from .bspline import basis_matrix, gauss_points
+from .geometry import tensor_apply
+
+
+def _grad_fd(fn, X, h=1e-6):
+    g = []
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        g.append((fn(X + e) - fn(X - e)) / (2 * h))
+    return np.stack(g, -1)
+
+
+def errors(knots3, p, ctrl, u_coef, u_fn, grad_fn=None):
+    """Relative (L2, H1-seminorm) errors of u_h = sum_j u_j b_j o F^{-1} (interior
+    coefficients, x fastest) against u_fn (callable on (..., 3) physical points)."""
+    pts, wts, B, D = [], [], [], []
+    for k in knots3:
+        x, w = gauss_points(k, p + 3)
+        pts.append(x)
+        wts.append(w)
+        B.append(basis_matrix(k, p, x, 0))
+        D.append(basis_matrix(k, p, x, 1))
+    F = np.stack([tensor_apply(B[2], B[1], B[0], ctrl[..., a]) for a in range(3)], -1)
+    J = np.empty(F.shape + (3,))
+    for a in range(3):
+        for b in range(3):
+            M = [D[l] if l == b else B[l] for l in range(3)]
+            J[..., a, b] = tensor_apply(M[2], M[1], M[0], ctrl[..., a])
+    n = [b.shape[1] - 2 for b in B]
+    U = np.zeros((n[2] + 2, n[1] + 2, n[0] + 2))
+    U[1:-1, 1:-1, 1:-1] = np.asarray(u_coef).reshape(n[2], n[1], n[0])
+    uh = tensor_apply(B[2], B[1], B[0], U)
+    gxi = []
+    for b in range(3):
+        M = [D[l] if l == b else B[l] for l in range(3)]
+        gxi.append(tensor_apply(M[2], M[1], M[0], U))
+    gxi = np.stack(gxi, -1)
+    detJ = np.linalg.det(J)
+    gx = np.einsum("...ba,...b->...a", np.linalg.inv(J), gxi)   # J^{-T} grad_xi
+    wq = np.einsum("k,j,i->kji", wts[2], wts[1], wts[0]) * np.abs(detJ)
+    ue = u_fn(F)
+    ge = grad_fn(F) if grad_fn is not None else _grad_fd(u_fn, F)
+    l2 = np.sqrt(np.sum(wq * (uh - ue) ** 2) / np.sum(wq * ue ** 2))
+    h1 = np.sqrt(np.sum(wq[..., None] * (gx - ge) ** 2) / np.sum(wq[..., None] * ge ** 2))
+    return l2, h1

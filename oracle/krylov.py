@@ -1,0 +1,56 @@
+"""Right-preconditioned BiCGStab (van der Vorst 1992), the Krylov method the
+paper uses for the non-symmetric WQ systems (Section 4).  CPU oracle, test
+infrastructure only.
+
+Reading R8: x0 = 0 unless given, shadow residual r^ = r0, stop when the
+recurrence residual satisfies |r|_2 / |b|_2 <= tol (then confirmed with the true
+residual b - A x; the iteration continues if the confirmation fails).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def bicgstab(A, b, M=None, tol=1e-10, maxit=1000, x0=None):
+    """Solve A x = b with right preconditioner M (x = M y).  ``A`` and ``M`` are
+    callables.  Returns (x, iterations, relres, history)."""
+    M = M or (lambda r: r)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - A(x) if x0 is not None else b.copy()
+    if nb == 0:
+        return x, 0, 0.0, []
+    rh = r.copy()
+    rho_old = alpha = omega = 1.0
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    hist = []
+    for it in range(1, maxit + 1):
+        rho = rh @ r
+        beta = (rho / rho_old) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        ph = M(p)
+        v = A(ph)
+        alpha = rho / (rh @ v)
+        s = r - alpha * v
+        if np.linalg.norm(s) / nb <= tol:
+            x = x + alpha * ph
+            rel = np.linalg.norm(b - A(x)) / nb
+            if rel <= tol:
+                hist.append(rel)
+                return x, it, rel, hist
+        sh = M(s)
+        t = A(sh)
+        omega = (t @ s) / (t @ t)
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        rho_old = rho
+        rel = np.linalg.norm(r) / nb
+        hist.append(rel)
+        if rel <= tol:
+            true = np.linalg.norm(b - A(x)) / nb
+            if true <= tol:
+                return x, it, true, hist
+            r = b - A(x)
+    return x, maxit, np.linalg.norm(b - A(x)) / nb, hist

@@ -1,0 +1,161 @@
+"""The MF-WQ stiffness operator (Sections 2.2-3.2).  CPU oracle, test
+infrastructure only.
+
+K~ = sum_{alpha,beta=1..3} W^(alpha,beta) D^(alpha,beta) B^(beta)          (Section 3.2)
+
+with, for direction l (x = 1 fastest, Kronecker order of eq. ordering):
+    B^(beta)        = B_3^(b3) (x) B_2^(b2) (x) B_1^(b1),   b_l = [l == beta]
+    W^(alpha,beta)  = W_3^{a3 b3} (x) W_2^{a2 b2} (x) W_1^{a1 b1},   a_l = [l == alpha]
+    D^(alpha,beta)  = diag(C_{alpha beta}(x_q))
+where B_l^(0) = B_l, B_l^(1) = B-dot_l and W_l^{ab} are the 1D weights of the
+rule for int b_i^{(a)} b_j^{(b)} (eq. exactness_K).
+
+``assemble`` builds K~ explicitly as a scipy.sparse matrix (small sizes only);
+``apply`` / ``apply_T`` evaluate K~ v and K~^T v with one 1D product per mode
+(eq. sum-factorization) and no fusion.  ``rhs`` is the load vector of reading
+R6: b_i = sum_q W^(00)_{iq} det J(x_q) f(F(x_q)) (weighted-quadrature mass rule,
+Section 3.1, eq. main).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .geometry import SYM_PAIRS, coefficient_planes, coefficient_tensor, map_and_jacobian
+from .wq import Space1D
+
+_PLANE = {}
+for _c, (_a, _b) in enumerate(SYM_PAIRS):
+    _PLANE[(_a, _b)] = _c
+    _PLANE[(_b, _a)] = _c
+
+
+def ab_indices(alpha: int, beta: int):
+    """Per-direction (a_l, b_l) for the pair (alpha, beta), 0-based directions."""
+    return [(int(l == alpha), int(l == beta)) for l in range(3)]
+
+
+def mode(A, X, axis):
+    """Apply the matrix A along ``axis`` of the 3D array X (axis 2 = x, 0 = z)."""
+    return np.moveaxis(np.tensordot(A, X, axes=(1, axis)), 0, axis)
+
+
+class Problem:
+    """Spaces, geometry and coefficient planes of one single-patch problem."""
+
+    def __init__(self, knots3, p, ctrl, K_fn=None):
+        self.p = p
+        self.spaces = [Space1D(k, p) for k in knots3]
+        S1, S2, S3 = self.spaces
+        self.n = (S1.n, S2.n, S3.n)
+        self.nq = (S1.nq, S2.nq, S3.nq)
+        self.N = S1.n * S2.n * S3.n
+        self.Nq = S1.nq * S2.nq * S3.nq
+        self.F, self.J = map_and_jacobian(self.spaces, ctrl)
+        self.set_K(K_fn(self.F) if K_fn is not None else None)
+
+    def set_K(self, K):
+        self.K = K
+        C, self.detJ = coefficient_tensor(self.J, K)
+        self.C = coefficient_planes(C)          # (6, nq3, nq2, nq1)
+
+    # -- factors -----------------------------------------------------------
+    def Wk(self, alpha, beta):
+        ab = ab_indices(alpha, beta)
+        S = self.spaces
+        return [S[l].W[ab[l]] for l in range(3)]
+
+    def Bk(self, beta):
+        S = self.spaces
+        return [S[l].B[int(l == beta)] for l in range(3)]
+
+    def plane(self, alpha, beta):
+        return self.C[_PLANE[(alpha, beta)]]
+
+    # -- explicit assembly (small sizes) -----------------------------------
+    def assemble(self, C=None):
+        C = self.C if C is None else C
+        K = None
+        for al in range(3):
+            for be in range(3):
+                W1, W2, W3 = self.Wk(al, be)
+                B1, B2, B3 = self.Bk(be)
+                Wk = sp.kron(sp.csr_matrix(W3), sp.kron(sp.csr_matrix(W2), sp.csr_matrix(W1)))
+                Bk = sp.kron(sp.csr_matrix(B3), sp.kron(sp.csr_matrix(B2), sp.csr_matrix(B1)))
+                D = sp.diags(C[_PLANE[(al, be)]].ravel())
+                term = (Wk @ D @ Bk).tocsr()
+                K = term if K is None else K + term
+        return K.tocsr()
+
+    # -- matrix-free products ---------------------------------------------
+    def _shape(self, v, q=False):
+        n = self.nq if q else self.n
+        return np.asarray(v, dtype=np.float64).reshape(n[2], n[1], n[0])
+
+    def grad_at_quad(self, v):
+        """v~^(beta) = B^(beta) v for beta = 1..3 (Algorithm 2, first step)."""
+        V = self._shape(v)
+        out = []
+        for be in range(3):
+            B1, B2, B3 = self.Bk(be)
+            out.append(mode(B3, mode(B2, mode(B1, V, 2), 1), 0))
+        return out
+
+    def test_contract(self, alpha, beta, Q):
+        W1, W2, W3 = self.Wk(alpha, beta)
+        return mode(W3, mode(W2, mode(W1, Q, 2), 1), 0)
+
+    def test_contract_T(self, alpha, beta, Y):
+        W1, W2, W3 = self.Wk(alpha, beta)
+        return mode(W3.T, mode(W2.T, mode(W1.T, Y, 2), 1), 0)
+
+    def apply(self, v):
+        """w = K~ v following Algorithm 2 step by step."""
+        g = self.grad_at_quad(v)
+        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+        for be in range(3):
+            for al in range(3):
+                w += self.test_contract(al, be, self.plane(al, be) * g[be])
+        return w.ravel()
+
+    def apply_T(self, v):
+        """w = K~^T v = sum_{alpha,beta} B^(beta)^T D^(alpha,beta) W^(alpha,beta)^T v."""
+        Y = self._shape(v)
+        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+        for be in range(3):
+            acc = np.zeros((self.nq[2], self.nq[1], self.nq[0]))
+            for al in range(3):
+                acc += self.plane(al, be) * self.test_contract_T(al, be, Y)
+            B1, B2, B3 = self.Bk(be)
+            w += mode(B3.T, mode(B2.T, mode(B1.T, acc, 2), 1), 0)
+        return w.ravel()
+
+    def explicit_row(self, i):
+        """Row i of K~ from the definition eq. Kwq, without forming the matrix:
+        K~_ij = sum_{ab} sum_q w^(ab)_{iq} C_ab(x_q) d_b b_j(x_q)."""
+        n1, n2, n3 = self.n
+        i1, i2, i3 = i % n1, (i // n1) % n2, i // (n1 * n2)
+        row = np.zeros(self.N)
+        for al in range(3):
+            for be in range(3):
+                W1, W2, W3 = self.Wk(al, be)
+                Q = np.einsum("c,b,a->cba", W3[i3], W2[i2], W1[i1]) * self.plane(al, be)
+                B1, B2, B3 = self.Bk(be)
+                row += np.einsum("cba,ck,bj,ai->kji", Q, B3, B2, B1, optimize=True).ravel()
+        return row
+
+    # -- load vector and mass-type pieces ----------------------------------
+    def W00(self, Q):
+        S = self.spaces
+        return mode(S[2].W[(0, 0)], mode(S[1].W[(0, 0)], mode(S[0].W[(0, 0)], Q, 2), 1), 0)
+
+    def W00_T(self, Y):
+        S = self.spaces
+        return mode(S[2].W[(0, 0)].T, mode(S[1].W[(0, 0)].T, mode(S[0].W[(0, 0)].T, Y, 2), 1), 0)
+
+    def rhs(self, f_q):
+        """Reading R6: b = W^(00) (det J f) with f sampled at the quadrature points."""
+        return self.W00(self.detJ * np.asarray(f_q).reshape(self.detJ.shape)).ravel()
+
+    def rhs_from(self, f_fn):
+        return self.rhs(f_fn(self.F))

@@ -1,0 +1,113 @@
+"""Weighted-quadrature points and weights (Section 2.2).  CPU oracle, test
+infrastructure only.
+
+Readings of the paper used here (the library implements the same readings with
+its own code):
+
+R1 (quadrature points; the paper gives "midpoints and endpoints of each knot
+   span, with a few more points in the first and last span"): all breakpoints,
+   the midpoint of every element except the first and the last, and p+1
+   equispaced interior points t_0 + k h/(p+2), k = 1..p+1, in the first element
+   (mirrored in the last).  n_q = 2 n_el + 2 p + 1.
+R2 (the local exactness systems are underdetermined and, for derivative trial
+   functions, rank deficient): the minimum-2-norm solution, via an SVD
+   pseudo-inverse with relative rank cut-off 1e-12.  Rows are first scaled to
+   unit 2-norm: that leaves the solution set of the (consistent) system, hence
+   its minimum-norm element, unchanged and makes the solve far better
+   conditioned (trial functions that barely overlap supp(b_i) give tiny rows).
+R3 (exactness trial set): exactness is imposed for every trial B-spline b_j,
+   j = 0..m-1 (boundary ones included), not only the interior ones; functions
+   with |j - i| > p vanish with their first derivative on supp(b_i) for p >= 2,
+   so the local system only carries |j - i| <= p.
+
+Weights depend on (a, b) = (test derivative order, trial derivative order):
+    sum_q W^{ab}_{i q} b_j^{(b)}(x_q) = int b_i^{(a)} b_j^{(b)}     (eqs. exactness1d, exactness_K)
+    W^{ab}_{i q} = 0 if x_q outside supp(b_i)                         (eq. weights-support)
+for interior test functions i = 1..m-2 (0-based), giving W^{ab} in R^{n x n_q}.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .bspline import basis_matrix, breakpoints, galerkin_1d, n_basis
+
+RANK_RTOL = 1e-12
+
+
+def quad_points(knots, p: int) -> np.ndarray:
+    """Reading R1 of the point placement (Section 2.2)."""
+    br = breakpoints(knots)
+    n_el = len(br) - 1
+    if n_el < 2:
+        raise ValueError("need at least two elements")
+    pts = list(br)
+    for e in range(1, n_el - 1):
+        pts.append(0.5 * (br[e] + br[e + 1]))
+    for e in (0, n_el - 1):
+        h = br[e + 1] - br[e]
+        pts.extend(br[e] + k * h / (p + 2) for k in range(1, p + 2))
+    return np.array(sorted(pts))
+
+
+def interior_B(knots, p: int, xq, deriv: int) -> np.ndarray:
+    """B_l (deriv 0) or B-dot_l (deriv 1): [n_q, n] values of the interior
+    B-splines j = 1..m-2 at the quadrature points (eq. Bl and its derivative)."""
+    m = n_basis(knots, p)
+    return basis_matrix(knots, p, xq, deriv)[:, 1:m - 1]
+
+
+def local_system(knots, p, xq, i, a, b, Bfull=None, G=None):
+    """Unknown set S_i, equation set T_i, matrix A (|T_i| x |S_i|) and right-hand
+    side of the exactness conditions for test function i and derivative pair (a,b)."""
+    t = np.asarray(knots, dtype=np.float64)
+    m = n_basis(t, p)
+    if Bfull is None:
+        Bfull = basis_matrix(t, p, xq, b)
+    if G is None:
+        G = galerkin_1d(t, p, a, b)
+    lo, hi = t[i], t[i + p + 1]
+    S = np.nonzero((xq >= lo) & (xq <= hi))[0]
+    T = np.array([j for j in range(m) if abs(j - i) <= p])
+    A = Bfull[np.ix_(S, T)].T
+    rhs = G[i, T]
+    return S, T, A, rhs
+
+
+def weights(knots, p: int, xq=None):
+    """All four 1D weight matrices {(a, b): W^{ab}} (each n x n_q)."""
+    t = np.asarray(knots, dtype=np.float64)
+    if xq is None:
+        xq = quad_points(t, p)
+    m = n_basis(t, p)
+    nq = len(xq)
+    Bf = {b: basis_matrix(t, p, xq, b) for b in (0, 1)}
+    out = {}
+    for a in (0, 1):
+        for b in (0, 1):
+            G = galerkin_1d(t, p, a, b)
+            W = np.zeros((m - 2, nq))
+            for i in range(1, m - 1):
+                S, T, A, rhs = local_system(t, p, xq, i, a, b, Bf[b], G)
+                d = 1.0 / np.linalg.norm(A, axis=1)
+                w, _, _, _ = np.linalg.lstsq(d[:, None] * A, d * rhs, rcond=RANK_RTOL)
+                W[i - 1, S] = w
+            out[(a, b)] = W
+    return out
+
+
+class Space1D:
+    """Everything one direction contributes: knots, points, B, B-dot, W^{ab}."""
+
+    def __init__(self, knots, p: int):
+        self.knots = np.asarray(knots, dtype=np.float64)
+        self.p = p
+        self.m = n_basis(self.knots, p)
+        self.n = self.m - 2
+        self.xq = quad_points(self.knots, p)
+        self.nq = len(self.xq)
+        self.B = {b: interior_B(self.knots, p, self.xq, b) for b in (0, 1)}
+        self.Bfull = {b: basis_matrix(self.knots, p, self.xq, b) for b in (0, 1)}
+        self.W = weights(self.knots, p, self.xq)
+        # interior 1D Galerkin mass and stiffness (used by FD and by pins)
+        self.M = galerkin_1d(self.knots, p, 0, 0)[1:-1, 1:-1]
+        self.K = galerkin_1d(self.knots, p, 1, 1)[1:-1, 1:-1]

@@ -1,0 +1,309 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix, none of
+which re-types the oracle's own formulas:
+
+* B-splines against scipy.interpolate.BSpline (an independent library routine);
+* 1D Galerkin integrals against adaptive scipy.integrate.quad of scipy B-splines,
+  plus closed forms (integral of a B-spline, integration by parts);
+* weights: exactness (eqs. exactness1d, exactness_K), support (eq. weights-support),
+  the minimum-norm characterisation (orthogonal to the null space, reading R2),
+  nonzero counts (Section 2.2);
+* the Kronecker ordering identity (eq. ordering) and sum-factorisation
+  (eq. sum-factorization) against dense Kronecker products;
+* identity geometry with constant K: K~ equals the exact Galerkin stiffness
+  (consequence of eq. exactness_K), both for K = I and for a full SPD K;
+* convergence of manufactured solutions at the spline rate (Table 1 rates);
+* the C = det J J^{-1} K J^{-T} convention (reading R5) by a sheared affine map,
+  with the transposed convention planted in the oracle to show it fails;
+* FD: generalized eigen-identities, exact inverse of its Kronecker form, and
+  one-iteration convergence on the identity cube;
+* load vector: exact for sources in the spline space (reading R3, R6).
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.integrate as si
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+from scipy.interpolate import BSpline
+
+import synth
+from oracle import bspline, geometry, wq
+from oracle.errors import errors
+from oracle.fd import FD
+from oracle.krylov import bicgstab
+from oracle.operator import Problem, mode
+
+ROOT = __import__("os").path.dirname(__import__("os").path.abspath(__file__))
+
+
+def nonuniform_knots(n_el, p, seed=3):
+    rng = np.random.default_rng(seed)
+    br = np.sort(rng.uniform(0.05, 0.95, n_el - 1))
+    return np.concatenate([np.zeros(p + 1), br, np.ones(p + 1)])
+
+
+# ---------------------------------------------------------------- B-splines
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+def test_basis_matches_scipy(p):
+    k = nonuniform_knots(7, p)
+    m = len(k) - p - 1
+    x = np.concatenate([np.linspace(0, 1, 257), k[p:-p]])   # includes knots and x = 1
+    B = bspline.basis_matrix(k, p, x, 0)
+    D = bspline.basis_matrix(k, p, x, 1)
+    Bs = BSpline.design_matrix(x, k, p).toarray()
+    Ds = np.stack([BSpline(k, np.eye(m)[j], p).derivative()(x) for j in range(m)], 1)
+    assert np.abs(B - Bs).max() < 1e-14
+    assert np.abs(D - Ds).max() < 1e-11 * np.abs(Ds).max()
+    assert np.abs(B.sum(1) - 1).max() < 1e-14           # partition of unity
+    assert np.abs(D.sum(1)).max() < 1e-11 * np.abs(D).max()
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_galerkin_1d_against_adaptive_quadrature(p):
+    k = nonuniform_knots(5, p, seed=7)
+    m = len(k) - p - 1
+    br = np.unique(k)
+    sp = [BSpline(k, np.eye(m)[j], p) for j in range(m)]
+    dsp = [s.derivative() for s in sp]
+    fns = {0: sp, 1: dsp}
+    rng = np.random.default_rng(0)
+    for a in (0, 1):
+        for b in (0, 1):
+            G = bspline.galerkin_1d(k, p, a, b)
+            for _ in range(6):
+                i, j = rng.integers(0, m, 2)
+                ref = sum(si.quad(lambda x: fns[a][i](x) * fns[b][j](x), lo, hi, epsabs=1e-15, epsrel=1e-13)[0]
+                          for lo, hi in zip(br[:-1], br[1:]))
+                assert abs(G[i, j] - ref) < 1e-12 * max(1.0, np.abs(G).max())
+    # closed forms: int b_i = (xi_{i+p+1} - xi_i)/(p+1); by parts G01 + G10^T = boundary terms
+    G00 = bspline.galerkin_1d(k, p, 0, 0)
+    assert np.allclose(G00.sum(1), (k[p + 1:p + 1 + m] - k[:m]) / (p + 1), atol=1e-15)
+    bp = bspline.galerkin_1d(k, p, 0, 1) + bspline.galerkin_1d(k, p, 1, 0)
+    E = np.zeros((m, m))
+    E[0, 0], E[-1, -1] = -1.0, 1.0
+    assert np.abs(bp - E).max() < 1e-12
+
+
+# ---------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("n_el,p", [(3, 2), (8, 3), (12, 6), (5, 10)])
+def test_point_count_and_nonzeros(n_el, p):
+    k = synth.uniform_knots(n_el, p)
+    xq = wq.quad_points(k, p)
+    assert len(xq) == 2 * n_el + 2 * p + 1                  # R1: ~2n, independent of p up to 2p
+    assert np.all(np.diff(xq) > 0)
+    W = wq.weights(k, p, xq)
+    for (a, b), Wab in W.items():
+        nnz = (np.abs(Wab) > 0).sum(1)
+        if n_el >= p + 2:                                   # no support spans both end elements
+            assert nnz.max() <= 3 * p + 3
+        if n_el >= 2 * p + 3:
+            mid = nnz[p:-p]                                  # rows away from the ends
+            assert np.all(mid == 2 * p + 3)                  # "roughly 2p" nonzeros per row
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 6])
+def test_weights_exact_supported_and_min_norm(p):
+    k = nonuniform_knots(9, p, seed=11)
+    m = len(k) - p - 1
+    xq = wq.quad_points(k, p)
+    W = wq.weights(k, p, xq)
+    for (a, b), Wab in W.items():
+        Bb = bspline.basis_matrix(k, p, xq, b)                # all m trial functions (R3)
+        G = bspline.galerkin_1d(k, p, a, b)[1:m - 1, :]
+        res = Wab @ Bb - G
+        assert np.abs(res).max() < 1e-12 * max(1.0, np.abs(G).max())
+        for i in range(1, m - 1):
+            lo, hi = k[i], k[i + p + 1]
+            outside = (xq < lo) | (xq > hi)
+            assert np.all(Wab[i - 1, outside] == 0.0)        # eq. weights-support
+            S, T, A, rhs = wq.local_system(k, p, xq, i, a, b)
+            As = A / np.linalg.norm(A, axis=1, keepdims=True)  # same null space as A
+            Z = sla.null_space(As, rcond=1e-10)               # min-norm <=> orthogonal to null(A)
+            w = Wab[i - 1, S]
+            s = np.linalg.svd(As, compute_uv=False)
+            cond = s[0] / s[s > 1e-12 * s[0]][-1]
+            assert np.abs(Z.T @ w).max() < 100 * cond * 2.2e-16 * np.abs(w).max()
+
+
+# ---------------------------------------------------------------- Kronecker / sum factorisation
+def test_kronecker_ordering_and_sum_factorisation():
+    rng = np.random.default_rng(5)
+    A1, A2, A3 = rng.standard_normal((4, 3)), rng.standard_normal((5, 2)), rng.standard_normal((3, 4))
+    Kr = np.kron(A3, np.kron(A2, A1))
+    for _ in range(20):
+        i1, i2, i3 = rng.integers(0, 4), rng.integers(0, 5), rng.integers(0, 3)
+        j1, j2, j3 = rng.integers(0, 3), rng.integers(0, 2), rng.integers(0, 4)
+        i = i1 + 4 * (i2 + 5 * i3)                           # eq. ordering, x fastest
+        j = j1 + 3 * (j2 + 2 * j3)
+        assert abs(Kr[i, j] - A1[i1, j1] * A2[i2, j2] * A3[i3, j3]) < 1e-14
+    x = rng.standard_normal(3 * 2 * 4)
+    X = x.reshape(4, 2, 3)
+    y = mode(A3, mode(A2, mode(A1, X, 2), 1), 0).ravel()
+    assert np.allclose(y, Kr @ x, atol=1e-13)
+
+
+def test_matrix_free_equals_explicit_on_curved_geometry():
+    w = synth.workload("ring8_p3")
+    pr = Problem(w.knots(), w.p, w.ctrl(), w.K_field())
+    K = pr.assemble()
+    v = synth.random_vector(pr.N, 1)
+    assert np.linalg.norm(pr.apply(v) - K @ v) <= 1e-13 * np.linalg.norm(K @ v)
+    assert np.linalg.norm(pr.apply_T(v) - K.T @ v) <= 1e-13 * np.linalg.norm(K.T @ v)
+    for i in (0, 17, pr.N // 2, pr.N - 1):
+        r = K[i].toarray().ravel()
+        assert np.linalg.norm(pr.explicit_row(i) - r) <= 1e-13 * np.linalg.norm(r)
+
+
+# ---------------------------------------------------------------- exactness consequences
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_identity_geometry_gives_exact_galerkin_stiffness(p):
+    k = synth.uniform_knots(5, p)
+    kn = (k, k, k)
+    pr = Problem(kn, p, synth.control_net("identity", kn, p))
+    K = pr.assemble().toarray()
+    P = FD(pr.spaces).P_matrix().toarray()                   # Galerkin Kronecker sum
+    assert np.abs(K - P).max() <= 1e-13 * np.abs(P).max()
+
+
+def test_identity_geometry_full_constant_K():
+    p = 3
+    k = nonuniform_knots(5, p, seed=2)
+    kn = (k, k, k)
+    Kc = np.array([[2.0, 0.5, 0.3], [0.5, 1.5, 0.2], [0.3, 0.2, 1.0]])
+    K6 = np.array([Kc[a, b] for a, b in geometry.SYM_PAIRS])
+    pr = Problem(kn, p, synth.control_net("identity", kn, p),
+                 lambda X: np.broadcast_to(K6, X.shape[:-1] + (6,)).copy())
+    Kt = pr.assemble().toarray()
+    m = len(k) - p - 1
+    G = {(a, b): bspline.galerkin_1d(k, p, a, b)[1:m - 1, 1:m - 1] for a in (0, 1) for b in (0, 1)}
+    ref = 0
+    for al in range(3):
+        for be in range(3):
+            ab = [(int(l == al), int(l == be)) for l in range(3)]
+            ref = ref + Kc[al, be] * np.kron(G[ab[2]], np.kron(G[ab[1]], G[ab[0]]))
+    assert np.abs(Kt - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _rates(errs):
+    return [math.log2(a / b) for a, b in zip(errs[:-1], errs[1:])]
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_manufactured_solution_converges_at_spline_rate(p):
+    paper = {int(r[0]): r[1:] for r in np.loadtxt(f"{ROOT}/golden/table1_h1_errors.txt")}
+    paper_rate = math.log2(paper[p][3] / paper[p][4])        # finest pair of Table 1
+    h1s = []
+    for ne in (4, 8, 16):
+        k = synth.uniform_knots(ne, p)
+        kn = (k, k, k)
+        ctrl = synth.control_net("identity", kn, p)
+        pr = Problem(kn, p, ctrl)
+        # identity geometry: FD is the exact inverse (pinned below), one iteration
+        u, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(synth.f_sine), FD(pr.spaces).apply, tol=1e-13)
+        assert it == 1
+        h1s.append(errors(kn, p, ctrl, u, synth.u_sine)[1])
+    r = _rates(h1s)[-1]
+    assert abs(r - p) < 0.3
+    assert abs(r - paper_rate) < 0.4
+
+
+# ---------------------------------------------------------------- C convention (R5)
+def _shear_problem(ne, p):
+    k = synth.uniform_knots(ne, p)
+    kn = (k, k, k)
+    ctrl = synth.control_net("shear", kn, p)
+    A = np.array([[1.0, 0.3, 0.1], [0.2, 1.2, -0.15], [0.05, 0.25, 0.9]])
+    Ai = np.linalg.inv(A)
+    S = Ai @ Ai.T
+
+    def uhat(xi):
+        return np.prod(np.sin(np.pi * xi), axis=-1)
+
+    def u(x):
+        return uhat(x @ Ai.T)
+
+    def f(x):
+        xi = x @ Ai.T
+        s, c = np.sin(np.pi * xi), np.cos(np.pi * xi)
+        H = np.empty(xi.shape[:-1] + (3, 3))
+        for a in range(3):
+            for b in range(3):
+                fa = [c[..., l] if l in (a, b) and a != b else s[..., l] for l in range(3)]
+                H[..., a, b] = np.pi ** 2 * np.prod(np.stack(fa, -1), -1) * (-1.0 if a == b else 1.0)
+        return -np.einsum("...ab,ab->...", H, S)
+    return kn, ctrl, u, f
+
+
+def test_coefficient_convention_by_sheared_map(monkeypatch):
+    p = 3
+    def h1_errs():
+        out = []
+        for ne in (4, 8):
+            kn, ctrl, u, f = _shear_problem(ne, p)
+            pr = Problem(kn, p, ctrl)
+            x = spla.spsolve(pr.assemble().tocsc(), pr.rhs_from(f))
+            out.append(errors(kn, p, ctrl, x, u)[1])
+        return out
+    good = h1_errs()
+    assert good[1] < 1.5e-3 and _rates(good)[0] > p - 0.4
+    # plant the transposed convention C = det J J^{-T} J^{-1} in the oracle: the pin must fail
+    real = geometry.coefficient_tensor
+
+    def wrong(J, K=None):
+        C, d = real(np.swapaxes(J, -1, -2), K)
+        return C, d
+    monkeypatch.setattr("oracle.operator.coefficient_tensor", wrong)
+    bad = h1_errs()
+    assert bad[1] > 10 * good[1]
+
+
+# ---------------------------------------------------------------- FD (R7)
+def test_fd_identities_and_exact_inverse():
+    p = 4
+    k = nonuniform_knots(6, p, seed=4)
+    pr = Problem((k, k, k), p, synth.control_net("identity", (k, k, k), p))
+    fd = FD(pr.spaces)
+    for U, lam, K, M in zip(fd.U, fd.lam, fd.K, fd.M):
+        assert np.abs(U.T @ M @ U - np.eye(len(lam))).max() < 1e-12
+        assert np.abs(U.T @ K @ U - np.diag(lam)).max() < 1e-10 * lam.max()
+    v = synth.random_vector(pr.N, 3)
+    assert np.linalg.norm(fd.apply(fd.P_apply(v)) - v) < 1e-12 * np.linalg.norm(v)
+    r = synth.random_vector(pr.N, 4)
+    z = spla.spsolve(fd.P_matrix().tocsc(), r)
+    assert np.linalg.norm(fd.apply(r) - z) < 1e-12 * np.linalg.norm(z)
+
+
+def test_identity_cube_converges_in_one_iteration():
+    w = synth.workload("cube12_p3")
+    pr = Problem(w.knots(), w.p, w.ctrl())
+    fd = FD(pr.spaces)
+    b = pr.rhs_from(w.f())
+    x, it, rel, _ = bicgstab(pr.apply, b, fd.apply, tol=1e-12)
+    assert it == 1 and rel < 1e-12
+
+
+def test_bicgstab_matches_direct_solve_on_ring():
+    w = synth.workload("ring8_p4")
+    pr = Problem(w.knots(), w.p, w.ctrl())
+    K = pr.assemble().tocsc()
+    b = pr.rhs_from(w.f())
+    x, it, rel, _ = bicgstab(pr.apply, b, FD(pr.spaces).apply, tol=1e-13)
+    xd = spla.spsolve(K, b)
+    assert rel <= 1e-13 and 1 < it < 60
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+# ---------------------------------------------------------------- load vector (R3, R6)
+def test_load_vector_exact_for_spline_sources():
+    p = 3
+    k = nonuniform_knots(6, p, seed=9)
+    kn = (k, k, k)
+    pr = Problem(kn, p, synth.control_net("identity", kn, p))
+    m = len(k) - p - 1
+    c = np.random.default_rng(1).standard_normal((m, m, m))     # all m^3 coefficients
+    fq = np.einsum("ck,bj,ai,kji->cba", *[pr.spaces[l].Bfull[0] for l in (2, 1, 0)], c)
+    b = pr.rhs(fq)
+    G = bspline.galerkin_1d(k, p, 0, 0)[1:m - 1, :]
+    ref = mode(G, mode(G, mode(G, c, 2), 1), 0).ravel()
+    assert np.linalg.norm(b - ref) <= 1e-13 * np.linalg.norm(ref)
