@@ -1,0 +1,217 @@
+/*
+ * wqfd.h -- C ABI of the MI355X (gfx950) matrix-free weighted-quadrature
+ * (MF-WQ) isogeometric solver: the WQ stiffness operator of Section 3.2
+ * (Algorithm 2), its transpose, the Fast Diagonalization (FD) preconditioner
+ * used in Section 4, and a right-preconditioned BiCGStab driver (Section 4).
+ *
+ * Model problem (Section 2.1, eq. poisson, with alpha = 0):
+ *     -div(K grad u) = f on Omega = F([0,1]^3),  u = 0 on the boundary,
+ * discretised with degree-p splines of maximum regularity on open knot
+ * vectors, homogeneous Dirichlet space of eq. (space): n = m - 2 interior
+ * B-splines per direction, N = n1 n2 n3 unknowns, x index fastest (eq. ordering).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: WQ_OK (0) or a negative WQ_E* code; wq_last_error() gives a
+ *    thread-local message for the last failure.
+ *  - Host pointers are read during the call only (setup copies what it keeps).
+ *  - Device pointers (vectors, fields, workspaces) are owned by the caller,
+ *    must be 256-byte aligned and must not alias each other unless stated.
+ *    A workspace passed to a *_setup call must stay allocated, untouched, until
+ *    the handle is destroyed.
+ *  - Work is enqueued on the given HIP stream and is asynchronous unless the
+ *    function says it synchronises.  Calls that share a handle must not run
+ *    concurrently on different streams.
+ *  - Layouts: DOF vectors [n3][n2][n1]; quadrature-point fields [nq3][nq2][nq1]
+ *    (x fastest), planes of N_q = nq1 nq2 nq3 values, one after another.
+ *  - Precision of vector arguments follows the `prec` argument:
+ *    WQ_F64 -> double*, WQ_F32 -> float*.
+ */
+#ifndef WQFD_H
+#define WQFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* wq_stream_t;   /* same type as hipStream_t */
+typedef struct wq_op_s* wq_op;              /* opaque WQ operator handle */
+typedef struct fd_pc_s* fd_pc;              /* opaque FD preconditioner handle */
+
+enum {
+    WQ_OK = 0,
+    WQ_EINVAL = -1,      /* bad argument: degree, knots, enum, size, null pointer */
+    WQ_EGEOM = -2,       /* det J <= 0 at some quadrature point */
+    WQ_ESINGULAR = -3,   /* weight system inexact, or FD mass matrix not SPD */
+    WQ_ENOMEM = -4,      /* workspace too small */
+    WQ_EHIP = -5,        /* HIP runtime error */
+    WQ_ENOCONV = -6,     /* iteration limit reached (x holds the last iterate) */
+    WQ_EBREAKDOWN = -7,  /* BiCGStab breakdown (rho or omega vanished) */
+    WQ_ENONFINITE = -8   /* NaN or Inf met in the iteration */
+};
+
+/* precision flags (bit mask at setup, single value per call) */
+enum { WQ_F64 = 1, WQ_F32 = 2, WQ_BF16 = 4 };
+
+/* coefficient tensor K at the quadrature points */
+enum {
+    WQ_K_IDENTITY = 0,   /* K = I; K_q ignored */
+    WQ_K_SCALAR = 1,     /* K = kappa I; K_q = kappa, one plane of N_q doubles */
+    WQ_K_SYM6 = 6        /* symmetric K; six planes (K11, K22, K33, K12, K13, K23) */
+};
+
+/* ------------------------------------------------------------------------ *
+ * wq_setup -- build the MF-WQ stiffness operator (Section 3.2, setup of
+ * Algorithm 2) from the knot vectors, degree and control points of the
+ * geometry map F (Section 2.1).
+ *   p            degree, 2 <= p <= 10.
+ *   nknots[l]    length of knots[l] (= m_l + p + 1); knots[l] host, open
+ *                (p+1 equal end knots, 0 and 1), non-decreasing, interior
+ *                knots simple (maximum regularity), at least 3 elements.
+ *   ctrl         host [m3][m2][m1][3] FP64 control points (all m_l functions).
+ *   k_kind,K_q   coefficient tensor (see WQ_K_*); K_q device FP64 or NULL
+ *                for WQ_K_IDENTITY.  May be changed later by wq_set_coef.
+ *   prec_mask    which apply precisions to prepare (WQ_F64 | WQ_F32).
+ *   ws,ws_bytes  device workspace; ws == NULL makes this a size query that
+ *                only writes *ws_needed (all other checks still run).
+ * Quadrature points: all breakpoints, interior-element midpoints and p+1
+ * equispaced interior points in each end element (n_q = 2 n_el + 2p + 1);
+ * weights: minimum-norm solutions of the exactness conditions for all m trial
+ * B-splines (eqs. exactness1d, weights-support, exactness_K).
+ * C = det(J) J^{-1} K J^{-T} with J = dF/dxi (eq. C).  Synchronises `s`.
+ * Errors: WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR, WQ_ENOMEM, WQ_EHIP.
+ * ------------------------------------------------------------------------ */
+int wq_setup(int p, const int32_t nknots[3], const double* const knots[3],
+             const double* ctrl, int k_kind, const double* K_q, int prec_mask,
+             void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, wq_op* out);
+
+/* Sizes: n[l] interior functions and nq[l] quadrature points per direction. */
+int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]);
+
+/* Quadrature points: xq host [nq1 + nq2 + nq3] parametric coordinates (or
+ * NULL); Fq device [3][N_q] physical points F(x_q) (or NULL).  Async on s. */
+int wq_quad_points(wq_op A, double* xq, double* Fq, wq_stream_t s);
+
+/* det J at the quadrature points into device [N_q] (FP64).  Async. */
+int wq_detj(wq_op A, double* detj, wq_stream_t s);
+
+/* Recompute the coefficient planes C = det J J^{-1} K J^{-T} from a new K_q
+ * (eq. C) without touching the geometry.  Async on s. */
+int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s);
+
+/* w = K~ v, Algorithm 2: w = sum_{a,b} W^(a,b) D^(a,b) B^(b) v (Section 3.2).
+ * prec: WQ_F64 or WQ_F32 (must have been prepared).  v, w device, N entries,
+ * must not alias.  Async on s. */
+int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
+
+/* w = K~^T v = sum_{a,b} B^(b)T D^(a,b) W^(a,b)T v (transpose of the
+ * factorisation of Section 3.2).  Same arguments as wq_apply.  Async. */
+int wq_apply_T(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
+
+/* Load vector b = W^(0,0) (det J f): the weighted-quadrature mass rule of
+ * Section 3.1 (eq. main) applied to f sampled at the quadrature points.
+ * f_q device [N_q] FP64, b device [N] FP64.  Async on s. */
+int wq_rhs(wq_op A, const double* f_q, double* b, wq_stream_t s);
+
+/* Adjoint gradients of J(u) with K~ u = b (derivative of the factorisation of
+ * Section 3.2 in the coefficient values):
+ *   dJ/dC_ab(q) = -(W^(a,b)T lam)_q (B^(b) u)_q, chained through eq. C to the
+ *   layout of K_q of the current k_kind (WQ_K_SCALAR: [N_q]; WQ_K_SYM6: [6][N_q];
+ *   WQ_K_IDENTITY: the six C planes).  gK device, overwritten.  Async. */
+int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream_t s);
+
+/* dJ/df_q = det J(q) (W^(0,0)T lam)_q into device [N_q].  Async on s. */
+int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s);
+
+void wq_destroy(wq_op A);
+
+/* ------------------------------------------------------------------------ *
+ * fd_setup -- Fast Diagonalization preconditioner (Section 4; Lynch, Rice and
+ * Thomas): P = K3 x M2 x M1 + M3 x K2 x M1 + M3 x M2 x K1 with the exact 1D
+ * Galerkin stiffness K_l and mass M_l of the interior B-splines, inverted as
+ * P^{-1} = (U3 x U2 x U1) diag(1/(l1_i + l2_j + l3_k)) (U3 x U2 x U1)^T where
+ * K_l U_l = M_l U_l diag(l_l), U_l^T M_l U_l = I (eigen-setup in FP64 on the
+ * host).  Same knot rules as wq_setup.  prec_mask: WQ_F64 | WQ_F32 | WQ_BF16.
+ * ws == NULL: size query.  Synchronises s.
+ * Errors: WQ_EINVAL, WQ_ESINGULAR, WQ_ENOMEM, WQ_EHIP.
+ * ------------------------------------------------------------------------ */
+int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int prec_mask,
+             void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, fd_pc* out);
+
+/* z = P^{-1} r.  prec WQ_F64: double in/out, FP64 MFMA; WQ_F32: float in/out,
+ * FP32 MFMA; WQ_BF16: float in/out, bf16 MFMA products with FP32
+ * accumulation.  r, z device (may alias).  Async on s. */
+int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s);
+
+/* Eigenvalues lam_l (host out, n_l doubles each, may be NULL) and
+ * eigenvectors U_l (host out, row-major n_l x n_l, may be NULL). */
+int fd_factors(fd_pc P, int l, double* lam, double* U);
+
+void fd_destroy(fd_pc P);
+
+/* ------------------------------------------------------------------------ *
+ * krylov_solve -- right-preconditioned BiCGStab (van der Vorst) in FP64 for
+ * K~ x = b (transpose = 0) or K~^T x = b (transpose = 1), preconditioner
+ * P^{-1} (FP64), as in Section 4.  x holds x0 on entry and the solution on
+ * exit.  Stops when |b - K~ x|_2 / |b|_2 <= rtol (recurrence residual, then
+ * confirmed with the true residual).  ws: device, at least
+ * krylov_ws_bytes(A) bytes.  Synchronises once per iteration (one small
+ * device-to-host copy).  *iters, *relres: host outputs.
+ * Errors: WQ_EINVAL, WQ_ENOMEM, WQ_ENOCONV, WQ_EBREAKDOWN, WQ_ENONFINITE, WQ_EHIP.
+ * ------------------------------------------------------------------------ */
+size_t krylov_ws_bytes(wq_op A);
+int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x,
+                 double rtol, int maxit, void* ws, size_t ws_bytes,
+                 int* iters, double* relres, wq_stream_t s);
+
+/* ------------------------------------------------------------------------ *
+ * ir_solve -- mixed-precision iterative refinement: outer FP64 residual
+ * r = b - K~ x and FP64 update x += d; inner right-preconditioned BiCGStab in
+ * FP32 (FP32 apply, FD in `fd_prec` = WQ_F32 or WQ_BF16) on the scaled residual
+ * to relative tolerance tau_inner.  Stops when the FP64 residual satisfies
+ * |r|_2/|b|_2 <= rtol.  x: FP64 in/out.  ws: device, at least
+ * ir_ws_bytes(A).  *outer, *inner_total, *relres: host outputs.
+ * Errors: as krylov_solve.
+ * ------------------------------------------------------------------------ */
+size_t ir_ws_bytes(wq_op A);
+int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double rtol,
+             double tau_inner, int max_outer, int maxit_inner, void* ws, size_t ws_bytes,
+             int* outer, int* inner_total, double* relres, wq_stream_t s);
+
+/* ------------------------------------------------------------------------ *
+ * Host-only inspection of the set-up (no device work; for checks and tools).
+ * ------------------------------------------------------------------------ */
+
+/* One direction's 1D factors (Section 2.2; points and weights as in wq_setup).
+ * Pass NULL arrays to get the sizes *n, *nq first.  Outputs are dense,
+ * row-major host arrays: xq [nq]; B [2][nq][n] (values, then first derivatives
+ * of the interior B-splines b_1 .. b_{m-2} at the points); W [4][n][nq] (weight
+ * matrices W^{ab} in the order v = 2a + b, a = test and b = trial derivative).
+ * Errors: WQ_EINVAL, WQ_ESINGULAR. */
+int wq_space_1d(int p, int nknots, const double* knots, int32_t* n, int32_t* nq, double* xq, double* B,
+                double* W);
+
+/* FD factors of one direction: lam [n] and U [n][n] (row-major, eigenvector k
+ * in column k) of K U = M U diag(lam), U^T M U = I (the 1D problems behind
+ * fd_setup).  Errors: WQ_EINVAL, WQ_ESINGULAR. */
+int fd_eig_1d(int p, int nknots, const double* knots, double* lam, double* U);
+
+/* Geometry at the quadrature points of wq_setup, on the host: detJ [N_q],
+ * Jinv [9][N_q] (entry (r, c) of J^{-1} in plane 3 r + c) and F [3][N_q].
+ * Errors: WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR. */
+int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                     double* detJ, double* Jinv, double* F);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* wq_last_error(void);
+
+/* Library version string. */
+const char* wq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WQFD_H */

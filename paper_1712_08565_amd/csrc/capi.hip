@@ -1,0 +1,604 @@
+// C ABI of the library (declared in include/wqfd.h): argument checks, host
+// set-up, workspace carving and uploads, and dispatch to the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/wqfd.h"
+#include "device.h"
+#include "host_setup.h"
+#include "krylov.h"
+
+struct wq_op_s {
+    wqfd::WqOp op;
+};
+struct fd_pc_s {
+    wqfd::FdPc pc;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return WQ_EHIP;
+}
+
+#define HIP_TRY(x, where)                        \
+    do {                                         \
+        hipError_t e_ = (x);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+int nthreads() {
+    unsigned h = std::thread::hardware_concurrency();
+    if (h == 0) h = 4;
+    return (int)std::min(16u, h);
+}
+
+// Host staging of banded factors.  Variants share the window start and width.
+struct HostBand {
+    int rows = 0, cols = 0, L = 0;
+    std::vector<int> start;
+    std::vector<std::vector<double>> c;   // per variant [rows][L]
+};
+
+HostBand make_band(const std::vector<const std::vector<double>*>& mats, int rows, int cols, bool transpose) {
+    // element (r, c) of the banded operator: transpose ? M[c][r] : M[r][c]
+    auto at = [&](const std::vector<double>& M, int r, int c) {
+        return transpose ? M[(size_t)c * rows + r] : M[(size_t)r * cols + c];
+    };
+    HostBand hb;
+    hb.rows = rows;
+    hb.cols = cols;
+    std::vector<int> lo(rows, -1), hi(rows, -1);
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) {
+            bool nz = false;
+            for (auto* M : mats) nz |= at(*M, r, c) != 0.0;
+            if (nz) {
+                if (lo[r] < 0) lo[r] = c;
+                hi[r] = c;
+            }
+        }
+    int L = 1;
+    for (int r = 0; r < rows; ++r)
+        if (lo[r] >= 0) L = std::max(L, hi[r] - lo[r] + 1);
+    L = std::min(L, cols);
+    hb.L = L;
+    hb.start.resize(rows);
+    hb.c.assign(mats.size(), std::vector<double>((size_t)rows * L, 0.0));
+    for (int r = 0; r < rows; ++r) {
+        int st = lo[r] < 0 ? 0 : std::min(lo[r], cols - L);
+        hb.start[r] = st;
+        for (size_t v = 0; v < mats.size(); ++v)
+            for (int s = 0; s < L; ++s) hb.c[v][(size_t)r * L + s] = at(*mats[v], r, st + s);
+    }
+    return hb;
+}
+
+// Packs host bands into one byte buffer; records offsets to patch device pointers.
+struct Packer {
+    std::vector<char> buf;
+    size_t add(const void* p, size_t bytes) {
+        size_t off = al256(buf.size());
+        buf.resize(off + al256(bytes));
+        std::memcpy(buf.data() + off, p, bytes);
+        return off;
+    }
+};
+
+template <typename T>
+struct BandOffsets {
+    int rows, cols, L;
+    size_t start;
+    std::vector<size_t> c;
+};
+
+template <typename T>
+BandOffsets<T> pack_band(Packer& pk, const HostBand& hb, size_t start_off) {
+    BandOffsets<T> bo;
+    bo.rows = hb.rows;
+    bo.cols = hb.cols;
+    bo.L = hb.L;
+    bo.start = start_off;
+    for (auto& cv : hb.c) {
+        std::vector<T> tmp(cv.begin(), cv.end());
+        bo.c.push_back(pk.add(tmp.data(), tmp.size() * sizeof(T)));
+    }
+    return bo;
+}
+
+template <typename T>
+void patch(wqfd::Band<T>* dst, const BandOffsets<T>& bo, int v, const char* base) {
+    dst->rows = bo.rows;
+    dst->cols = bo.cols;
+    dst->L = bo.L;
+    dst->start = reinterpret_cast<const int*>(base + bo.start);
+    dst->c = reinterpret_cast<const T*>(base + bo.c[v]);
+}
+
+int check_knots_args(int p, const int32_t nknots[3], const double* const knots[3]) {
+    if (!nknots || !knots) return fail(WQ_EINVAL, "null knot arguments");
+    for (int l = 0; l < 3; ++l)
+        if (!knots[l]) return fail(WQ_EINVAL, "null knot vector");
+    if (p < 2 || p > wqfd::kMaxDegree) return fail(WQ_EINVAL, "degree p outside [2, 10]");
+    return WQ_OK;
+}
+
+uint16_t f32_to_bf16_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;                                                    // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wq_last_error(void) { return g_err.c_str(); }
+const char* wq_version(void) { return "wqfd 0.1 (gfx950)"; }
+
+int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
+             const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s_,
+             wq_op* out) {
+    g_err.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(s_);
+    int rc = check_knots_args(p, nknots, knots);
+    if (rc) return rc;
+    if (!ctrl) return fail(WQ_EINVAL, "null control points");
+    if (k_kind != WQ_K_IDENTITY && k_kind != WQ_K_SCALAR && k_kind != WQ_K_SYM6)
+        return fail(WQ_EINVAL, "unknown k_kind");
+    if (k_kind != WQ_K_IDENTITY && !K_q && ws) return fail(WQ_EINVAL, "K_q is required for this k_kind");
+    if (prec_mask == 0 || (prec_mask & ~(WQ_F64 | WQ_F32))) return fail(WQ_EINVAL, "prec_mask must be WQ_F64 | WQ_F32");
+    if (!ws && !ws_needed) return fail(WQ_EINVAL, "need ws or ws_needed");
+    if (ws && !out) return fail(WQ_EINVAL, "null output handle");
+
+    wqfd::Space1D sp[3];
+    std::string err;
+    for (int l = 0; l < 3; ++l) {
+        rc = wqfd::build_space(p, nknots[l], knots[l], true, sp[l], err);
+        if (rc) return fail(rc, "direction " + std::to_string(l + 1) + ": " + err);
+    }
+    auto op = std::make_unique<wq_op_s>();
+    wqfd::WqOp& o = op->op;
+    o.p = p;
+    o.prec_mask = prec_mask;
+    o.k_kind = k_kind;
+    for (int l = 0; l < 3; ++l) {
+        o.n[l] = sp[l].n;
+        o.nq[l] = sp[l].nq;
+        o.xq[l] = sp[l].xq;
+    }
+    o.N = (size_t)o.n[0] * o.n[1] * o.n[2];
+    o.Nq = (size_t)o.nq[0] * o.nq[1] * o.nq[2];
+
+    // banded factors, both precisions
+    Packer pk;
+    struct DirOff {
+        BandOffsets<double> B, W, BT, WT;
+        BandOffsets<float> B32, W32, BT32, WT32;
+    } doff[3];
+    for (int l = 0; l < 3; ++l) {
+        const auto& S = sp[l];
+        HostBand hB = make_band({&S.B[0], &S.B[1]}, S.nq, S.n, false);
+        HostBand hW = make_band({&S.W[0][0], &S.W[0][1], &S.W[1][0], &S.W[1][1]}, S.n, S.nq, false);
+        HostBand hBT = make_band({&S.B[0], &S.B[1]}, S.n, S.nq, true);
+        HostBand hWT = make_band({&S.W[0][0], &S.W[0][1], &S.W[1][0], &S.W[1][1]}, S.nq, S.n, true);
+        const size_t sB = pk.add(hB.start.data(), hB.start.size() * sizeof(int));
+        const size_t sW = pk.add(hW.start.data(), hW.start.size() * sizeof(int));
+        const size_t sBT = pk.add(hBT.start.data(), hBT.start.size() * sizeof(int));
+        const size_t sWT = pk.add(hWT.start.data(), hWT.start.size() * sizeof(int));
+        doff[l].B = pack_band<double>(pk, hB, sB);
+        doff[l].W = pack_band<double>(pk, hW, sW);
+        doff[l].BT = pack_band<double>(pk, hBT, sBT);
+        doff[l].WT = pack_band<double>(pk, hWT, sWT);
+        doff[l].B32 = pack_band<float>(pk, hB, sB);
+        doff[l].W32 = pack_band<float>(pk, hW, sW);
+        doff[l].BT32 = pack_band<float>(pk, hBT, sBT);
+        doff[l].WT32 = pack_band<float>(pk, hWT, sWT);
+    }
+    // workspace layout
+    size_t off = 0;
+    const size_t o_tab = off;
+    off += al256(pk.buf.size());
+    const size_t o_detj = off;
+    off += al256(o.Nq * 8);
+    const size_t o_jinv = off;
+    off += al256(9 * o.Nq * 8);
+    const size_t o_F = off;
+    off += al256(3 * o.Nq * 8);
+    const size_t o_c64 = off;
+    off += al256(6 * o.Nq * 8);
+    size_t o_c32 = 0;
+    if (prec_mask & WQ_F32) {
+        o_c32 = off;
+        off += al256(6 * o.Nq * 4);
+    }
+    const size_t o_scr = off;
+    o.scratch_bytes = wqfd::wq_scratch_bytes(o, prec_mask);
+    off += al256(o.scratch_bytes);
+    if (ws_needed) *ws_needed = off;
+    if (!ws) return WQ_OK;
+    if (ws_bytes < off) return fail(WQ_ENOMEM, "workspace too small for wq_setup");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(WQ_EINVAL, "workspace must be 256-byte aligned");
+
+    // geometry on the host
+    std::vector<double> hdet(o.Nq), hjinv(9 * o.Nq), hF(3 * o.Nq);
+    rc = wqfd::geometry_at_quad(sp, ctrl, hdet.data(), hjinv.data(), hF.data(), err, nthreads());
+    if (rc) return fail(rc, err);
+
+    char* base = static_cast<char*>(ws);
+    HIP_TRY(hipMemcpyAsync(base + o_tab, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, s), "upload tables");
+    o.detJ = reinterpret_cast<double*>(base + o_detj);
+    o.Jinv = reinterpret_cast<double*>(base + o_jinv);
+    o.F = reinterpret_cast<double*>(base + o_F);
+    o.C64 = reinterpret_cast<double*>(base + o_c64);
+    o.C32 = (prec_mask & WQ_F32) ? reinterpret_cast<float*>(base + o_c32) : nullptr;
+    o.scratch = base + o_scr;
+    HIP_TRY(hipMemcpyAsync(o.detJ, hdet.data(), o.Nq * 8, hipMemcpyHostToDevice, s), "upload detJ");
+    HIP_TRY(hipMemcpyAsync(o.Jinv, hjinv.data(), 9 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload Jinv");
+    HIP_TRY(hipMemcpyAsync(o.F, hF.data(), 3 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload F");
+    const char* tb = base + o_tab;
+    for (int l = 0; l < 3; ++l) {
+        auto& d64 = o.t64.dir[l];
+        auto& d32 = o.t32.dir[l];
+        for (int v = 0; v < 2; ++v) {
+            patch(&d64.B[v], doff[l].B, v, tb);
+            patch(&d64.BT[v], doff[l].BT, v, tb);
+            patch(&d32.B[v], doff[l].B32, v, tb);
+            patch(&d32.BT[v], doff[l].BT32, v, tb);
+        }
+        for (int v = 0; v < 4; ++v) {
+            patch(&d64.W[v], doff[l].W, v, tb);
+            patch(&d64.WT[v], doff[l].WT, v, tb);
+            patch(&d32.W[v], doff[l].W32, v, tb);
+            patch(&d32.WT[v], doff[l].WT32, v, tb);
+        }
+    }
+    HIP_TRY(wqfd::launch_set_coef(o, k_kind, K_q, s), "set_coef");
+    HIP_TRY(hipStreamSynchronize(s), "wq_setup sync");
+    *out = op.release();
+    return WQ_OK;
+}
+
+int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]) {
+    if (!A) return fail(WQ_EINVAL, "null handle");
+    for (int l = 0; l < 3; ++l) {
+        if (n) n[l] = A->op.n[l];
+        if (nq) nq[l] = A->op.nq[l];
+    }
+    return WQ_OK;
+}
+
+int wq_quad_points(wq_op A, double* xq, double* Fq, wq_stream_t s) {
+    if (!A) return fail(WQ_EINVAL, "null handle");
+    if (xq) {
+        size_t o = 0;
+        for (int l = 0; l < 3; ++l) {
+            std::memcpy(xq + o, A->op.xq[l].data(), A->op.xq[l].size() * 8);
+            o += A->op.xq[l].size();
+        }
+    }
+    if (Fq)
+        HIP_TRY(hipMemcpyAsync(Fq, A->op.F, 3 * A->op.Nq * 8, hipMemcpyDeviceToDevice,
+                               reinterpret_cast<hipStream_t>(s)),
+                "copy F");
+    return WQ_OK;
+}
+
+int wq_detj(wq_op A, double* detj, wq_stream_t s) {
+    if (!A || !detj) return fail(WQ_EINVAL, "null argument");
+    HIP_TRY(hipMemcpyAsync(detj, A->op.detJ, A->op.Nq * 8, hipMemcpyDeviceToDevice, reinterpret_cast<hipStream_t>(s)),
+            "copy detJ");
+    return WQ_OK;
+}
+
+int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s) {
+    if (!A) return fail(WQ_EINVAL, "null handle");
+    if (k_kind != WQ_K_IDENTITY && k_kind != WQ_K_SCALAR && k_kind != WQ_K_SYM6)
+        return fail(WQ_EINVAL, "unknown k_kind");
+    if (k_kind != WQ_K_IDENTITY && !K_q) return fail(WQ_EINVAL, "K_q is required for this k_kind");
+    A->op.k_kind = k_kind;
+    HIP_TRY(wqfd::launch_set_coef(A->op, k_kind, K_q, reinterpret_cast<hipStream_t>(s)), "set_coef");
+    return WQ_OK;
+}
+
+static int apply_common(wq_op A, int prec, const void* v, void* w, wq_stream_t s, bool tr) {
+    if (!A || !v || !w) return fail(WQ_EINVAL, "null argument");
+    if ((prec != WQ_F64 && prec != WQ_F32) || !(A->op.prec_mask & prec))
+        return fail(WQ_EINVAL, "precision not prepared for this operator");
+    if (v == w) return fail(WQ_EINVAL, "v and w must not alias");
+    HIP_TRY(wqfd::launch_apply(A->op, prec, v, w, tr, reinterpret_cast<hipStream_t>(s)), tr ? "wq_apply_T" : "wq_apply");
+    return WQ_OK;
+}
+
+int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s) { return apply_common(A, prec, v, w, s, false); }
+int wq_apply_T(wq_op A, int prec, const void* v, void* w, wq_stream_t s) { return apply_common(A, prec, v, w, s, true); }
+
+int wq_rhs(wq_op A, const double* f_q, double* b, wq_stream_t s) {
+    if (!A || !f_q || !b) return fail(WQ_EINVAL, "null argument");
+    HIP_TRY(wqfd::launch_rhs(A->op, f_q, b, reinterpret_cast<hipStream_t>(s)), "wq_rhs");
+    return WQ_OK;
+}
+
+int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream_t s) {
+    if (!A || !lam || !u || !gK) return fail(WQ_EINVAL, "null argument");
+    HIP_TRY(wqfd::launch_grad_K(A->op, lam, u, gK, reinterpret_cast<hipStream_t>(s)), "wq_grad_K");
+    return WQ_OK;
+}
+
+int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s) {
+    if (!A || !lam || !gf) return fail(WQ_EINVAL, "null argument");
+    HIP_TRY(wqfd::launch_grad_f(A->op, lam, gf, reinterpret_cast<hipStream_t>(s)), "wq_grad_f");
+    return WQ_OK;
+}
+
+void wq_destroy(wq_op A) { delete A; }
+
+// ------------------------------------------------------------------------ FD
+int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int prec_mask, void* ws, size_t ws_bytes,
+             size_t* ws_needed, wq_stream_t s_, fd_pc* out) {
+    g_err.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(s_);
+    int rc = check_knots_args(p, nknots, knots);
+    if (rc) return rc;
+    if (prec_mask == 0 || (prec_mask & ~(WQ_F64 | WQ_F32 | WQ_BF16)))
+        return fail(WQ_EINVAL, "prec_mask must combine WQ_F64, WQ_F32, WQ_BF16");
+    if (!ws && !ws_needed) return fail(WQ_EINVAL, "need ws or ws_needed");
+    if (ws && !out) return fail(WQ_EINVAL, "null output handle");
+    wqfd::Space1D sp[3];
+    std::string err;
+    for (int l = 0; l < 3; ++l) {
+        rc = wqfd::build_space(p, nknots[l], knots[l], false, sp[l], err);
+        if (rc) return fail(rc, "direction " + std::to_string(l + 1) + ": " + err);
+    }
+    auto P = std::make_unique<fd_pc_s>();
+    wqfd::FdPc& f = P->pc;
+    f.prec_mask = prec_mask;
+    for (int l = 0; l < 3; ++l) f.n[l] = sp[l].n;
+    f.N = (size_t)f.n[0] * f.n[1] * f.n[2];
+    size_t off = 0, o_u64[3], o_u32[3], o_ubf[3], o_lam[3];
+    for (int l = 0; l < 3; ++l) {
+        const size_t n = f.n[l];
+        const size_t np = (n + 63) / 64 * 64;
+        o_u64[l] = off;
+        off += al256(n * n * 8);
+        o_lam[l] = off;
+        off += al256(n * 8);
+        o_u32[l] = off;
+        if (prec_mask & WQ_F32) off += al256(n * n * 4);
+        o_ubf[l] = off;
+        if (prec_mask & WQ_BF16) off += al256(2 * np * np * 2);
+    }
+    const size_t o_scr = off;
+    off += al256(f.N * 8);
+    if (ws_needed) *ws_needed = off;
+    if (!ws) return WQ_OK;
+    if (ws_bytes < off) return fail(WQ_ENOMEM, "workspace too small for fd_setup");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(WQ_EINVAL, "workspace must be 256-byte aligned");
+    char* base = static_cast<char*>(ws);
+    for (int l = 0; l < 3; ++l) {
+        const int n = f.n[l];
+        rc = wqfd::gen_eig(n, sp[l].Ki, sp[l].Mi, f.hlam[l], f.hU[l], err);
+        if (rc) return fail(rc, err);
+        f.U64[l] = reinterpret_cast<double*>(base + o_u64[l]);
+        f.lam[l] = reinterpret_cast<double*>(base + o_lam[l]);
+        HIP_TRY(hipMemcpy(f.U64[l], f.hU[l].data(), (size_t)n * n * 8, hipMemcpyHostToDevice), "upload U");
+        HIP_TRY(hipMemcpy(f.lam[l], f.hlam[l].data(), (size_t)n * 8, hipMemcpyHostToDevice), "upload lam");
+        if (prec_mask & WQ_F32) {
+            std::vector<float> u32(f.hU[l].begin(), f.hU[l].end());
+            f.U32[l] = reinterpret_cast<float*>(base + o_u32[l]);
+            HIP_TRY(hipMemcpy(f.U32[l], u32.data(), (size_t)n * n * 4, hipMemcpyHostToDevice), "upload U32");
+        }
+        if (prec_mask & WQ_BF16) {
+            const int np = (n + 63) / 64 * 64;
+            std::vector<uint16_t> ub(2 * (size_t)np * np, 0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    ub[(size_t)i * np + j] = f32_to_bf16_bits((float)f.hU[l][(size_t)j * n + i]);          // U^T
+                    ub[(size_t)np * np + (size_t)i * np + j] = f32_to_bf16_bits((float)f.hU[l][(size_t)i * n + j]);  // U
+                }
+            f.Ubf[l] = reinterpret_cast<uint16_t*>(base + o_ubf[l]);
+            HIP_TRY(hipMemcpy(f.Ubf[l], ub.data(), ub.size() * 2, hipMemcpyHostToDevice), "upload Ubf");
+        }
+    }
+    f.scratch = base + o_scr;
+    (void)s;
+    *out = P.release();
+    return WQ_OK;
+}
+
+int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s) {
+    if (!P || !r || !z) return fail(WQ_EINVAL, "null argument");
+    if ((prec != WQ_F64 && prec != WQ_F32 && prec != WQ_BF16) || !(P->pc.prec_mask & prec))
+        return fail(WQ_EINVAL, "precision not prepared for this preconditioner");
+    HIP_TRY(wqfd::launch_fd_apply(P->pc, prec, r, z, reinterpret_cast<hipStream_t>(s)), "fd_apply");
+    return WQ_OK;
+}
+
+int fd_factors(fd_pc P, int l, double* lam, double* U) {
+    if (!P || l < 0 || l > 2) return fail(WQ_EINVAL, "bad argument");
+    const auto& f = P->pc;
+    if (lam) std::memcpy(lam, f.hlam[l].data(), f.hlam[l].size() * 8);
+    if (U) std::memcpy(U, f.hU[l].data(), f.hU[l].size() * 8);
+    return WQ_OK;
+}
+
+void fd_destroy(fd_pc P) { delete P; }
+
+// ------------------------------------------------------------------------ host-only inspection
+int wq_space_1d(int p, int nknots, const double* knots, int32_t* n, int32_t* nq, double* xq, double* B, double* W) {
+    g_err.clear();
+    if (!knots || !n || !nq) return fail(WQ_EINVAL, "null argument");
+    wqfd::Space1D S;
+    std::string err;
+    int rc = wqfd::build_space(p, nknots, knots, B != nullptr || W != nullptr, S, err);
+    if (rc) return fail(rc, err);
+    *n = S.n;
+    *nq = S.nq;
+    if (xq) std::memcpy(xq, S.xq.data(), S.xq.size() * 8);
+    if (B)
+        for (int d = 0; d < 2; ++d) std::memcpy(B + (size_t)d * S.nq * S.n, S.B[d].data(), S.B[d].size() * 8);
+    if (W)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                std::memcpy(W + (size_t)(2 * a + b) * S.n * S.nq, S.W[a][b].data(), S.W[a][b].size() * 8);
+    return WQ_OK;
+}
+
+int fd_eig_1d(int p, int nknots, const double* knots, double* lam, double* U) {
+    g_err.clear();
+    if (!knots) return fail(WQ_EINVAL, "null argument");
+    wqfd::Space1D S;
+    std::string err;
+    int rc = wqfd::build_space(p, nknots, knots, false, S, err);
+    if (rc) return fail(rc, err);
+    std::vector<double> l, u;
+    rc = wqfd::gen_eig(S.n, S.Ki, S.Mi, l, u, err);
+    if (rc) return fail(rc, err);
+    if (lam) std::memcpy(lam, l.data(), l.size() * 8);
+    if (U) std::memcpy(U, u.data(), u.size() * 8);
+    return WQ_OK;
+}
+
+int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, double* detJ,
+                     double* Jinv, double* F) {
+    g_err.clear();
+    int rc = check_knots_args(p, nknots, knots);
+    if (rc) return rc;
+    if (!ctrl || !detJ || !Jinv || !F) return fail(WQ_EINVAL, "null argument");
+    wqfd::Space1D sp[3];
+    std::string err;
+    for (int l = 0; l < 3; ++l) {
+        rc = wqfd::build_space(p, nknots[l], knots[l], false, sp[l], err);
+        if (rc) return fail(rc, err);
+    }
+    rc = wqfd::geometry_at_quad(sp, ctrl, detJ, Jinv, F, err, nthreads());
+    return rc ? fail(rc, err) : WQ_OK;
+}
+
+// ------------------------------------------------------------------------ Krylov
+size_t krylov_ws_bytes(wq_op A) { return A ? wqfd::krylov_bytes(A->op.N, false) : 0; }
+
+int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x, double rtol, int maxit, void* ws,
+                 size_t ws_bytes, int* iters, double* relres, wq_stream_t s_) {
+    g_err.clear();
+    if (!A || !P || !b || !x || !ws || !iters || !relres) return fail(WQ_EINVAL, "null argument");
+    if (!(A->op.prec_mask & WQ_F64) || !(P->pc.prec_mask & WQ_F64)) return fail(WQ_EINVAL, "FP64 not prepared");
+    if (P->pc.N != A->op.N) return fail(WQ_EINVAL, "operator and preconditioner sizes differ");
+    if (!(rtol > 0) || maxit < 1) return fail(WQ_EINVAL, "need rtol > 0 and maxit >= 1");
+    if (ws_bytes < krylov_ws_bytes(A)) return fail(WQ_ENOMEM, "Krylov workspace too small");
+    hipStream_t s = reinterpret_cast<hipStream_t>(s_);
+    const wqfd::WqOp* op = &A->op;
+    const wqfd::FdPc* pc = &P->pc;
+    wqfd::LinOp Aop = [op, transpose](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F64, in, o, transpose != 0, st);
+    };
+    wqfd::LinOp Mop = [pc](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_fd_apply(*pc, WQ_F64, in, o, st);
+    };
+    std::string err;
+    int rc = wqfd::bicgstab<double>(Aop, Mop, op->N, b, x, false, rtol, maxit, ws, iters, relres, err, s);
+    if (rc) return fail(rc, err);
+    return WQ_OK;
+}
+
+size_t ir_ws_bytes(wq_op A) {
+    if (!A) return 0;
+    const size_t N = A->op.N;
+    return al256(N * 8) * 2 + al256(N * 4) * 2 + al256(wqfd::krylov_bytes(N, true)) + al256(wqfd::norm2_ws_bytes());
+}
+
+int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double rtol, double tau_inner, int max_outer,
+             int maxit_inner, void* ws, size_t ws_bytes, int* outer, int* inner_total, double* relres,
+             wq_stream_t s_) {
+    g_err.clear();
+    if (!A || !P || !b || !x || !ws || !outer || !inner_total || !relres) return fail(WQ_EINVAL, "null argument");
+    if (!(A->op.prec_mask & WQ_F64) || !(A->op.prec_mask & WQ_F32))
+        return fail(WQ_EINVAL, "operator needs both WQ_F64 and WQ_F32");
+    if ((fd_prec != WQ_F32 && fd_prec != WQ_BF16) || !(P->pc.prec_mask & fd_prec))
+        return fail(WQ_EINVAL, "fd_prec must be a prepared WQ_F32 or WQ_BF16");
+    if (P->pc.N != A->op.N) return fail(WQ_EINVAL, "operator and preconditioner sizes differ");
+    if (!(rtol > 0) || !(tau_inner > 0) || max_outer < 1 || maxit_inner < 1) return fail(WQ_EINVAL, "bad tolerances");
+    if (ws_bytes < ir_ws_bytes(A)) return fail(WQ_ENOMEM, "IR workspace too small");
+    hipStream_t s = reinterpret_cast<hipStream_t>(s_);
+    const wqfd::WqOp* op = &A->op;
+    const wqfd::FdPc* pc = &P->pc;
+    const size_t N = op->N;
+    char* c = static_cast<char*>(ws);
+    double* r64 = reinterpret_cast<double*>(c);
+    c += al256(N * 8);
+    double* t64 = reinterpret_cast<double*>(c);
+    c += al256(N * 8);
+    float* b32 = reinterpret_cast<float*>(c);
+    c += al256(N * 4);
+    float* d32 = reinterpret_cast<float*>(c);
+    c += al256(N * 4);
+    void* kws = c;
+    c += al256(wqfd::krylov_bytes(N, true));
+    void* nws = c;
+    wqfd::LinOp A32 = [op](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F32, in, o, false, st);
+    };
+    wqfd::LinOp M32 = [pc, fd_prec](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_fd_apply(*pc, fd_prec, in, o, st);
+    };
+    std::string err;
+    double nb = 0, nr = 0;
+    int rc = wqfd::norm2(b, N, nws, &nb, err, s);
+    if (rc) return fail(rc, err);
+    *outer = 0;
+    *inner_total = 0;
+    if (nb == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, N * 8, s), "zero x");
+        *relres = 0;
+        return WQ_OK;
+    }
+    auto residual = [&]() -> int {
+        hipError_t e = wqfd::launch_apply(*op, WQ_F64, x, t64, false, s);
+        if (e != hipSuccess) return hip_fail(e, "ir residual apply");
+        HIP_TRY(hipMemcpyAsync(r64, t64, N * 8, hipMemcpyDeviceToDevice, s), "ir copy");
+        HIP_TRY(wqfd::launch_resid(b, r64, N, s), "ir resid");
+        int r2 = wqfd::norm2(r64, N, nws, &nr, err, s);
+        return r2 ? fail(r2, err) : WQ_OK;
+    };
+    rc = residual();
+    if (rc) return rc;
+    *relres = nr / nb;
+    while (nr / nb > rtol && *outer < max_outer) {
+        if (!std::isfinite(nr)) return fail(WQ_ENONFINITE, "non-finite residual in iterative refinement");
+        HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
+        int it = 0;
+        double rel = 0;
+        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tau_inner, maxit_inner, kws, &it, &rel, err, s);
+        *inner_total += it;
+        if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
+        HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");
+        ++*outer;
+        rc = residual();
+        if (rc) return rc;
+        *relres = nr / nb;
+    }
+    if (nr / nb > rtol) return fail(WQ_ENOCONV, "iterative refinement reached max_outer");
+    return WQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Device-side data of the MF-WQ operator and the FD preconditioner, and the
+// launch wrappers of the HIP kernels (gfx950).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace wqfd {
+
+// Banded 1D operator with `rows` rows over `cols` columns.  Row r has its
+// non-zeros inside columns [start[r], start[r] + L); start is clamped so the
+// window stays inside [0, cols).  Coefficients are stored [rows][L].
+template <typename T>
+struct Band {
+    int rows = 0, cols = 0, L = 0;
+    const int* start = nullptr;
+    const T* c = nullptr;
+};
+
+// All banded 1D factors of one direction, in one precision.
+//   B[d]  : n_q x n   values (d = 0) or derivatives (d = 1) of interior B-splines
+//   W[v]  : n   x n_q weights, v = 2 a + b (a test, b trial derivative order)
+//   BT[d] : n   x n_q transpose of B[d]
+//   WT[v] : n_q x n   transpose of W[v]
+template <typename T>
+struct Dir1D {
+    Band<T> B[2], W[4], BT[2], WT[4];
+};
+
+template <typename T>
+struct OpTables {
+    Dir1D<T> dir[3];
+};
+
+struct WqOp {
+    int p = 0;
+    int n[3] = {0, 0, 0}, nq[3] = {0, 0, 0};
+    size_t N = 0, Nq = 0;
+    int prec_mask = 0;
+    int k_kind = 0;
+    // device arrays (carved from the caller's workspace)
+    double* detJ = nullptr;     // [Nq]
+    double* Jinv = nullptr;     // [9][Nq]
+    double* F = nullptr;        // [3][Nq]
+    double* C64 = nullptr;      // [6][Nq] (C11, C22, C33, C12, C13, C23)
+    float* C32 = nullptr;       // [6][Nq]
+    void* scratch = nullptr;    // apply intermediates (bytes: scratch_bytes)
+    size_t scratch_bytes = 0;
+    OpTables<double> t64;
+    OpTables<float> t32;
+    std::vector<double> xq[3];  // host copy of the quadrature points
+};
+
+struct FdPc {
+    int n[3] = {0, 0, 0};
+    size_t N = 0;
+    int prec_mask = 0;
+    double* U64[3] = {nullptr, nullptr, nullptr};   // row-major n x n (eigenvector k = column k)
+    float* U32[3] = {nullptr, nullptr, nullptr};
+    uint16_t* Ubf[3] = {nullptr, nullptr, nullptr};  // bf16 copies (raw bits)
+    float* Ubf_padded = nullptr;
+    double* lam[3] = {nullptr, nullptr, nullptr};    // eigenvalues (device)
+    std::vector<double> hlam[3], hU[3];
+    void* scratch = nullptr;    // one N-sized buffer of the widest precision
+};
+
+// ---------------------------------------------------------------- launchers
+// MF-WQ operator (wq_kernels.hip)
+size_t wq_scratch_bytes(const WqOp& op, int prec_mask);
+hipError_t launch_set_coef(const WqOp& op, int k_kind, const double* K_q, hipStream_t s);
+hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s);
+hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s);
+hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s);
+hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s);
+
+// FD preconditioner (fd_kernels.hip)
+hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s);
+
+// BLAS-1 helpers for the Krylov drivers (blas1.hip)
+hipError_t launch_cast_f64_to_f32(const double* x, float* y, size_t n, double scale, hipStream_t s);
+hipError_t launch_axpy_f32_to_f64(const float* d, double* x, size_t n, double scale, hipStream_t s);
+
+}  // namespace wqfd

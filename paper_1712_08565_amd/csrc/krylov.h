@@ -1,0 +1,28 @@
+// BiCGStab driver and mixed-precision helpers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <string>
+
+namespace wqfd {
+
+// y = Op(x) enqueued on the stream; element type fixed by the caller.
+using LinOp = std::function<hipError_t(const void*, void*, hipStream_t)>;
+
+// Device workspace bytes of one BiCGStab run on N unknowns.
+size_t krylov_bytes(size_t N, bool fp32);
+
+// Right-preconditioned BiCGStab: A x = b with x = M y.  Returns 0 or a
+// negative wqfd error code (message in err).  Synchronises once per iteration.
+template <typename T>
+int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0_zero, double tol, int maxit,
+             void* ws, int* iters, double* relres, std::string& err, hipStream_t s);
+
+int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s);
+size_t norm2_ws_bytes();
+hipError_t launch_resid(const double* b, double* y, size_t n, hipStream_t s);
+hipError_t launch_fill0_f32(float* x, size_t n, hipStream_t s);
+
+}  // namespace wqfd

@@ -1,0 +1,382 @@
+// Right-preconditioned BiCGStab (van der Vorst 1992), the Krylov solver the
+// paper uses for the non-symmetric weighted-quadrature systems (Section 4), and
+// a mixed-precision iterative-refinement loop around an FP32 inner BiCGStab.
+//
+// All scalars of the recurrence (rho, alpha, omega, ...) live in device memory
+// and are produced by the reduction kernels, so an iteration enqueues its work
+// without waiting for the host; the host reads back one small scalar block per
+// iteration for the convergence and breakdown tests.  Dot products are
+// deterministic two-pass reductions (fixed block partition and order), always
+// accumulated in FP64.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "device.h"
+#include "krylov.h"
+
+namespace wqfd {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kMaxBlocks = 1024;
+
+enum Slot {
+    S_RHO = 0, S_RHO_OLD, S_ALPHA, S_OMEGA, S_RV, S_TS, S_TT, S_RR, S_BB, S_AUX, S_AUX2, kSlots
+};
+
+enum FinalOp { F_STORE = 0, F_ALPHA, F_OMEGA, F_RHO_RR };
+
+inline int nblocks(size_t n) {
+    size_t b = (n + (size_t)kT * 4 - 1) / ((size_t)kT * 4);
+    if (b > kMaxBlocks) b = kMaxBlocks;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+    __syncthreads();
+    return r;
+}
+
+// partial sums of up to three dot products (x_k, y_k)
+template <typename T, int K>
+__global__ __launch_bounds__(kT) void dot_partial(const T* __restrict__ x0, const T* __restrict__ y0,
+                                                  const T* __restrict__ x1, const T* __restrict__ y1,
+                                                  const T* __restrict__ x2, const T* __restrict__ y2, size_t n,
+                                                  double* __restrict__ part) {
+    __shared__ double sh[kT / 64];
+    double a0 = 0, a1 = 0, a2 = 0;
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+        a0 += (double)x0[i] * (double)y0[i];
+        if (K > 1) a1 += (double)x1[i] * (double)y1[i];
+        if (K > 2) a2 += (double)x2[i] * (double)y2[i];
+    }
+    double r = block_sum(a0, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+    if (K > 1) {
+        r = block_sum(a1, sh);
+        if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = r;
+    }
+    if (K > 2) {
+        r = block_sum(a2, sh);
+        if (threadIdx.x == 0) part[2 * gridDim.x + blockIdx.x] = r;
+    }
+}
+
+// single block: sum the partials of K dots and update the scalar block
+template <int K>
+__global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
+                                                int slot0, int op) {
+    __shared__ double sh[kT / 64];
+    double res[3] = {0, 0, 0};
+    for (int k = 0; k < K; ++k) {
+        double a = 0;
+        for (int i = threadIdx.x; i < nb; i += kT) a += part[k * nb + i];
+        res[k] = block_sum(a, sh);
+    }
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case F_STORE:
+            for (int k = 0; k < K; ++k) sc[slot0 + k] = res[k];
+            break;
+        case F_ALPHA:   // res0 = (r^, v)
+            sc[S_RV] = res[0];
+            sc[S_ALPHA] = sc[S_RHO] / res[0];
+            break;
+        case F_OMEGA:   // res0 = (t, s), res1 = (t, t)
+            sc[S_TS] = res[0];
+            sc[S_TT] = res[1];
+            sc[S_OMEGA] = res[1] != 0.0 ? res[0] / res[1] : 0.0;
+            break;
+        case F_RHO_RR:  // res0 = (r^, r), res1 = (r, r)
+            sc[S_RHO_OLD] = sc[S_RHO];
+            sc[S_RHO] = res[0];
+            sc[S_RR] = res[1];
+            break;
+    }
+}
+
+// p = r + beta (p - omega v),  beta = (rho / rho_old) (alpha / omega)
+template <typename T>
+__global__ __launch_bounds__(kT) void upd_p(T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ v,
+                                            const double* __restrict__ sc, size_t n, int first) {
+    const double beta = first ? 0.0 : (sc[S_RHO] / sc[S_RHO_OLD]) * (sc[S_ALPHA] / sc[S_OMEGA]);
+    const double om = sc[S_OMEGA];
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+        p[i] = first ? r[i] : (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
+}
+
+// s = r - alpha v
+template <typename T>
+__global__ __launch_bounds__(kT) void upd_s(T* __restrict__ s, const T* __restrict__ r, const T* __restrict__ v,
+                                            const double* __restrict__ sc, size_t n) {
+    const double al = sc[S_ALPHA];
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+        s[i] = (T)((double)r[i] - al * (double)v[i]);
+}
+
+// x += alpha p^ + omega s^ ; r = s - omega t ; partial (r^, r) and (r, r)
+template <typename T>
+__global__ __launch_bounds__(kT) void upd_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ ph,
+                                             const T* __restrict__ sh_, const T* __restrict__ s,
+                                             const T* __restrict__ t, const T* __restrict__ rh,
+                                             const double* __restrict__ sc, size_t n, double* __restrict__ part) {
+    __shared__ double sh[kT / 64];
+    const double al = sc[S_ALPHA], om = sc[S_OMEGA];
+    double a0 = 0, a1 = 0;
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+        x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)sh_[i]);
+        const T rn = (T)((double)s[i] - om * (double)t[i]);
+        r[i] = rn;
+        a0 += (double)rh[i] * (double)rn;
+        a1 += (double)rn * (double)rn;
+    }
+    double v = block_sum(a0, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    v = block_sum(a1, sh);
+    if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = v;
+}
+
+// y = b - y (true residual) ; copy
+template <typename T>
+__global__ __launch_bounds__(kT) void resid(const T* __restrict__ b, T* __restrict__ y, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) y[i] = b[i] - y[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void copy2(const T* __restrict__ a, T* __restrict__ b, T* __restrict__ c, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
+        b[i] = a[i];
+        if (c) c[i] = a[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kT) void fill0(T* __restrict__ a, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) a[i] = T(0);
+}
+
+__global__ __launch_bounds__(kT) void cast_kernel(const double* __restrict__ x, float* __restrict__ y, size_t n,
+                                                  double scale) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+        y[i] = (float)(x[i] * scale);
+}
+
+__global__ __launch_bounds__(kT) void axpy_kernel(const float* __restrict__ d, double* __restrict__ x, size_t n,
+                                                  double scale) {
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+        x[i] += scale * (double)d[i];
+}
+
+// thread-local pinned host block for the per-iteration scalar read-back
+double* host_scalars() {
+    static thread_local double* h = nullptr;
+    if (!h) {
+        if (hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) h = nullptr;
+    }
+    return h;
+}
+
+#define KR_TRY(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) {                     \
+            err = hipGetErrorString(e_);            \
+            return WQ_EHIP_CODE;                    \
+        }                                           \
+    } while (0)
+
+constexpr int WQ_EHIP_CODE = -5;
+
+template <typename T>
+struct Vecs {
+    T *r, *rh, *p, *v, *s, *t, *ph, *sh;
+    double *sc, *part;
+};
+
+template <typename T>
+size_t vec_bytes(size_t N) {
+    const size_t v = (N * sizeof(T) + 255) / 256 * 256;
+    return 8 * v + 256 + (size_t)3 * kMaxBlocks * sizeof(double) + 256;
+}
+
+template <typename T>
+Vecs<T> carve(void* ws, size_t N) {
+    Vecs<T> V;
+    char* c = static_cast<char*>(ws);
+    const size_t v = (N * sizeof(T) + 255) / 256 * 256;
+    T** ptrs[8] = {&V.r, &V.rh, &V.p, &V.v, &V.s, &V.t, &V.ph, &V.sh};
+    for (int k = 0; k < 8; ++k) {
+        *ptrs[k] = reinterpret_cast<T*>(c);
+        c += v;
+    }
+    V.sc = reinterpret_cast<double*>(c);
+    c += 256;
+    V.part = reinterpret_cast<double*>(c);
+    return V;
+}
+
+}  // namespace
+
+size_t krylov_bytes(size_t N, bool fp32) { return fp32 ? vec_bytes<float>(N) : vec_bytes<double>(N); }
+
+hipError_t launch_cast_f64_to_f32(const double* x, float* y, size_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL(cast_kernel, dim3(nblocks(n)), dim3(kT), 0, s, x, y, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32_to_f64(const float* d, double* x, size_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(nblocks(n)), dim3(kT), 0, s, d, x, n, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0_zero, double tol, int maxit,
+             void* ws, int* iters, double* relres, std::string& err, hipStream_t s) {
+    Vecs<T> V = carve<T>(ws, N);
+    const int nb = nblocks(N);
+    const dim3 g(nb), blk(kT);
+    double* h = host_scalars();
+    if (!h) {
+        err = "could not allocate pinned host memory";
+        return WQ_EHIP_CODE;
+    }
+    *iters = 0;
+    *relres = 0.0;
+    // r = b - A x0 ; r^ = r ; scalars
+    if (x0_zero) {
+        hipLaunchKernelGGL(fill0<T>, g, blk, 0, s, x, N);
+        hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, b, V.r, V.rh, N);
+    } else {
+        KR_TRY(A(x, V.t, s));
+        hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.t, V.r, (T*)nullptr, N);
+        hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.r, N);
+        hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.r, V.rh, (T*)nullptr, N);
+    }
+    hipLaunchKernelGGL((dot_partial<T, 3>), g, blk, 0, s, V.rh, V.r, V.r, V.r, b, b, N, V.part);
+    hipLaunchKernelGGL((dot_final<3>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_RHO, (int)F_STORE);
+    // S_RHO = (r^, r), S_RHO_OLD = (r, r) (overwritten below), S_ALPHA = (b, b): fix up on the host
+    KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+    KR_TRY(hipStreamSynchronize(s));
+    const double bb = h[S_ALPHA], rr0 = h[S_RHO_OLD], rho0 = h[S_RHO];
+    if (!std::isfinite(bb) || !std::isfinite(rr0)) {
+        err = "non-finite value in the right-hand side or initial residual";
+        return -8;
+    }
+    if (bb == 0.0) {
+        hipLaunchKernelGGL(fill0<T>, g, blk, 0, s, x, N);
+        return 0;
+    }
+    const double nbn = std::sqrt(bb);
+    {
+        double init[kSlots] = {0};
+        init[S_RHO] = rho0;
+        init[S_RHO_OLD] = 1.0;
+        init[S_ALPHA] = 1.0;
+        init[S_OMEGA] = 1.0;
+        init[S_RR] = rr0;
+        init[S_BB] = bb;
+        std::memcpy(h, init, sizeof init);
+        KR_TRY(hipMemcpyAsync(V.sc, h, kSlots * sizeof(double), hipMemcpyHostToDevice, s));
+        KR_TRY(hipStreamSynchronize(s));
+    }
+    if (std::sqrt(rr0) / nbn <= tol) {
+        *relres = std::sqrt(rr0) / nbn;
+        return 0;
+    }
+    for (int it = 1; it <= maxit; ++it) {
+        hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, it == 1 ? 1 : 0);
+        KR_TRY(M(V.p, V.ph, s));
+        KR_TRY(A(V.ph, V.v, s));
+        hipLaunchKernelGGL((dot_partial<T, 1>), g, blk, 0, s, V.rh, V.v, (const T*)nullptr, (const T*)nullptr,
+                           (const T*)nullptr, (const T*)nullptr, N, V.part);
+        hipLaunchKernelGGL((dot_final<1>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_ALPHA);
+        hipLaunchKernelGGL(upd_s<T>, g, blk, 0, s, V.s, V.r, V.v, V.sc, N);
+        KR_TRY(M(V.s, V.sh, s));
+        KR_TRY(A(V.sh, V.t, s));
+        hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.s, V.t, V.t, (const T*)nullptr,
+                           (const T*)nullptr, N, V.part);
+        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_OMEGA);
+        hipLaunchKernelGGL(upd_xr<T>, g, blk, 0, s, x, V.r, V.ph, V.sh, V.s, V.t, V.rh, V.sc, N, V.part);
+        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_RHO_RR);
+        KR_TRY(hipGetLastError());
+        KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+        KR_TRY(hipStreamSynchronize(s));
+        *iters = it;
+        const double rel = std::sqrt(h[S_RR]) / nbn;
+        *relres = rel;
+        if (!std::isfinite(rel) || !std::isfinite(h[S_ALPHA]) || !std::isfinite(h[S_OMEGA])) {
+            err = "non-finite value in the BiCGStab recurrence";
+            return -8;
+        }
+        if (rel <= tol) {
+            // confirm with the true residual r = b - A x
+            KR_TRY(A(x, V.t, s));
+            hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.t, N);
+            hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.t, V.rh, V.t, (const T*)nullptr,
+                               (const T*)nullptr, N, V.part);
+            hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_AUX, (int)F_STORE);
+            KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+            KR_TRY(hipStreamSynchronize(s));
+            const double tr = std::sqrt(h[S_AUX]) / nbn;
+            *relres = tr;
+            if (tr <= tol) return 0;
+            // continue from the true residual: r = r_true, rho = (r^, r_true)
+            hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.t, V.r, (T*)nullptr, N);
+            h[0] = h[S_AUX2];
+            KR_TRY(hipMemcpyAsync(V.sc + S_RHO, &h[0], sizeof(double), hipMemcpyHostToDevice, s));
+            KR_TRY(hipStreamSynchronize(s));
+            continue;
+        }
+        if (h[S_RHO] == 0.0 || h[S_OMEGA] == 0.0 || h[S_RV] == 0.0) {
+            err = "BiCGStab breakdown (rho, (r^, v) or omega vanished)";
+            return -7;
+        }
+    }
+    err = "BiCGStab reached the iteration limit";
+    return -6;
+}
+
+template int bicgstab<double>(const LinOp&, const LinOp&, size_t, const double*, double*, bool, double, int,
+                              void*, int*, double*, std::string&, hipStream_t);
+template int bicgstab<float>(const LinOp&, const LinOp&, size_t, const float*, float*, bool, double, int, void*,
+                             int*, double*, std::string&, hipStream_t);
+
+// FP64 norm of a vector (two-pass), synchronising.
+int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s) {
+    double* part = reinterpret_cast<double*>(part_ws);
+    double* sc = part + 3 * kMaxBlocks;
+    const int nb = nblocks(N);
+    hipLaunchKernelGGL((dot_partial<double, 1>), dim3(nb), dim3(kT), 0, s, x, x, (const double*)nullptr,
+                       (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, N, part);
+    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE);
+    double* h = host_scalars();
+    KR_TRY(hipMemcpyAsync(h, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    KR_TRY(hipStreamSynchronize(s));
+    *out = std::sqrt(h[0]);
+    return 0;
+}
+
+size_t norm2_ws_bytes() { return (3 * kMaxBlocks + 64) * sizeof(double); }
+
+hipError_t launch_resid(const double* b, double* y, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(resid<double>, dim3(nblocks(n)), dim3(kT), 0, s, b, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill0_f32(float* x, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(fill0<float>, dim3(nblocks(n)), dim3(kT), 0, s, x, n);
+    return hipGetLastError();
+}
+
+}  // namespace wqfd

@@ -1,0 +1,404 @@
+// MF-WQ stiffness operator on gfx950: Algorithm 2 of Section 3.2,
+//     K~ v = sum_{a,b} W^(a,b) D^(a,b) B^(b) v,
+// evaluated by sum factorisation (eq. sum-factorization): banded 1D
+// contractions along z, y and x with the basis matrices B_l / B-dot_l, a
+// pointwise product with the coefficient planes C_ab(x_q), then banded
+// contractions with the weight matrices W_l^{ab}.  Also the transpose, the
+// coefficient set-up C = det J J^{-1} K J^{-T} (eq. C), the load vector and the
+// adjoint gradients with respect to K and f.
+//
+// This file holds the staged form: one launch per 1D contraction, with
+// intermediates in device memory.  Each launch streams its input once with
+// coalesced accesses along x.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace wqfd {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// ab index pairs: direction l gets a_l = [l == alpha], b_l = [l == beta];
+// weight variant v = 2 a + b; coefficient plane of the symmetric pair.
+__host__ __device__ inline int plane_of(int a, int b) {
+    if (a == b) return a;
+    const int lo = a < b ? a : b, hi = a < b ? b : a;
+    return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
+}
+
+enum { kPlain = 0, kMulIn = 1, kMulOut = 2 };
+
+// out[...] (+)= sum_s coef[r][s] * in[... start[r] + s ...] along AXIS
+// (0 = x, 1 = y, 2 = z); input dims (d0, d1, d2) with x fastest; output has R
+// entries along AXIS.  kMulIn multiplies each input by mul (same layout as in),
+// kMulOut multiplies the sum by mul (same layout as out).
+template <typename T, int AXIS, int MODE>
+__global__ __launch_bounds__(kThreads) void band_axis_kernel(
+    const T* __restrict__ in, const T* __restrict__ mul, T* __restrict__ out, int d0, int d1, int d2,
+    int R, const int* __restrict__ start, const T* __restrict__ coef, int L, int accumulate) {
+    const int o0 = AXIS == 0 ? R : d0;
+    const int o1 = AXIS == 1 ? R : d1;
+    const int o2 = AXIS == 2 ? R : d2;
+    const size_t total = (size_t)o0 * o1 * o2;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(idx % o0);
+        const size_t t = idx / o0;
+        const int y = (int)(t % o1);
+        const int z = (int)(t / o1);
+        const int r = AXIS == 0 ? x : (AXIS == 1 ? y : z);
+        const int st = start[r];
+        const T* cf = coef + (size_t)r * L;
+        size_t base, stride;
+        if (AXIS == 0) {
+            base = ((size_t)z * d1 + y) * d0 + st;
+            stride = 1;
+        } else if (AXIS == 1) {
+            base = ((size_t)z * d1 + st) * d0 + x;
+            stride = (size_t)d0;
+        } else {
+            base = ((size_t)st * d1 + y) * d0 + x;
+            stride = (size_t)d0 * d1;
+        }
+        T sum = 0;
+        for (int s = 0; s < L; ++s) {
+            T val = in[base + s * stride];
+            if (MODE == kMulIn) val *= mul[base + s * stride];
+            sum += cf[s] * val;
+        }
+        if (MODE == kMulOut) sum *= mul[idx];
+        out[idx] = accumulate ? out[idx] + sum : sum;
+    }
+}
+
+inline int grid_for(size_t total) {
+    size_t g = (total + kThreads - 1) / kThreads;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+template <typename T, int MODE = kPlain>
+hipError_t band(int axis, const Band<T>& b, const T* in, const T* mul, T* out, int d0, int d1, int d2,
+                bool acc, hipStream_t s) {
+    const int dims[3] = {d0, d1, d2};
+    size_t total = (size_t)b.rows;
+    for (int a = 0; a < 3; ++a)
+        if (a != axis) total *= dims[a];
+    const int g = grid_for(total);
+    switch (axis) {
+        case 0:
+            hipLaunchKernelGGL((band_axis_kernel<T, 0, MODE>), dim3(g), dim3(kThreads), 0, s, in, mul, out, d0, d1,
+                               d2, b.rows, b.start, b.c, b.L, (int)acc);
+            break;
+        case 1:
+            hipLaunchKernelGGL((band_axis_kernel<T, 1, MODE>), dim3(g), dim3(kThreads), 0, s, in, mul, out, d0, d1,
+                               d2, b.rows, b.start, b.c, b.L, (int)acc);
+            break;
+        default:
+            hipLaunchKernelGGL((band_axis_kernel<T, 2, MODE>), dim3(g), dim3(kThreads), 0, s, in, mul, out, d0, d1,
+                               d2, b.rows, b.start, b.c, b.L, (int)acc);
+            break;
+    }
+    return hipGetLastError();
+}
+
+#define WQ_TRY(...)                            \
+    do {                                       \
+        hipError_t e_ = (__VA_ARGS__);         \
+        if (e_ != hipSuccess) return e_;       \
+    } while (0)
+
+// Scratch layout shared by the staged forward and transposed applies.
+template <typename T>
+struct Staged {
+    T *g[3], *A, *Bq, *Z[4], *X;
+    Staged(const WqOp& op, void* base) {
+        const size_t n1 = op.n[0], n2 = op.n[1], nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+        T* p = reinterpret_cast<T*>(base);
+        for (int k = 0; k < 3; ++k) {
+            g[k] = p;
+            p += op.Nq;
+        }
+        A = p;                    // nq3 nq2 n1
+        p += nq3 * nq2 * n1;
+        Bq = p;                   // nq3 nq2 n1
+        p += nq3 * nq2 * n1;
+        X = p;                    // nq3 nq2 nq1
+        p += nq3 * nq2 * nq1;
+        for (int k = 0; k < 4; ++k) {
+            Z[k] = p;             // nq3 n2 n1 (z-quadrature, xy-DOF)
+            p += nq3 * n2 * n1;
+        }
+    }
+    static size_t elems(const WqOp& op) {
+        const size_t n1 = op.n[0], n2 = op.n[1], nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+        return 3 * op.Nq + 2 * nq3 * nq2 * n1 + nq3 * nq2 * nq1 + 4 * nq3 * n2 * n1;
+    }
+};
+
+// v~^(beta) = B^(beta) v for beta = x, y, z (first step of Algorithm 2).
+template <typename T>
+hipError_t trial_gradient(const WqOp& op, const OpTables<T>& tb, const T* v, Staged<T>& st, hipStream_t s) {
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq2 = op.nq[1], nq3 = op.nq[2];
+    const Dir1D<T>&dx = tb.dir[0], &dy = tb.dir[1], &dz = tb.dir[2];
+    T* Tz0 = st.Z[0];   // [nq3][n2][n1]  B3 v
+    T* Tz1 = st.Z[1];   // [nq3][n2][n1]  B-dot3 v
+    WQ_TRY(band<T>(2, dz.B[0], v, nullptr, Tz0, n1, n2, n3, false, s));
+    WQ_TRY(band<T>(2, dz.B[1], v, nullptr, Tz1, n1, n2, n3, false, s));
+    // beta = x: B3 B2 Bdot1
+    WQ_TRY(band<T>(1, dy.B[0], Tz0, nullptr, st.A, n1, n2, nq3, false, s));
+    WQ_TRY(band<T>(0, dx.B[1], st.A, nullptr, st.g[0], n1, nq2, nq3, false, s));
+    // beta = y: B3 Bdot2 B1
+    WQ_TRY(band<T>(1, dy.B[1], Tz0, nullptr, st.Bq, n1, n2, nq3, false, s));
+    WQ_TRY(band<T>(0, dx.B[0], st.Bq, nullptr, st.g[1], n1, nq2, nq3, false, s));
+    // beta = z: Bdot3 B2 B1
+    WQ_TRY(band<T>(1, dy.B[0], Tz1, nullptr, st.A, n1, n2, nq3, false, s));
+    WQ_TRY(band<T>(0, dx.B[0], st.A, nullptr, st.g[2], n1, nq2, nq3, false, s));
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t apply_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* v, T* w, hipStream_t s) {
+    Staged<T> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1];
+    const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+    WQ_TRY(trial_gradient(op, tb, v, st, s));
+    bool zset[4] = {false, false, false, false};
+    for (int be = 0; be < 3; ++be)
+        for (int al = 0; al < 3; ++al) {
+            int var[3];
+            for (int l = 0; l < 3; ++l) var[l] = 2 * (l == al) + (l == be);
+            const T* Cp = C + (size_t)plane_of(al, be) * op.Nq;
+            // x: W1 (C .* v~)  -> [nq3][nq2][n1]
+            WQ_TRY(band<T, kMulIn>(0, tb.dir[0].W[var[0]], st.g[be], Cp, st.A, nq1, nq2, nq3, false, s));
+            // y: W2           -> [nq3][n2][n1], grouped by the z weight variant
+            const int grp = var[2];
+            WQ_TRY(band<T>(1, tb.dir[1].W[var[1]], st.A, nullptr, st.Z[grp], n1, nq2, nq3, zset[grp], s));
+            zset[grp] = true;
+        }
+    for (int grp = 0; grp < 4; ++grp)
+        WQ_TRY(band<T>(2, tb.dir[2].W[grp], st.Z[grp], nullptr, w, n1, n2, nq3, grp > 0, s));
+    return hipSuccess;
+}
+
+template <typename T>
+hipError_t apply_T_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* v, T* w, hipStream_t s) {
+    Staged<T> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+    const Dir1D<T>&dx = tb.dir[0], &dy = tb.dir[1], &dz = tb.dir[2];
+    // z: W3^T v for the four variants -> [nq3][n2][n1]
+    for (int grp = 0; grp < 4; ++grp) WQ_TRY(band<T>(2, dz.WT[grp], v, nullptr, st.Z[grp], n1, n2, n3, false, s));
+    // psi_beta = sum_alpha C_ab (W^(ab)^T v)
+    for (int be = 0; be < 3; ++be)
+        for (int al = 0; al < 3; ++al) {
+            int var[3];
+            for (int l = 0; l < 3; ++l) var[l] = 2 * (l == al) + (l == be);
+            const T* Cp = C + (size_t)plane_of(al, be) * op.Nq;
+            WQ_TRY(band<T>(1, dy.WT[var[1]], st.Z[var[2]], nullptr, st.A, n1, n2, nq3, false, s));
+            WQ_TRY(band<T, kMulOut>(0, dx.WT[var[0]], st.A, Cp, st.g[be], n1, nq2, nq3, al > 0, s));
+        }
+    // w = sum_beta B^(beta)^T psi_beta
+    for (int be = 0; be < 3; ++be) {
+        const int d1 = be == 0, d2 = be == 1, d3 = be == 2;
+        WQ_TRY(band<T>(0, dx.BT[d1], st.g[be], nullptr, st.A, nq1, nq2, nq3, false, s));     // [nq3][nq2][n1]
+        WQ_TRY(band<T>(1, dy.BT[d2], st.A, nullptr, st.X, n1, nq2, nq3, false, s));          // [nq3][n2][n1]
+        WQ_TRY(band<T>(2, dz.BT[d3], st.X, nullptr, w, n1, n2, nq3, be > 0, s));              // [n3][n2][n1]
+    }
+    return hipSuccess;
+}
+
+// C = det J J^{-1} K J^{-T} per quadrature point (eq. C); writes FP64 planes
+// and, when c32 != nullptr, an FP32 copy.
+__global__ __launch_bounds__(kThreads) void set_coef_kernel(const double* __restrict__ detJ,
+                                                            const double* __restrict__ Jinv, int k_kind,
+                                                            const double* __restrict__ Kq,
+                                                            double* __restrict__ c64, float* __restrict__ c32,
+                                                            size_t Nq) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < Nq; q += (size_t)gridDim.x * blockDim.x) {
+        double Ji[3][3], K[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Ji[r][c] = Jinv[(size_t)(3 * r + c) * Nq + q];
+        if (k_kind == 0) {
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) K[r][c] = r == c ? 1.0 : 0.0;
+        } else if (k_kind == 1) {
+            const double k = Kq[q];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) K[r][c] = r == c ? k : 0.0;
+        } else {
+            K[0][0] = Kq[q];
+            K[1][1] = Kq[Nq + q];
+            K[2][2] = Kq[2 * Nq + q];
+            K[0][1] = K[1][0] = Kq[3 * Nq + q];
+            K[0][2] = K[2][0] = Kq[4 * Nq + q];
+            K[1][2] = K[2][1] = Kq[5 * Nq + q];
+        }
+        // M = Ji K ; C = det M Ji^T
+        double M[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[r][c] = Ji[r][0] * K[0][c] + Ji[r][1] * K[1][c] + Ji[r][2] * K[2][c];
+        const double d = detJ[q];
+        const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+        for (int k = 0; k < 6; ++k) {
+            const int a = pr[k][0], b = pr[k][1];
+            const double v = d * (M[a][0] * Ji[b][0] + M[a][1] * Ji[b][1] + M[a][2] * Ji[b][2]);
+            c64[(size_t)k * Nq + q] = v;
+            if (c32) c32[(size_t)k * Nq + q] = (float)v;
+        }
+    }
+}
+
+// Gradient of J with respect to C_ab at each point, chained to K:
+//   gC_ab = -(W^(ab)^T lam)_q (B^(b) u)_q ;  scalar: sum_ab gC_ab G_ab, G = det Ji Ji^T;
+//   sym6: H = det Ji^T gC Ji, diagonal H_aa, off-diagonal H_ab + H_ba;
+//   identity kind: the six stored C planes (g_ab + g_ba off the diagonal).
+__global__ __launch_bounds__(kThreads) void grad_K_kernel(const double* __restrict__ wtl,  // [9][Nq] (al*3+be)
+                                                          const double* __restrict__ gu,   // [3][Nq]
+                                                          const double* __restrict__ detJ,
+                                                          const double* __restrict__ Jinv, int k_kind,
+                                                          double* __restrict__ out, size_t Nq) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < Nq; q += (size_t)gridDim.x * blockDim.x) {
+        double g[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) g[a][b] = -wtl[(size_t)(3 * a + b) * Nq + q] * gu[(size_t)b * Nq + q];
+        if (k_kind == 0) {
+            out[q] = g[0][0];
+            out[Nq + q] = g[1][1];
+            out[2 * Nq + q] = g[2][2];
+            out[3 * Nq + q] = g[0][1] + g[1][0];
+            out[4 * Nq + q] = g[0][2] + g[2][0];
+            out[5 * Nq + q] = g[1][2] + g[2][1];
+            continue;
+        }
+        double Ji[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) Ji[r][c] = Jinv[(size_t)(3 * r + c) * Nq + q];
+        const double d = detJ[q];
+        if (k_kind == 1) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double G = Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2];
+                    acc += g[a][b] * G;
+                }
+            out[q] = d * acc;
+        } else {
+            double T[3][3], H[3][3];   // T = g Ji ; H = Ji^T T
+            for (int a = 0; a < 3; ++a)
+                for (int c = 0; c < 3; ++c) T[a][c] = g[a][0] * Ji[0][c] + g[a][1] * Ji[1][c] + g[a][2] * Ji[2][c];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) H[r][c] = d * (Ji[0][r] * T[0][c] + Ji[1][r] * T[1][c] + Ji[2][r] * T[2][c]);
+            out[q] = H[0][0];
+            out[Nq + q] = H[1][1];
+            out[2 * Nq + q] = H[2][2];
+            out[3 * Nq + q] = H[0][1] + H[1][0];
+            out[4 * Nq + q] = H[0][2] + H[2][0];
+            out[5 * Nq + q] = H[1][2] + H[2][1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void mul_kernel(const double* __restrict__ a, double* __restrict__ b,
+                                                       size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] *= a[i];
+}
+
+}  // namespace
+
+size_t wq_scratch_bytes(const WqOp& op, int prec_mask) {
+    // staged apply in the widest precision, or the gradient fields (12 N_q FP64)
+    size_t e = Staged<double>::elems(op);
+    size_t grad = 12 * op.Nq + 2 * (size_t)op.nq[2] * op.nq[1] * op.n[0] + 4 * (size_t)op.nq[2] * op.n[1] * op.n[0];
+    if (grad > e) e = grad;
+    (void)prec_mask;
+    return e * sizeof(double);
+}
+
+hipError_t launch_set_coef(const WqOp& op, int k_kind, const double* K_q, hipStream_t s) {
+    hipLaunchKernelGGL(set_coef_kernel, dim3(grid_for(op.Nq)), dim3(kThreads), 0, s, op.detJ, op.Jinv, k_kind, K_q,
+                       op.C64, (op.prec_mask & 2) ? op.C32 : nullptr, op.Nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s) {
+    if (prec == 1) {
+        const double* vv = static_cast<const double*>(v);
+        double* ww = static_cast<double*>(w);
+        return transpose ? apply_T_staged<double>(op, op.t64, op.C64, vv, ww, s)
+                         : apply_staged<double>(op, op.t64, op.C64, vv, ww, s);
+    }
+    const float* vv = static_cast<const float*>(v);
+    float* ww = static_cast<float*>(w);
+    return transpose ? apply_T_staged<float>(op, op.t32, op.C32, vv, ww, s)
+                     : apply_staged<float>(op, op.t32, op.C32, vv, ww, s);
+}
+
+hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s) {
+    Staged<double> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1];
+    const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+    const OpTables<double>& tb = op.t64;
+    WQ_TRY(band<double, kMulIn>(0, tb.dir[0].W[0], f_q, op.detJ, st.A, nq1, nq2, nq3, false, s));
+    WQ_TRY(band<double>(1, tb.dir[1].W[0], st.A, nullptr, st.Z[0], n1, nq2, nq3, false, s));
+    WQ_TRY(band<double>(2, tb.dir[2].W[0], st.Z[0], nullptr, b, n1, n2, nq3, false, s));
+    return hipSuccess;
+}
+
+hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s) {
+    Staged<double> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+    const OpTables<double>& tb = op.t64;
+    WQ_TRY(band<double>(2, tb.dir[2].WT[0], lam, nullptr, st.Z[0], n1, n2, n3, false, s));
+    WQ_TRY(band<double>(1, tb.dir[1].WT[0], st.Z[0], nullptr, st.A, n1, n2, nq3, false, s));
+    WQ_TRY(band<double, kMulOut>(0, tb.dir[0].WT[0], st.A, op.detJ, gf, n1, nq2, nq3, false, s));
+    (void)nq1;
+    return hipSuccess;
+}
+
+hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s) {
+    // fields: wtl [9][Nq] = W^(ab)^T lam, gu [3][Nq] = B^(b) u
+    double* base = reinterpret_cast<double*>(op.scratch);
+    double* wtl = base;
+    double* gu = base + 9 * op.Nq;
+    double* tmpA = base + 12 * op.Nq;                                        // nq3 nq2 n1
+    double* tmpZ = tmpA + 2 * (size_t)op.nq[2] * op.nq[1] * op.n[0];         // 4 x nq3 n2 n1
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq2 = op.nq[1], nq3 = op.nq[2];
+    const size_t zsz = (size_t)op.nq[2] * op.n[1] * op.n[0];
+    const OpTables<double>& tb = op.t64;
+    const Dir1D<double>&dx = tb.dir[0], &dy = tb.dir[1], &dz = tb.dir[2];
+    // B^(b) u  (same chain as the trial step of the apply)
+    double* Tz0 = tmpZ;
+    double* Tz1 = tmpZ + zsz;
+    WQ_TRY(band<double>(2, dz.B[0], u, nullptr, Tz0, n1, n2, n3, false, s));
+    WQ_TRY(band<double>(2, dz.B[1], u, nullptr, Tz1, n1, n2, n3, false, s));
+    WQ_TRY(band<double>(1, dy.B[0], Tz0, nullptr, tmpA, n1, n2, nq3, false, s));
+    WQ_TRY(band<double>(0, dx.B[1], tmpA, nullptr, gu, n1, nq2, nq3, false, s));
+    WQ_TRY(band<double>(1, dy.B[1], Tz0, nullptr, tmpA, n1, n2, nq3, false, s));
+    WQ_TRY(band<double>(0, dx.B[0], tmpA, nullptr, gu + op.Nq, n1, nq2, nq3, false, s));
+    WQ_TRY(band<double>(1, dy.B[0], Tz1, nullptr, tmpA, n1, n2, nq3, false, s));
+    WQ_TRY(band<double>(0, dx.B[0], tmpA, nullptr, gu + 2 * op.Nq, n1, nq2, nq3, false, s));
+    // W^(ab)^T lam for the nine pairs
+    for (int grp = 0; grp < 4; ++grp)
+        WQ_TRY(band<double>(2, dz.WT[grp], lam, nullptr, tmpZ + grp * zsz, n1, n2, n3, false, s));
+    for (int al = 0; al < 3; ++al)
+        for (int be = 0; be < 3; ++be) {
+            int var[3];
+            for (int l = 0; l < 3; ++l) var[l] = 2 * (l == al) + (l == be);
+            WQ_TRY(band<double>(1, dy.WT[var[1]], tmpZ + var[2] * zsz, nullptr, tmpA, n1, n2, nq3, false, s));
+            WQ_TRY(band<double>(0, dx.WT[var[0]], tmpA, nullptr, wtl + (size_t)(3 * al + be) * op.Nq, n1, nq2, nq3,
+                                false, s));
+        }
+    hipLaunchKernelGGL(grad_K_kernel, dim3(grid_for(op.Nq)), dim3(kThreads), 0, s, wtl, gu, op.detJ, op.Jinv,
+                       op.k_kind, gK, op.Nq);
+    return hipGetLastError();
+}
+
+}  // namespace wqfd

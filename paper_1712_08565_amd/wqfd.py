@@ -1,0 +1,230 @@
+"""Thin torch binding of the C ABI (include/wqfd.h): same names as the C entry
+points, argument marshalling only.  Device memory (vectors, fields and the
+library workspaces) is owned by torch tensors; work is enqueued on the current
+torch stream (a HIP stream on ROCm).  Every computation runs in libwqfd.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_K_IDENTITY, WQ_K_SCALAR, WQ_K_SYM6, WQError, check, lib)
+
+__all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
+           "wq_apply_T", "wq_rhs", "wq_grad_K", "wq_grad_f", "fd_setup", "fd_apply", "fd_factors",
+           "krylov_solve", "ir_solve", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
+           "WQ_K_SYM6", "WQError"]
+
+_DT = {WQ_F64: torch.float64, WQ_F32: torch.float32, WQ_BF16: torch.float32}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _knots(knots: Sequence[np.ndarray]):
+    ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
+    nk = (C.c_int32 * 3)(*[len(k) for k in ks])
+    kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
+    return ks, nk, kp
+
+
+def _need(t: torch.Tensor, dtype, numel: int, name: str):
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name}: need a contiguous {dtype} device tensor with {numel} entries")
+
+
+class WqOp:
+    """MF-WQ stiffness operator handle; owns its device workspace tensor."""
+
+    def __init__(self, handle, ws, p, prec_mask, k_kind, device):
+        self.handle, self.ws, self.p, self.prec_mask, self.k_kind, self.device = \
+            handle, ws, p, prec_mask, k_kind, device
+        self._destroy = lib().wq_destroy
+        n = (C.c_int32 * 3)()
+        nq = (C.c_int32 * 3)()
+        check(lib().wq_dims(handle, n, nq), "wq_dims")
+        self.n, self.nq = tuple(n), tuple(nq)
+        self.N = int(np.prod(self.n))
+        self.Nq = int(np.prod(self.nq))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._destroy(h)
+            self.handle = None
+
+
+class FdPc:
+    """Fast Diagonalization preconditioner handle; owns its workspace tensor."""
+
+    def __init__(self, handle, ws, n, prec_mask, device):
+        self.handle, self.ws, self.n, self.prec_mask, self.device = handle, ws, n, prec_mask, device
+        self.N = int(np.prod(n))
+        self._destroy = lib().fd_destroy
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._destroy(h)
+            self.handle = None
+
+
+def wq_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, k_kind: int = WQ_K_IDENTITY,
+             K_q: Optional[torch.Tensor] = None, prec_mask: int = WQ_F64, device="cuda", stream=None) -> WqOp:
+    ks, nk, kp = _knots(knots)
+    ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+    need = C.c_size_t(0)
+    h = C.c_void_p(0)
+    L = lib()
+    check(L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, C.c_void_p(0), prec_mask, None, 0,
+                     C.byref(need), _stream(stream), C.byref(h)), "wq_setup(size)")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=device)
+    if K_q is not None:
+        K_q = K_q.contiguous()
+    check(L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, _p(K_q), prec_mask, _p(ws), need.value,
+                     None, _stream(stream), C.byref(h)), "wq_setup")
+    return WqOp(h, ws, p, prec_mask, k_kind, device)
+
+
+def wq_dims(op: WqOp) -> Tuple[Tuple[int, int, int], Tuple[int, int, int]]:
+    return op.n, op.nq
+
+
+def wq_quad_points(op: WqOp, stream=None):
+    """(xq: three numpy arrays of parametric points, Fq: device tensor [3, N_q])."""
+    xq = np.empty(sum(op.nq))
+    Fq = torch.empty(3, op.Nq, dtype=torch.float64, device=op.device)
+    check(lib().wq_quad_points(op.handle, C.c_void_p(xq.ctypes.data), _p(Fq), _stream(stream)), "wq_quad_points")
+    o = np.cumsum((0,) + op.nq)
+    return [xq[o[i]:o[i + 1]] for i in range(3)], Fq
+
+
+def wq_detj(op: WqOp, stream=None) -> torch.Tensor:
+    d = torch.empty(op.Nq, dtype=torch.float64, device=op.device)
+    check(lib().wq_detj(op.handle, _p(d), _stream(stream)), "wq_detj")
+    return d
+
+
+def wq_set_coef(op: WqOp, k_kind: int, K_q: Optional[torch.Tensor] = None, stream=None):
+    if K_q is not None:
+        K_q = K_q.contiguous()
+    check(lib().wq_set_coef(op.handle, k_kind, _p(K_q), _stream(stream)), "wq_set_coef")
+    op.k_kind = k_kind
+
+
+def _apply(fn, name, op, v, w, prec, stream):
+    prec = prec or (WQ_F64 if v.dtype == torch.float64 else WQ_F32)
+    _need(v, _DT[prec], op.N, "v")
+    if w is None:
+        w = torch.empty_like(v)
+    _need(w, _DT[prec], op.N, "w")
+    check(fn(op.handle, prec, _p(v), _p(w), _stream(stream)), name)
+    return w
+
+
+def wq_apply(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+             stream=None) -> torch.Tensor:
+    return _apply(lib().wq_apply, "wq_apply", op, v, w, prec, stream)
+
+
+def wq_apply_T(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+               stream=None) -> torch.Tensor:
+    return _apply(lib().wq_apply_T, "wq_apply_T", op, v, w, prec, stream)
+
+
+def wq_rhs(op: WqOp, f_q: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    _need(f_q, torch.float64, op.Nq, "f_q")
+    b = torch.empty(op.N, dtype=torch.float64, device=op.device) if b is None else b
+    _need(b, torch.float64, op.N, "b")
+    check(lib().wq_rhs(op.handle, _p(f_q), _p(b), _stream(stream)), "wq_rhs")
+    return b
+
+
+def wq_grad_K(op: WqOp, lam: torch.Tensor, u: torch.Tensor, gK: Optional[torch.Tensor] = None,
+              stream=None) -> torch.Tensor:
+    _need(lam, torch.float64, op.N, "lam")
+    _need(u, torch.float64, op.N, "u")
+    planes = {WQ_K_IDENTITY: 6, WQ_K_SCALAR: 1, WQ_K_SYM6: 6}[op.k_kind]
+    gK = torch.empty(planes * op.Nq, dtype=torch.float64, device=op.device) if gK is None else gK
+    _need(gK, torch.float64, planes * op.Nq, "gK")
+    check(lib().wq_grad_K(op.handle, _p(lam), _p(u), _p(gK), _stream(stream)), "wq_grad_K")
+    return gK
+
+
+def wq_grad_f(op: WqOp, lam: torch.Tensor, gf: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    _need(lam, torch.float64, op.N, "lam")
+    gf = torch.empty(op.Nq, dtype=torch.float64, device=op.device) if gf is None else gf
+    _need(gf, torch.float64, op.Nq, "gf")
+    check(lib().wq_grad_f(op.handle, _p(lam), _p(gf), _stream(stream)), "wq_grad_f")
+    return gf
+
+
+def fd_setup(p: int, knots: Sequence[np.ndarray], prec_mask: int = WQ_F64, device="cuda", stream=None) -> FdPc:
+    ks, nk, kp = _knots(knots)
+    need = C.c_size_t(0)
+    h = C.c_void_p(0)
+    L = lib()
+    check(L.fd_setup(p, nk, kp, prec_mask, None, 0, C.byref(need), _stream(stream), C.byref(h)), "fd_setup(size)")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=device)
+    check(L.fd_setup(p, nk, kp, prec_mask, _p(ws), need.value, None, _stream(stream), C.byref(h)), "fd_setup")
+    n = tuple(len(k) - p - 3 for k in ks)
+    return FdPc(h, ws, n, prec_mask, device)
+
+
+def fd_apply(P: FdPc, r: torch.Tensor, z: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+             stream=None) -> torch.Tensor:
+    prec = prec or (WQ_F64 if r.dtype == torch.float64 else WQ_F32)
+    _need(r, _DT[prec], P.N, "r")
+    z = torch.empty_like(r) if z is None else z
+    _need(z, _DT[prec], P.N, "z")
+    check(lib().fd_apply(P.handle, prec, _p(r), _p(z), _stream(stream)), "fd_apply")
+    return z
+
+
+def fd_factors(P: FdPc, l: int):
+    n = P.n[l]
+    lam = np.empty(n)
+    U = np.empty((n, n))
+    check(lib().fd_factors(P.handle, l, C.c_void_p(lam.ctypes.data), C.c_void_p(U.ctypes.data)), "fd_factors")
+    return lam, U
+
+
+def krylov_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None, transpose: bool = False,
+                 rtol: float = 1e-10, maxit: int = 2000, ws: Optional[torch.Tensor] = None, stream=None,
+                 raise_on_noconv: bool = True):
+    """Right-preconditioned BiCGStab in FP64.  Returns (x, iterations, relres)."""
+    _need(b, torch.float64, A.N, "b")
+    x = torch.zeros_like(b) if x is None else x
+    _need(x, torch.float64, A.N, "x")
+    nb = lib().krylov_ws_bytes(A.handle)
+    ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    it, rel = C.c_int(0), C.c_double(0)
+    rc = lib().krylov_solve(A.handle, P.handle, int(transpose), _p(b), _p(x), rtol, maxit, _p(ws), ws.numel(),
+                            C.byref(it), C.byref(rel), _stream(stream))
+    if rc != 0 and (raise_on_noconv or rc != -6):
+        check(rc, "krylov_solve")
+    return x, it.value, rel.value
+
+
+def ir_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None, fd_prec: int = WQ_BF16,
+             rtol: float = 1e-10, tau_inner: float = 1e-3, max_outer: int = 30, maxit_inner: int = 500,
+             ws: Optional[torch.Tensor] = None, stream=None):
+    """Mixed-precision iterative refinement.  Returns (x, outer, inner_total, relres)."""
+    _need(b, torch.float64, A.N, "b")
+    x = torch.zeros_like(b) if x is None else x
+    _need(x, torch.float64, A.N, "x")
+    nb = lib().ir_ws_bytes(A.handle)
+    ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    outer, inner, rel = C.c_int(0), C.c_int(0), C.c_double(0)
+    check(lib().ir_solve(A.handle, P.handle, fd_prec, _p(b), _p(x), rtol, tau_inner, max_outer, maxit_inner, _p(ws),
+                         ws.numel(), C.byref(outer), C.byref(inner), C.byref(rel), _stream(stream)), "ir_solve")
+    return x, outer.value, inner.value, rel.value

@@ -1,0 +1,106 @@
+"""Host-side set-up of the library (C++, no GPU) against the CPU oracle:
+quadrature points, basis matrices and weighted-quadrature weights of one
+direction, the FD generalized eigenpairs, and the geometry at the quadrature
+points.  The two sides share no code; agreement is to rounding (weights: to the
+conditioning of the local exactness systems)."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import wq as owq
+from oracle.geometry import map_and_jacobian
+from oracle.operator import Problem
+
+
+def L():
+    from paper_1712_08565_amd import _lib
+    return _lib.lib()
+
+
+def space_1d(p, k):
+    k = np.ascontiguousarray(k, dtype=np.float64)
+    n, nq = C.c_int32(0), C.c_int32(0)
+    assert L().wq_space_1d(p, len(k), C.c_void_p(k.ctypes.data), C.byref(n), C.byref(nq), None, None, None) == 0
+    n, nq = n.value, nq.value
+    xq, B, W = np.empty(nq), np.empty((2, nq, n)), np.empty((4, n, nq))
+    assert L().wq_space_1d(p, len(k), C.c_void_p(k.ctypes.data), C.byref(C.c_int32()), C.byref(C.c_int32()),
+                           C.c_void_p(xq.ctypes.data), C.c_void_p(B.ctypes.data), C.c_void_p(W.ctypes.data)) == 0
+    return xq, B, W
+
+
+def nonuniform(n_el, p, seed):
+    rng = np.random.default_rng(seed)
+    br = np.sort(rng.uniform(0.08, 0.92, n_el - 1))
+    br = np.unique(np.round(br, 3))
+    return np.concatenate([np.zeros(p + 1), br, np.ones(p + 1)])
+
+
+@pytest.mark.parametrize("p", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("kind", ["uniform", "nonuniform"])
+def test_space_1d_matches_oracle(p, kind):
+    k = synth.uniform_knots(11, p) if kind == "uniform" else nonuniform(9, p, 100 + p)
+    xq, B, W = space_1d(p, k)
+    S = owq.Space1D(k, p)
+    assert np.array_equal(xq, S.xq) or np.abs(xq - S.xq).max() < 1e-15
+    for d in (0, 1):
+        assert np.abs(B[d] - S.B[d]).max() <= 1e-13 * max(1.0, np.abs(S.B[d]).max())
+    tol = 1e-12 if kind == "uniform" else 1e-9
+    for a in (0, 1):
+        for b in (0, 1):
+            ref = S.W[(a, b)]
+            got = W[2 * a + b]
+            assert np.array_equal(got != 0, ref != 0) or np.abs(got - ref).max() < 1e-14
+            assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (a, b)
+
+
+@pytest.mark.parametrize("p", [2, 4, 6])
+def test_fd_eigenpairs_match_oracle(p):
+    k = nonuniform(10, p, 7)
+    S = owq.Space1D(k, p)
+    kk = np.ascontiguousarray(k)
+    lam, U = np.empty(S.n), np.empty((S.n, S.n))
+    assert L().fd_eig_1d(p, len(kk), C.c_void_p(kk.ctypes.data), C.c_void_p(lam.ctypes.data),
+                         C.c_void_p(U.ctypes.data)) == 0
+    import scipy.linalg as sla
+    lam_ref = sla.eigh(S.K, S.M, eigvals_only=True)
+    assert np.abs(lam - lam_ref).max() <= 1e-11 * lam_ref.max()
+    assert np.abs(U.T @ S.M @ U - np.eye(S.n)).max() < 1e-11
+    assert np.abs(U.T @ S.K @ U - np.diag(lam)).max() < 1e-10 * lam.max()
+
+
+@pytest.mark.parametrize("name", ["ring8_p3", "twist6_p6", "shear6_p3"])
+def test_geometry_matches_oracle(name):
+    wl = synth.workload(name)
+    kn = wl.knots()
+    ctrl = wl.ctrl()
+    spaces = [owq.Space1D(k, wl.p) for k in kn]
+    F_ref, J_ref = map_and_jacobian(spaces, ctrl)
+    Nq = F_ref[..., 0].size
+    ks = [np.ascontiguousarray(k) for k in kn]
+    nk = (C.c_int32 * 3)(*[len(k) for k in ks])
+    kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
+    det, Ji, F = np.empty(Nq), np.empty((9, Nq)), np.empty((3, Nq))
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(det.ctypes.data),
+                              C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
+    assert rc == 0
+    assert np.abs(F - F_ref.reshape(Nq, 3).T).max() < 1e-13
+    assert np.abs(det - np.linalg.det(J_ref).ravel()).max() < 1e-12 * np.abs(det).max()
+    Ji_ref = np.linalg.inv(J_ref).reshape(Nq, 9).T
+    assert np.abs(Ji - Ji_ref).max() < 1e-12 * np.abs(Ji_ref).max()
+
+
+def test_inverted_geometry_is_reported():
+    wl = synth.workload("cube5_p2")
+    kn = wl.knots()
+    ctrl = wl.ctrl()[..., ::-1].copy()      # swap x and z: det J < 0
+    ks = [np.ascontiguousarray(k) for k in kn]
+    nk = (C.c_int32 * 3)(*[len(k) for k in ks])
+    kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
+    Nq = 15 ** 3
+    det, Ji, F = np.empty(Nq), np.empty((9, Nq)), np.empty((3, Nq))
+    from paper_1712_08565_amd import _lib
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(det.ctypes.data),
+                              C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
+    assert rc == _lib.WQ_EGEOM

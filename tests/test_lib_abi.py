@@ -1,0 +1,95 @@
+"""The C ABI library loads without a GPU and exports every function that
+include/wqfd.h declares; host-side argument errors are reported as documented
+(no device work is started by these calls)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wqfd.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][A-Za-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if not n.startswith("__")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("wq_setup", "wq_apply", "wq_apply_T", "fd_setup", "fd_apply", "krylov_solve", "ir_solve",
+              "wq_grad_K", "wq_grad_f", "wq_rhs"):
+        assert n in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    declared = declared_functions()
+    bound = {n for n, _, _ in _lib.SIGNATURES}
+    assert set(declared) == bound, (set(declared) ^ bound)
+    for n in declared:
+        assert hasattr(L, n)
+    assert b"gfx950" in L.wq_version()
+
+
+def _setup_args(p, knots):
+    ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
+    nk = (C.c_int32 * 3)(*[len(k) for k in ks])
+    kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
+    return ks, nk, kp
+
+
+@pytest.mark.parametrize("case", ["p_low", "p_high", "not_open", "multiple_knot", "too_few_elements"])
+def test_invalid_spaces_are_rejected_on_the_host(case):
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    p = 3
+    k = synth.uniform_knots(6, p)
+    if case == "p_low":
+        p = 1
+    elif case == "p_high":
+        p = 11
+    elif case == "not_open":
+        k = k.copy()
+        k[0] = -0.1
+    elif case == "multiple_knot":
+        k = k.copy()
+        k[p + 2] = k[p + 1]
+    elif case == "too_few_elements":
+        k = synth.uniform_knots(2, p)
+    ks, nk, kp = _setup_args(p, (k, k, k))
+    m = len(k) - 3 - 1
+    ctrl = np.zeros((m, m, m, 3))
+    need = C.c_size_t(0)
+    rc = L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 1, None, 0, C.byref(need), None, None)
+    assert rc == _lib.WQ_EINVAL
+    assert len(L.wq_last_error()) > 0
+    rc = L.fd_setup(p, nk, kp, 1, None, 0, C.byref(need), None, None)
+    assert rc == _lib.WQ_EINVAL
+
+
+def test_size_query_needs_no_device():
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    wl = synth.workload("cube12_p3")
+    ks, nk, kp = _setup_args(wl.p, wl.knots())
+    ctrl = wl.ctrl()
+    need = C.c_size_t(0)
+    assert L.wq_setup(3, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 3, None, 0, C.byref(need), None,
+                      None) == 0
+    Nq = 31 ** 3
+    assert need.value > (10 + 3 + 6) * 8 * Nq + 6 * 4 * Nq
+    assert L.fd_setup(3, nk, kp, 7, None, 0, C.byref(need), None, None) == 0
+    assert need.value >= 3 * 13 * 13 * 8 + 13 ** 3 * 8
+    # bad enums are rejected before any device work
+    assert L.wq_setup(3, nk, kp, C.c_void_p(ctrl.ctypes.data), 5, None, 1, None, 0, C.byref(need), None,
+                      None) == _lib.WQ_EINVAL
+    assert L.wq_setup(3, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 8, None, 0, C.byref(need), None,
+                      None) == _lib.WQ_EINVAL
