@@ -1,0 +1,217 @@
+"""Benchmark of the MF-WQ hot path on one MI355X.
+
+Workload: the thick quarter ring (spline geometry + 0.02 smooth noise, K = I,
+oscillating source), 64 elements per direction, degrees p = 2..6 -- the
+full-size FP64 configuration of the benchmark (degrees 3..6, plus p = 2 that the
+metric also names).  Inputs are synthetic and seeded (``synth``).
+
+One step = for every degree p:
+  * R timed FP64 operator applies w = K~ v (HIP events around each launch on the
+    stream the library runs on),
+  * one FP64 right-preconditioned BiCGStab solve to relative residual 1e-10,
+  * one mixed-precision solve (FP32 apply, BF16 FD, FP64 refinement) to the
+    same residual.
+Set-up (splines, weights, geometry, FD eigenpairs) is outside the timed region.
+
+value   = FP64 apply throughput, sum_p N_p * applies / sum of apply times (GDOF/s)
+roofline: algorithmic bytes of one FP64 apply = 48 N_q + 16 N (six coefficient
+          planes read once, v read and w written once) over the average apply time.
+cpu_baseline: the CPU FP64 oracle's matrix-free apply on a bounded sample
+          (degree 3 of the same workload), timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "WQ apply GDOF/s & time-to-solve to rel.res 1e-10, FP64 vs mixed, p=2..6"
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(budget_s: float):
+    """Oracle matrix-free apply (CPU FP64) on ring64 p=3: GDOF/s on this host."""
+    import numpy as np
+
+    import synth
+    from oracle.operator import Problem
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    wl = synth.workload("ring64_p3")
+    t0 = time.perf_counter()
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    log(f"cpu oracle setup {time.perf_counter() - t0:.1f}s")
+    v = synth.random_vector(pr.N, 42)
+    pr.apply(v)  # warm-up
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        pr.apply(v)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start > budget_s or len(times) >= 100:
+            break
+    t = float(np.median(times))
+    return {"value": pr.N / t / 1e9, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"ring64 p=3 (N={pr.N}), {len(times)} FP64 matrix-free applies, median {t:.3f} s each; "
+                      f"host cpus={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--degrees", default="2,3,4,5,6")
+    ap.add_argument("--n-el", type=int, default=64)
+    ap.add_argument("--reps", type=int, default=20, help="timed applies per degree per step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-solve", action="store_true", help="time the applies only")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the multi-GPU (z-slab) decomposition is a design note, "
+              "not built (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1712_08565_amd import problem, wqfd
+
+    torch.cuda.set_device(0)
+    degrees = [int(x) for x in args.degrees.split(",")]
+    probs = {}
+    for p in degrees:
+        wl = synth.Workload(f"ring{args.n_el}_p{p}", args.n_el, p, "ring", 0.02, "identity", "paper")
+        t0 = time.perf_counter()
+        dp = problem.build(wl, wqfd.WQ_F64 | wqfd.WQ_F32, wqfd.WQ_F64 | wqfd.WQ_F32 | wqfd.WQ_BF16)
+        torch.cuda.synchronize()
+        v = torch.as_tensor(synth.random_vector(dp.A.N, 42), device="cuda")
+        w = torch.empty_like(v)
+        kws = torch.empty(wqfd.lib().krylov_ws_bytes(dp.A.handle), dtype=torch.uint8, device="cuda")
+        iws = torch.empty(wqfd.lib().ir_ws_bytes(dp.A.handle), dtype=torch.uint8, device="cuda")
+        # reference solution for the equal-accuracy comparison (outside the timed region)
+        xref, it_ref, res_ref = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-13, maxit=2000, ws=kws,
+                                                  raise_on_noconv=False)
+        probs[p] = dict(dp=dp, v=v, w=w, kws=kws, iws=iws, xref=xref, x=torch.zeros_like(v),
+                        N=dp.A.N, Nq=dp.A.Nq, setup_s=time.perf_counter() - t0)
+        log(f"setup p={p}: N={dp.A.N} Nq={dp.A.Nq} {probs[p]['setup_s']:.1f}s (ref solve {it_ref} it, "
+            f"relres {res_ref:.1e})")
+
+    stream = torch.cuda.current_stream()
+    rec = {p: dict(apply_ms=[], fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
+                   mix_err=[]) for p in degrees}
+
+    def one_step(record: bool):
+        for p in degrees:
+            P = probs[p]
+            dp = P["dp"]
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.reps)]
+            for e0, e1 in evs:
+                e0.record(stream)
+                wqfd.wq_apply(dp.A, P["v"], P["w"])
+                e1.record(stream)
+            if not args.no_solve:
+                P["x"].zero_()
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                _, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, x=P["x"], rtol=1e-10, maxit=2000, ws=P["kws"])
+                s1.record(stream)
+                xm = torch.zeros_like(P["x"])
+                m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                m0.record(stream)
+                _, outer, inner, mres = wqfd.ir_solve(dp.A, dp.P, dp.b, x=xm, fd_prec=wqfd.WQ_BF16, rtol=1e-10,
+                                                      tau_inner=1e-3, ws=P["iws"])
+                m1.record(stream)
+            torch.cuda.synchronize()
+            if record:
+                r = rec[p]
+                r["apply_ms"] += [e0.elapsed_time(e1) for e0, e1 in evs]
+                if not args.no_solve:
+                    nref = torch.linalg.norm(P["xref"]).item()
+                    r["fp64_ms"].append(s0.elapsed_time(s1))
+                    r["fp64_it"].append(it)
+                    r["fp64_err"].append(torch.linalg.norm(P["x"] - P["xref"]).item() / nref)
+                    r["mix_ms"].append(m0.elapsed_time(m1))
+                    r["mix_outer"].append(outer)
+                    r["mix_inner"].append(inner)
+                    r["mix_err"].append(torch.linalg.norm(xm - P["xref"]).item() / nref)
+
+    for i in range(args.warmup):
+        one_step(False)
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one_step(True)
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    tot_dof = sum(probs[p]["N"] * len(rec[p]["apply_ms"]) for p in degrees)
+    tot_s = sum(sum(rec[p]["apply_ms"]) for p in degrees) / 1e3
+    tot_bytes = sum((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) * len(rec[p]["apply_ms"]) for p in degrees)
+    n_apply = sum(len(rec[p]["apply_ms"]) for p in degrees)
+    achieved = tot_bytes / tot_s / 1e9
+    per_p = {}
+    for p in degrees:
+        r = rec[p]
+        t_ap = float(np.mean(r["apply_ms"]))
+        d = {"N": probs[p]["N"], "Nq": probs[p]["Nq"], "apply_ms": round(t_ap, 4),
+             "apply_GDOFs": round(probs[p]["N"] / t_ap / 1e6, 3),
+             "apply_GBs": round((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) / t_ap / 1e6, 1),
+             "setup_s": round(probs[p]["setup_s"], 2)}
+        if not args.no_solve:
+            d.update({"fp64_solve_ms": round(float(np.median(r["fp64_ms"])), 2),
+                      "fp64_iters": int(np.median(r["fp64_it"])),
+                      "fp64_rel_err_vs_tight": float(np.max(r["fp64_err"])),
+                      "mixed_solve_ms": round(float(np.median(r["mix_ms"])), 2),
+                      "mixed_outer": int(np.median(r["mix_outer"])), "mixed_inner": int(np.median(r["mix_inner"])),
+                      "mixed_rel_err_vs_tight": float(np.max(r["mix_err"]))})
+        per_p[f"p{p}"] = d
+    out = {
+        "metric": METRIC,
+        "value": round(tot_dof / tot_s / 1e9, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded spline ring geometry, K = I, oscillating source)",
+        "config": {"workload": f"thick quarter ring, {args.n_el}^3 elements, degrees {args.degrees}, "
+                               f"FP64 apply + FP64 BiCGStab/FD and mixed FP32/BF16 IR solves to rel.res 1e-10",
+                   "n_el": args.n_el, "degrees": degrees, "applies_per_degree_per_step": args.reps},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "wq_apply (FP64)", "launches": n_apply,
+                     "bytes_per_launch": "48 N_q + 16 N"},
+        "per_degree": per_p,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -140,6 +142,99 @@ int check_knots_args(int p, const int32_t nknots[3], const double* const knots[3
     return WQ_OK;
 }
 
+// Tables of the fused apply: dense 16 x 16 blocks of the x and y factors per
+// 16-point tile and the z windows per quadrature plane (see fused.h).
+struct FusedHost {
+    int ntile[2] = {0, 0};
+    std::vector<double> tiles[2];   // [t][6][256]
+    std::vector<int> J[2], I[2];
+    std::vector<int> bs3, wts3;
+    std::vector<double> cz;         // [nq3][2(p+1) + 4(p+2)]
+    int zchunk = 0;
+};
+
+bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
+    if (p > 7) return false;
+    for (int l = 0; l < 2; ++l) {
+        const wqfd::Space1D& S = sp[l];
+        const int n = S.n, nq = S.nq, nt = (nq + 15) / 16;
+        fh.ntile[l] = nt;
+        fh.tiles[l].assign((size_t)nt * 6 * 256, 0.0);
+        fh.J[l].assign(nt, 0);
+        fh.I[l].assign(nt, 0);
+        const std::vector<double>* Wv[4] = {&S.W[0][0], &S.W[0][1], &S.W[1][0], &S.W[1][1]};
+        for (int t = 0; t < nt; ++t) {
+            const int Q = 16 * t, qe = std::min(Q + 16, nq);
+            int jmin = n, jmax = -1, imin = n, imax = -1;
+            for (int q = Q; q < qe; ++q)
+                for (int j = 0; j < n; ++j)
+                    if (S.B[0][(size_t)q * n + j] != 0.0 || S.B[1][(size_t)q * n + j] != 0.0) {
+                        jmin = std::min(jmin, j);
+                        jmax = std::max(jmax, j);
+                    }
+            for (int i = 0; i < n; ++i)
+                for (int q = Q; q < qe; ++q) {
+                    bool nz = false;
+                    for (auto* W : Wv) nz |= (*W)[(size_t)i * nq + q] != 0.0;
+                    if (nz) {
+                        imin = std::min(imin, i);
+                        imax = std::max(imax, i);
+                    }
+                }
+            if (jmax < 0) jmin = jmax = 0;
+            if (imax < 0) imin = imax = 0;
+            if (jmax - jmin >= 16 || imax - imin >= 16) return false;
+            fh.J[l][t] = jmin;
+            fh.I[l][t] = imin;
+            double* blk = &fh.tiles[l][(size_t)t * 6 * 256];
+            for (int a = 0; a < 16; ++a)
+                for (int b = 0; b < 16; ++b) {
+                    const int q = Q + a, j = jmin + b;       // B_d[q][j]
+                    if (q < nq && j < n) {
+                        blk[0 * 256 + a * 16 + b] = S.B[0][(size_t)q * n + j];
+                        blk[1 * 256 + a * 16 + b] = S.B[1][(size_t)q * n + j];
+                    }
+                    const int i = imin + a, qq = Q + b;      // W_v[i][q]
+                    if (i < n && qq < nq)
+                        for (int v = 0; v < 4; ++v) blk[(2 + v) * 256 + a * 16 + b] = (*Wv[v])[(size_t)i * nq + qq];
+                }
+        }
+    }
+    const wqfd::Space1D& S3 = sp[2];
+    const int n3 = S3.n, nq3 = S3.nq, RT = p + 1, RO = p + 2, CZ = 2 * RT + 4 * RO;
+    HostBand hB = make_band({&S3.B[0], &S3.B[1]}, nq3, n3, false);
+    HostBand hWT = make_band({&S3.W[0][0], &S3.W[0][1], &S3.W[1][0], &S3.W[1][1]}, nq3, n3, true);
+    if (hB.L > RT || hWT.L > RO) return false;
+    fh.bs3 = hB.start;
+    fh.wts3 = hWT.start;
+    for (int k = 1; k < nq3; ++k)
+        if (fh.bs3[k] < fh.bs3[k - 1] || fh.wts3[k] < fh.wts3[k - 1]) return false;
+    fh.cz.assign((size_t)nq3 * CZ, 0.0);
+    const std::vector<double>* Wv[4] = {&S3.W[0][0], &S3.W[0][1], &S3.W[1][0], &S3.W[1][1]};
+    for (int k = 0; k < nq3; ++k) {
+        double* c = &fh.cz[(size_t)k * CZ];
+        for (int s = 0; s < RT; ++s) {
+            const int j = fh.bs3[k] + s;
+            if (j < n3) {
+                c[s] = S3.B[0][(size_t)k * n3 + j];
+                c[RT + s] = S3.B[1][(size_t)k * n3 + j];
+            }
+        }
+        for (int v = 0; v < 4; ++v)
+            for (int s = 0; s < RO; ++s) {
+                const int i = fh.wts3[k] + s;
+                if (i < n3) c[2 * RT + v * RO + s] = (*Wv[v])[(size_t)i * nq3 + k];
+            }
+    }
+    // z ranges: about 1024 workgroups, but no range shorter than 3 (p + 2) planes
+    const int tiles = fh.ntile[0] * fh.ntile[1];
+    int nzc = (1024 + tiles - 1) / tiles;
+    nzc = std::max(1, std::min(nzc, nq3 / (3 * (p + 2))));
+    if (const char* e = std::getenv("WQFD_ZCHUNKS")) nzc = std::max(1, std::min(nq3, std::atoi(e)));
+    fh.zchunk = (nq3 + nzc - 1) / nzc;
+    return true;
+}
+
 uint16_t f32_to_bf16_bits(float f) {
     uint32_t u;
     std::memcpy(&u, &f, 4);
@@ -215,6 +310,25 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
         doff[l].BT32 = pack_band<float>(pk, hBT, sBT);
         doff[l].WT32 = pack_band<float>(pk, hWT, sWT);
     }
+    // fused-apply tables, both precisions
+    FusedHost fh;
+    const bool fused_ok = build_fused_tables(sp, p, fh) && !std::getenv("WQFD_STAGED");
+    size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0};
+    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0;
+    if (fused_ok) {
+        for (int l = 0; l < 2; ++l) {
+            f_tiles64[l] = pk.add(fh.tiles[l].data(), fh.tiles[l].size() * 8);
+            std::vector<float> t32(fh.tiles[l].begin(), fh.tiles[l].end());
+            f_tiles32[l] = pk.add(t32.data(), t32.size() * 4);
+            f_J[l] = pk.add(fh.J[l].data(), fh.J[l].size() * sizeof(int));
+            f_I[l] = pk.add(fh.I[l].data(), fh.I[l].size() * sizeof(int));
+        }
+        f_bs3 = pk.add(fh.bs3.data(), fh.bs3.size() * sizeof(int));
+        f_wts3 = pk.add(fh.wts3.data(), fh.wts3.size() * sizeof(int));
+        f_cz64 = pk.add(fh.cz.data(), fh.cz.size() * 8);
+        std::vector<float> c32(fh.cz.begin(), fh.cz.end());
+        f_cz32 = pk.add(c32.data(), c32.size() * 4);
+    }
     // workspace layout
     size_t off = 0;
     const size_t o_tab = off;
@@ -272,6 +386,34 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
             patch(&d32.W[v], doff[l].W32, v, tb);
             patch(&d32.WT[v], doff[l].WT32, v, tb);
         }
+    }
+    if (fused_ok) {
+        auto fill = [&](auto& fz, size_t ot0, size_t ot1, size_t ocz, auto* Cp) {
+            using T = std::remove_pointer_t<decltype(Cp)>;
+            fz.C = Cp;
+            fz.n1 = o.n[0];
+            fz.n2 = o.n[1];
+            fz.n3 = o.n[2];
+            fz.nq1 = o.nq[0];
+            fz.nq2 = o.nq[1];
+            fz.nq3 = o.nq[2];
+            fz.Nq = o.Nq;
+            fz.tilesX = reinterpret_cast<const T*>(tb + ot0);
+            fz.tilesY = reinterpret_cast<const T*>(tb + ot1);
+            fz.JX = reinterpret_cast<const int*>(tb + f_J[0]);
+            fz.IX = reinterpret_cast<const int*>(tb + f_I[0]);
+            fz.JY = reinterpret_cast<const int*>(tb + f_J[1]);
+            fz.IY = reinterpret_cast<const int*>(tb + f_I[1]);
+            fz.bs3 = reinterpret_cast<const int*>(tb + f_bs3);
+            fz.wts3 = reinterpret_cast<const int*>(tb + f_wts3);
+            fz.cz = reinterpret_cast<const T*>(tb + ocz);
+            fz.ntx = fh.ntile[0];
+            fz.nty = fh.ntile[1];
+            fz.zchunk = fh.zchunk;
+        };
+        fill(o.fz64, f_tiles64[0], f_tiles64[1], f_cz64, o.C64);
+        fill(o.fz32, f_tiles32[0], f_tiles32[1], f_cz32, o.C32);
+        o.fused = true;
     }
     HIP_TRY(wqfd::launch_set_coef(o, k_kind, K_q, s), "set_coef");
     HIP_TRY(hipStreamSynchronize(s), "wq_setup sync");

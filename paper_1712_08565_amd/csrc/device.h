@@ -7,6 +7,9 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
+
+#include "fused.h"
 
 namespace wqfd {
 
@@ -51,6 +54,9 @@ struct WqOp {
     size_t scratch_bytes = 0;
     OpTables<double> t64;
     OpTables<float> t32;
+    bool fused = false;         // fused apply available (p <= 7 and tile footprints fit)
+    FusedArgs<double> fz64;     // fused-apply tables (v, w filled per call)
+    FusedArgs<float> fz32;
     std::vector<double> xq[3];  // host copy of the quadrature points
 };
 

@@ -281,7 +281,7 @@ hipError_t fd_apply_bf16(const FdPc& P, const float* r, float* z, hipStream_t s)
     int npad[3];
     const __bf16 *Tf[3], *Tb[3];
     for (int l = 0; l < 3; ++l) {
-        npad[l] = (P.n[l] + 31) / 32 * 32;
+        npad[l] = (P.n[l] + 63) / 64 * 64;   // rows and columns padded as stored by fd_setup
         Tf[l] = reinterpret_cast<const __bf16*>(P.Ubf[l]);
         Tb[l] = Tf[l] + (size_t)npad[l] * npad[l];
     }

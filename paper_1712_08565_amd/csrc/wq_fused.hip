@@ -1,0 +1,284 @@
+// Fused MF-WQ stiffness apply (Algorithm 2, Section 3.2) for gfx950.
+//
+// One workgroup owns a 16 x 16 tile of quadrature columns (q1, q2) and a
+// contiguous range of quadrature planes k, and streams through k:
+//
+//   trial (v~^b = B^(b) v):  each DOF plane j3 entering the z window is
+//       contracted in x and y on the matrix cores (two 16x16x16 products for
+//       x, three for y), giving U_x = (B2 x B-dot1) v, U_y = (B-dot2 x B1) v,
+//       U_0 = (B2 x B1) v at the tile's columns; every thread keeps the last
+//       p+1 planes of its column in registers and forms
+//         v~^x = sum_j3 B3 U_x,  v~^y = sum_j3 B3 U_y,  v~^z = sum_j3 B-dot3 U_0.
+//   pointwise: psi_ab = C_ab(x_q) v~^b, the six coefficient planes streamed
+//       from HBM once, coalesced along x.
+//   test, z first: every thread accumulates W3^{a3 b3}[i3][k] psi_ab into a
+//       register window of the p+2 output planes i3 that plane k touches.
+//   test, x and y: when plane i3 leaves the window, the nine fields of the
+//       tile are contracted with W2^{a2 b2} (y) and W1^{a1 b1} (x) on the matrix
+//       cores and the 16 x 16 DOF block is added to w with atomics (tiles and
+//       z ranges overlap in the DOFs they touch).
+//
+// The banded 1D factors restricted to a tile are stored as dense 16 x 16
+// blocks (DOF footprints of 16 quadrature points fit in 16 for p <= 7), held in
+// LDS for the whole kernel.  FP64 uses v_mfma_f64_16x16x4f64, FP32
+// v_mfma_f32_16x16x4f32.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "fused.h"
+
+namespace wqfd {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
+constexpr int BLK = 16 * LD;
+
+template <typename T>
+struct MF;
+template <>
+struct MF<double> {
+    using acc = d4;
+    __device__ static acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int kb, int v) { return kb + 4 * v; }
+};
+template <>
+struct MF<float> {
+    using acc = f4;
+    __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int kb, int v) { return 4 * kb + v; }
+};
+
+// 16x16x16 product accumulated into c.  A[m][k] = At[m][k]; B[k][n] = Bt[k][n]
+// (BT = false) or Bt[n][k] (BT = true).
+template <typename T, bool BT>
+__device__ inline typename MF<T>::acc gemm16(const T* At, const T* Bt, typename MF<T>::acc c, int cl, int kb) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const T a = At[cl * LD + 4 * s + kb];
+        const T b = BT ? Bt[cl * LD + 4 * s + kb] : Bt[(4 * s + kb) * LD + cl];
+        c = MF<T>::mma(a, b, c);
+    }
+    return c;
+}
+
+template <typename T>
+__device__ inline void store16(T* tile, const typename MF<T>::acc& c, int cl, int kb) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) tile[MF<T>::drow(kb, v) * LD + cl] = c[v];
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
+    constexpr int RT = P + 1;              // trial window (DOF planes)
+    constexpr int RO = P + 2;              // test window (output planes)
+    constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
+    __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
+    __shared__ T sT[6][BLK];               // V, A_0, A_1, U_x, U_y, U_0
+    __shared__ T sP[9][BLK];               // psi_f, then per-wave partial sums
+    __shared__ T sY[9][BLK];               // y-contracted fields
+
+    using acc_t = typename MF<T>::acc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int q1l = tid & 15, q2l = tid >> 4;
+
+    // workgroup -> (t1, t2, zc); consecutive blocks are dealt round-robin to the
+    // eight XCDs, so hand each XCD a contiguous run of neighbouring tiles
+    const int nblk = gridDim.x, b = blockIdx.x;
+    const int base = nblk / 8, rem = nblk % 8, xcd = b % 8, slot = b / 8;
+    const int lin = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
+    const int t1 = lin % a.ntx;
+    const int t2 = (lin / a.ntx) % a.nty;
+    const int zc = lin / (a.ntx * a.nty);
+    const int k0 = zc * a.zchunk;
+    const int k1 = min(a.nq3, k0 + a.zchunk);
+    if (k0 >= k1) return;
+
+    const int Q1 = t1 * 16, Q2 = t2 * 16;
+    const int q1 = Q1 + q1l, q2 = Q2 + q2l;
+    const bool active = q1 < a.nq1 && q2 < a.nq2;
+    const int J1 = a.JX[t1], I1 = a.IX[t1], J2 = a.JY[t2], I2 = a.IY[t2];
+
+    // coefficient blocks of this tile
+    for (int idx = tid; idx < 12 * 256; idx += 256) {
+        const int tl = idx >> 8, e = idx & 255;
+        const T* src;
+        if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
+        else if (tl < 4) src = a.tilesY + ((size_t)t2 * 6 + (tl - 2)) * 256;
+        else if (tl < 8) src = a.tilesX + ((size_t)t1 * 6 + 2 + (tl - 4)) * 256;
+        else src = a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;
+        sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
+    }
+
+    // trial contraction of DOF plane j3 onto the tile's columns
+    auto trial_plane = [&](int j3, T& ux, T& uy, T& u0) {
+        {
+            const int j1 = J1 + q1l, j2 = J2 + q2l;
+            T val = T(0);
+            if (j3 < a.n3 && j1 < a.n1 && j2 < a.n2) val = a.v[((size_t)j3 * a.n2 + j2) * a.n1 + j1];
+            sT[0][q2l * LD + q1l] = val;                       // V[j2][j1]
+        }
+        __syncthreads();
+        if (wave < 2) {                                        // A_d[j2][q1] = sum_j1 V[j2][j1] B1_d[q1][j1]
+            acc_t c = {0, 0, 0, 0};
+            c = gemm16<T, true>(sT[0], sCoef[wave], c, cl, kb);
+            store16<T>(sT[1 + wave], c, cl, kb);
+        }
+        __syncthreads();
+        if (wave < 3) {                                        // U[q2][q1] = sum_j2 B2_d[q2][j2] A[j2][q1]
+            const T* At = sCoef[2 + (wave == 1 ? 1 : 0)];      // U_y uses B-dot2
+            const T* Bt = sT[wave == 0 ? 2 : 1];               // U_x uses A_1 (B-dot1)
+            acc_t c = {0, 0, 0, 0};
+            c = gemm16<T, false>(At, Bt, c, cl, kb);
+            store16<T>(sT[3 + wave], c, cl, kb);
+        }
+        __syncthreads();
+        ux = sT[3][q2l * LD + q1l];
+        uy = sT[4][q2l * LD + q1l];
+        u0 = sT[5][q2l * LD + q1l];
+    };
+
+    // x/y test contraction of output plane i3 and atomic update of w
+    auto flush = [&](int i3, const T* vals) {
+        if (i3 < 0 || i3 >= a.n3) return;                      // uniform across the workgroup
+#pragma unroll
+        for (int f = 0; f < 9; ++f) sP[f][q2l * LD + q1l] = vals[f];
+        __syncthreads();
+        for (int f = wave; f < 9; f += 4) {                    // Y_f[i2][q1] = sum_q2 W2[i2][q2] psi_f[q2][q1]
+            const int al = f / 3, be = f % 3;
+            const int v2 = 2 * (al == 1) + (be == 1);
+            acc_t c = {0, 0, 0, 0};
+            c = gemm16<T, false>(sCoef[8 + v2], sP[f], c, cl, kb);
+            store16<T>(sY[f], c, cl, kb);
+        }
+        __syncthreads();
+        acc_t z = {0, 0, 0, 0};
+        for (int f = wave; f < 9; f += 4) {                    // Z[i2][i1] += sum_q1 Y_f[i2][q1] W1[i1][q1]
+            const int al = f / 3, be = f % 3;
+            const int v1 = 2 * (al == 0) + (be == 0);
+            z = gemm16<T, true>(sY[f], sCoef[4 + v1], z, cl, kb);
+        }
+        store16<T>(sP[wave], z, cl, kb);
+        __syncthreads();
+        {
+            const T s = sP[0][q2l * LD + q1l] + sP[1][q2l * LD + q1l] + sP[2][q2l * LD + q1l] + sP[3][q2l * LD + q1l];
+            const int i1 = I1 + q1l, i2 = I2 + q2l;
+            if (i1 < a.n1 && i2 < a.n2 && s != T(0)) atomicAdd(&a.w[((size_t)i3 * a.n2 + i2) * a.n1 + i1], s);
+        }
+        __syncthreads();
+    };
+
+    T Ux[RT], Uy[RT], U0[RT];
+    T acc[9][RO];
+#pragma unroll
+    for (int f = 0; f < 9; ++f)
+#pragma unroll
+        for (int s = 0; s < RO; ++s) acc[f][s] = T(0);
+
+    int tbase = a.bs3[k0];
+    int obase = a.wts3[k0];
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < RT; ++s) trial_plane(tbase + s, Ux[s], Uy[s], U0[s]);
+
+    const size_t Nq = a.Nq;
+    const size_t col = (size_t)q2 * a.nq1 + q1;
+    for (int k = k0; k < k1; ++k) {
+        const int bk = a.bs3[k], wk = a.wts3[k];
+        while (tbase < bk) {                                   // slide the trial window
+#pragma unroll
+            for (int s = 0; s < RT - 1; ++s) {
+                Ux[s] = Ux[s + 1];
+                Uy[s] = Uy[s + 1];
+                U0[s] = U0[s + 1];
+            }
+            trial_plane(tbase + RT, Ux[RT - 1], Uy[RT - 1], U0[RT - 1]);
+            ++tbase;
+        }
+        while (obase < wk) {                                   // retire the oldest output plane
+            T vals[9];
+#pragma unroll
+            for (int f = 0; f < 9; ++f) vals[f] = acc[f][0];
+            flush(obase, vals);
+#pragma unroll
+            for (int f = 0; f < 9; ++f) {
+#pragma unroll
+                for (int s = 0; s < RO - 1; ++s) acc[f][s] = acc[f][s + 1];
+                acc[f][RO - 1] = T(0);
+            }
+            ++obase;
+        }
+        const T* cz = a.cz + (size_t)k * CZ;
+        T g[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int s = 0; s < RT; ++s) {
+            g[0] += cz[s] * Ux[s];
+            g[1] += cz[s] * Uy[s];
+            g[2] += cz[RT + s] * U0[s];
+        }
+        T C[6];
+        const size_t q = (size_t)k * a.nq1 * a.nq2 + col;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) C[c] = active ? a.C[c * Nq + q] : T(0);
+        // psi_ab = C_ab g_b, plane order (C11, C22, C33, C12, C13, C23)
+        const T psi[9] = {C[0] * g[0], C[3] * g[1], C[4] * g[2],
+                          C[3] * g[0], C[1] * g[1], C[5] * g[2],
+                          C[4] * g[0], C[5] * g[1], C[2] * g[2]};
+#pragma unroll
+        for (int f = 0; f < 9; ++f) {
+            const int al = f / 3, be = f % 3;
+            const int v3 = 2 * (al == 2) + (be == 2);
+            const T* cw = cz + 2 * RT + v3 * RO;
+#pragma unroll
+            for (int s = 0; s < RO; ++s) acc[f][s] += cw[s] * psi[f];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < RO; ++s) {
+        T vals[9];
+#pragma unroll
+        for (int f = 0; f < 9; ++f) vals[f] = acc[f][s];
+        flush(obase + s, vals);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = T(0);
+}
+
+template <typename T, int P>
+hipError_t launch_p(const FusedArgs<T>& a, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(nblk), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
+    const size_t N = (size_t)a.n1 * a.n2 * a.n3;
+    size_t g = (N + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
+    const int nblk = a.ntx * a.nty * nzc;
+    switch (p) {
+        case 2: return launch_p<T, 2>(a, nblk, s);
+        case 3: return launch_p<T, 3>(a, nblk, s);
+        case 4: return launch_p<T, 4>(a, nblk, s);
+        case 5: return launch_p<T, 5>(a, nblk, s);
+        case 6: return launch_p<T, 6>(a, nblk, s);
+        case 7: return launch_p<T, 7>(a, nblk, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_fused_apply<double>(const FusedArgs<double>&, int, hipStream_t);
+template hipError_t launch_fused_apply<float>(const FusedArgs<float>&, int, hipStream_t);
+
+}  // namespace wqfd

@@ -306,6 +306,10 @@ def _mk() -> Dict[str, Workload]:
         w[f"ring8_p{p}"] = Workload(f"ring8_p{p}", 8, p, "ring", 0.02, "identity", "paper")
     w["ring7_p4_kappa"] = Workload("ring7_p4_kappa", 7, 4, "ring", 0.02, "scalar", "paper")
     w["twist6_p6"] = Workload("twist6_p6", 6, 6, "twist", 0.0, "sym6", "smooth")
+    w["twist5_p4"] = Workload("twist5_p4", 5, 4, "twist", 0.0, "sym6", "smooth")
+    w["ring6_p8"] = Workload("ring6_p8", 6, 8, "ring", 0.02, "identity", "paper")
+    # several 16-point tiles per direction and a ragged last tile (n_q = 53)
+    w["ring20_p6"] = Workload("ring20_p6", 20, 6, "ring", 0.02, "identity", "paper")
     w["shear6_p3"] = Workload("shear6_p3", 6, 3, "shear", 0.0, "identity", "sine")
     w["cube5_p2"] = Workload("cube5_p2", 5, 2, "identity")
     return w
