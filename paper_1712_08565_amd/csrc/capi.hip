@@ -522,11 +522,11 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
         const size_t n = f.n[l];
         const size_t np = (n + 63) / 64 * 64;
         o_u64[l] = off;
-        off += al256(n * n * 8);
+        off += 2 * al256(n * n * 8);
         o_lam[l] = off;
         off += al256(n * 8);
         o_u32[l] = off;
-        if (prec_mask & WQ_F32) off += al256(n * n * 4);
+        if (prec_mask & WQ_F32) off += 2 * al256(n * n * 4);
         o_ubf[l] = off;
         if (prec_mask & WQ_BF16) off += al256(2 * np * np * 2);
     }
@@ -541,14 +541,21 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
         const int n = f.n[l];
         rc = wqfd::gen_eig(n, sp[l].Ki, sp[l].Mi, f.hlam[l], f.hU[l], err);
         if (rc) return fail(rc, err);
+        std::vector<double> ut((size_t)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) ut[(size_t)i * n + j] = f.hU[l][(size_t)j * n + i];
         f.U64[l] = reinterpret_cast<double*>(base + o_u64[l]);
+        f.UT64[l] = reinterpret_cast<double*>(base + o_u64[l] + al256((size_t)n * n * 8));
         f.lam[l] = reinterpret_cast<double*>(base + o_lam[l]);
         HIP_TRY(hipMemcpy(f.U64[l], f.hU[l].data(), (size_t)n * n * 8, hipMemcpyHostToDevice), "upload U");
+        HIP_TRY(hipMemcpy(f.UT64[l], ut.data(), (size_t)n * n * 8, hipMemcpyHostToDevice), "upload U^T");
         HIP_TRY(hipMemcpy(f.lam[l], f.hlam[l].data(), (size_t)n * 8, hipMemcpyHostToDevice), "upload lam");
         if (prec_mask & WQ_F32) {
-            std::vector<float> u32(f.hU[l].begin(), f.hU[l].end());
+            std::vector<float> u32(f.hU[l].begin(), f.hU[l].end()), ut32(ut.begin(), ut.end());
             f.U32[l] = reinterpret_cast<float*>(base + o_u32[l]);
+            f.UT32[l] = reinterpret_cast<float*>(base + o_u32[l] + al256((size_t)n * n * 4));
             HIP_TRY(hipMemcpy(f.U32[l], u32.data(), (size_t)n * n * 4, hipMemcpyHostToDevice), "upload U32");
+            HIP_TRY(hipMemcpy(f.UT32[l], ut32.data(), (size_t)n * n * 4, hipMemcpyHostToDevice), "upload U32^T");
         }
         if (prec_mask & WQ_BF16) {
             const int np = (n + 63) / 64 * 64;

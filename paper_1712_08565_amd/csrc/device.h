@@ -65,7 +65,9 @@ struct FdPc {
     size_t N = 0;
     int prec_mask = 0;
     double* U64[3] = {nullptr, nullptr, nullptr};   // row-major n x n (eigenvector k = column k)
+    double* UT64[3] = {nullptr, nullptr, nullptr};  // transposes, row-major
     float* U32[3] = {nullptr, nullptr, nullptr};
+    float* UT32[3] = {nullptr, nullptr, nullptr};
     uint16_t* Ubf[3] = {nullptr, nullptr, nullptr};  // bf16 copies (raw bits)
     float* Ubf_padded = nullptr;
     double* lam[3] = {nullptr, nullptr, nullptr};    // eigenvalues (device)

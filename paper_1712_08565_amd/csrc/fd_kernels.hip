@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "fd_gemm.h"
 
 namespace wqfd {
 
@@ -300,9 +301,84 @@ hipError_t fd_apply_bf16(const FdPc& P, const float* r, float* z, hipStream_t s)
     return hipGetLastError();
 }
 
+// Six LDS-tiled mode products (fd_gemm.hip): x, y, z forward with U^T (scaling
+// fused into z), then x, y, z backward with U.  Ping-pongs between z and the
+// preconditioner's scratch buffer, so r and z may alias.
+template <typename T, typename S>
+hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], const S* const Tb[3],
+                         const int ld[3], hipStream_t s) {
+    const int n1 = P.n[0], n2 = P.n[1], n3 = P.n[2];
+    T* tmp = reinterpret_cast<T*>(P.scratch);
+    auto mode = [&](int axis, const T* in, T* out, const S* mat, bool scale) {
+        FdModeArgs<T, S> a;
+        a.in = in;
+        a.out = out;
+        a.mat = mat;
+        a.ldT = ld[axis];
+        int batches = 1;
+        if (axis == 0) {
+            a.n = n1;
+            a.C = n2 * n3;
+            a.sj = 1;
+            a.sc = (size_t)n1;
+        } else if (axis == 1) {
+            a.n = n2;
+            a.C = n1;
+            a.sj = (size_t)n1;
+            a.sc = 1;
+            a.sa = (size_t)n1 * n2;
+            batches = n3;
+        } else {
+            a.n = n3;
+            a.C = n1 * n2;
+            a.sj = (size_t)n1 * n2;
+            a.sc = 1;
+        }
+        if (scale) {
+            a.l1 = P.lam[0];
+            a.l2 = P.lam[1];
+            a.l3 = P.lam[2];
+            a.n1 = n1;
+        }
+        return launch_fd_mode(a, batches, s);
+    };
+    hipError_t e;
+    if ((e = mode(0, r, tmp, Tf[0], false)) != hipSuccess) return e;
+    if ((e = mode(1, tmp, z, Tf[1], false)) != hipSuccess) return e;
+    if ((e = mode(2, z, tmp, Tf[2], true)) != hipSuccess) return e;
+    if ((e = mode(0, tmp, z, Tb[0], false)) != hipSuccess) return e;
+    if ((e = mode(1, z, tmp, Tb[1], false)) != hipSuccess) return e;
+    return mode(2, tmp, z, Tb[2], false);
+}
+
 }  // namespace
 
 hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s) {
+    const bool small = P.n[0] <= 144 && P.n[1] <= 144 && P.n[2] <= 144;
+    if (small) {
+        if (prec == 1) {
+            const double* Tf[3] = {P.UT64[0], P.UT64[1], P.UT64[2]};
+            const double* Tb[3] = {P.U64[0], P.U64[1], P.U64[2]};
+            const int ld[3] = {P.n[0], P.n[1], P.n[2]};
+            return fd_apply_gemm<double, double>(P, static_cast<const double*>(r), static_cast<double*>(z), Tf, Tb,
+                                                 ld, s);
+        }
+        if (prec == 2) {
+            const float* Tf[3] = {P.UT32[0], P.UT32[1], P.UT32[2]};
+            const float* Tb[3] = {P.U32[0], P.U32[1], P.U32[2]};
+            const int ld[3] = {P.n[0], P.n[1], P.n[2]};
+            return fd_apply_gemm<float, float>(P, static_cast<const float*>(r), static_cast<float*>(z), Tf, Tb, ld,
+                                               s);
+        }
+        const __bf16 *Tf[3], *Tb[3];
+        int ld[3];
+        for (int l = 0; l < 3; ++l) {
+            ld[l] = (P.n[l] + 63) / 64 * 64;
+            Tf[l] = reinterpret_cast<const __bf16*>(P.Ubf[l]);
+            Tb[l] = Tf[l] + (size_t)ld[l] * ld[l];
+        }
+        return fd_apply_gemm<float, __bf16>(P, static_cast<const float*>(r), static_cast<float*>(z), Tf, Tb, ld, s);
+    }
     if (prec == 1) return fd_apply_t<1>(P, static_cast<const double*>(r), static_cast<double*>(z), s);
     if (prec == 2) return fd_apply_t<2>(P, static_cast<const float*>(r), static_cast<float*>(z), s);
     return fd_apply_bf16(P, static_cast<const float*>(r), static_cast<float*>(z), s);

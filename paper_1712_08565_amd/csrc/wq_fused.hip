@@ -65,14 +65,20 @@ __device__ inline typename MF<T>::acc gemm16(const T* At, const T* Bt, typename 
     return c;
 }
 
+// Workgroup barrier that waits only for this wave's LDS operations: global loads
+// already in flight (coefficient planes, the next DOF plane) stay in flight
+// across it, unlike __syncthreads(), whose release fence drains them.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <typename T>
 __device__ inline void store16(T* tile, const typename MF<T>::acc& c, int cl, int kb) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) tile[MF<T>::drow(kb, v) * LD + cl] = c[v];
 }
 
+// two waves per SIMD (at most 256 registers per lane); a few spills at p >= 6 in FP64
 template <typename T, int P>
-__global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
+__global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) {
     constexpr int RT = P + 1;              // trial window (DOF planes)
     constexpr int RO = P + 2;              // test window (output planes)
     constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
@@ -114,21 +120,22 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
         sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
     }
 
-    // trial contraction of DOF plane j3 onto the tile's columns
-    auto trial_plane = [&](int j3, T& ux, T& uy, T& u0) {
-        {
-            const int j1 = J1 + q1l, j2 = J2 + q2l;
-            T val = T(0);
-            if (j3 < a.n3 && j1 < a.n1 && j2 < a.n2) val = a.v[((size_t)j3 * a.n2 + j2) * a.n1 + j1];
-            sT[0][q2l * LD + q1l] = val;                       // V[j2][j1]
-        }
-        __syncthreads();
+    // this thread's entry V[j2][j1] of DOF plane j3 (zero outside the mesh)
+    const int vj1 = J1 + q1l, vj2 = J2 + q2l;
+    const bool vin = vj1 < a.n1 && vj2 < a.n2;
+    auto load_v = [&](int j3) -> T {
+        return (vin && j3 < a.n3) ? a.v[((size_t)j3 * a.n2 + vj2) * a.n1 + vj1] : T(0);
+    };
+    // trial contraction of a DOF plane (this thread's entry: val) onto the tile's columns
+    auto trial_plane = [&](T val, T& ux, T& uy, T& u0) {
+        sT[0][q2l * LD + q1l] = val;                           // V[j2][j1]
+        lds_barrier();
         if (wave < 2) {                                        // A_d[j2][q1] = sum_j1 V[j2][j1] B1_d[q1][j1]
             acc_t c = {0, 0, 0, 0};
             c = gemm16<T, true>(sT[0], sCoef[wave], c, cl, kb);
             store16<T>(sT[1 + wave], c, cl, kb);
         }
-        __syncthreads();
+        lds_barrier();
         if (wave < 3) {                                        // U[q2][q1] = sum_j2 B2_d[q2][j2] A[j2][q1]
             const T* At = sCoef[2 + (wave == 1 ? 1 : 0)];      // U_y uses B-dot2
             const T* Bt = sT[wave == 0 ? 2 : 1];               // U_x uses A_1 (B-dot1)
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
             c = gemm16<T, false>(At, Bt, c, cl, kb);
             store16<T>(sT[3 + wave], c, cl, kb);
         }
-        __syncthreads();
+        lds_barrier();
         ux = sT[3][q2l * LD + q1l];
         uy = sT[4][q2l * LD + q1l];
         u0 = sT[5][q2l * LD + q1l];
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
         if (i3 < 0 || i3 >= a.n3) return;                      // uniform across the workgroup
 #pragma unroll
         for (int f = 0; f < 9; ++f) sP[f][q2l * LD + q1l] = vals[f];
-        __syncthreads();
+        lds_barrier();
         for (int f = wave; f < 9; f += 4) {                    // Y_f[i2][q1] = sum_q2 W2[i2][q2] psi_f[q2][q1]
             const int al = f / 3, be = f % 3;
             const int v2 = 2 * (al == 1) + (be == 1);
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
             c = gemm16<T, false>(sCoef[8 + v2], sP[f], c, cl, kb);
             store16<T>(sY[f], c, cl, kb);
         }
-        __syncthreads();
+        lds_barrier();
         acc_t z = {0, 0, 0, 0};
         for (int f = wave; f < 9; f += 4) {                    // Z[i2][i1] += sum_q1 Y_f[i2][q1] W1[i1][q1]
             const int al = f / 3, be = f % 3;
@@ -163,13 +170,13 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
             z = gemm16<T, true>(sY[f], sCoef[4 + v1], z, cl, kb);
         }
         store16<T>(sP[wave], z, cl, kb);
-        __syncthreads();
+        lds_barrier();
         {
             const T s = sP[0][q2l * LD + q1l] + sP[1][q2l * LD + q1l] + sP[2][q2l * LD + q1l] + sP[3][q2l * LD + q1l];
             const int i1 = I1 + q1l, i2 = I2 + q2l;
             if (i1 < a.n1 && i2 < a.n2 && s != T(0)) atomicAdd(&a.w[((size_t)i3 * a.n2 + i2) * a.n1 + i1], s);
         }
-        __syncthreads();
+        lds_barrier();
     };
 
     T Ux[RT], Uy[RT], U0[RT];
@@ -181,13 +188,19 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
 
     int tbase = a.bs3[k0];
     int obase = a.wts3[k0];
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
-    for (int s = 0; s < RT; ++s) trial_plane(tbase + s, Ux[s], Uy[s], U0[s]);
+    for (int s = 0; s < RT; ++s) trial_plane(load_v(tbase + s), Ux[s], Uy[s], U0[s]);
+    T vnext = load_v(tbase + RT);                              // next plane to enter the window
 
     const size_t Nq = a.Nq;
     const size_t col = (size_t)q2 * a.nq1 + q1;
     for (int k = k0; k < k1; ++k) {
+        // coefficient loads first: their latency overlaps the window updates below
+        T C[6];
+        const size_t q = (size_t)k * a.nq1 * a.nq2 + col;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) C[c] = active ? a.C[c * Nq + q] : T(0);
         const int bk = a.bs3[k], wk = a.wts3[k];
         while (tbase < bk) {                                   // slide the trial window
 #pragma unroll
@@ -196,7 +209,9 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
                 Uy[s] = Uy[s + 1];
                 U0[s] = U0[s + 1];
             }
-            trial_plane(tbase + RT, Ux[RT - 1], Uy[RT - 1], U0[RT - 1]);
+            const T vcur = vnext;
+            vnext = load_v(tbase + RT + 1);                    // issue the following load early
+            trial_plane(vcur, Ux[RT - 1], Uy[RT - 1], U0[RT - 1]);
             ++tbase;
         }
         while (obase < wk) {                                   // retire the oldest output plane
@@ -220,10 +235,6 @@ __global__ __launch_bounds__(256) void wq_apply_fused_kernel(FusedArgs<T> a) {
             g[1] += cz[s] * Uy[s];
             g[2] += cz[RT + s] * U0[s];
         }
-        T C[6];
-        const size_t q = (size_t)k * a.nq1 * a.nq2 + col;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) C[c] = active ? a.C[c * Nq + q] : T(0);
         // psi_ab = C_ab g_b, plane order (C11, C22, C33, C12, C13, C23)
         const T psi[9] = {C[0] * g[0], C[3] * g[1], C[4] * g[2],
                           C[3] * g[0], C[1] * g[1], C[5] * g[2],
