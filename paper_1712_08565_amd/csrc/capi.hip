@@ -231,6 +231,7 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
     int nzc = (1024 + tiles - 1) / tiles;
     nzc = std::max(1, std::min(nzc, nq3 / (3 * (p + 2))));
     if (const char* e = std::getenv("WQFD_ZCHUNKS")) nzc = std::max(1, std::min(nq3, std::atoi(e)));
+    nzc = std::max(nzc, (nq3 + 63) / 64);                // the kernel stages at most 64 planes
     fh.zchunk = (nq3 + nzc - 1) / nzc;
     return true;
 }

@@ -36,6 +36,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
 constexpr int BLK = 16 * LD;
+constexpr int kMaxZ = 64;         // longest z range of one workgroup (host caps zchunk)
 
 template <typename T>
 struct MF;
@@ -76,21 +77,27 @@ __device__ inline void store16(T* tile, const typename MF<T>::acc& c, int cl, in
     for (int v = 0; v < 4; ++v) tile[MF<T>::drow(kb, v) * LD + cl] = c[v];
 }
 
-// two waves per SIMD (at most 256 registers per lane); a few spills at p >= 6 in FP64
+// 512 threads: two per quadrature column.  Threads 0..255 (waves 0-3) carry
+// the test fields f = 3 alpha + beta = 0..4, threads 256..511 (waves 4-7) the
+// fields 5..8, which halves the per-thread register windows; the x/y work of a
+// retired output plane is spread over all eight waves.
 template <typename T, int P>
-__global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) {
+__global__ __launch_bounds__(512, 1) void wq_apply_fused_kernel(FusedArgs<T> a) {
     constexpr int RT = P + 1;              // trial window (DOF planes)
     constexpr int RO = P + 2;              // test window (output planes)
     constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
     __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
     __shared__ T sT[6][BLK];               // V, A_0, A_1, U_x, U_y, U_0
-    __shared__ T sP[9][BLK];               // psi_f, then per-wave partial sums
-    __shared__ T sY[9][BLK];               // y-contracted fields
+    __shared__ T sP[9][BLK];               // psi_f of the plane being retired
+    __shared__ T sR[8][BLK];               // per-wave partial output blocks
+    __shared__ T sZ[kMaxZ * CZ];            // z coefficients of this workgroup's planes
+    __shared__ int sB3[kMaxZ], sW3[kMaxZ];  // z window starts of these planes
 
     using acc_t = typename MF<T>::acc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int half = tid >> 8, ct = tid & 255;
     const int cl = lane & 15, kb = lane >> 4;
-    const int q1l = tid & 15, q2l = tid >> 4;
+    const int q1l = ct & 15, q2l = ct >> 4;
 
     // workgroup -> (t1, t2, zc); consecutive blocks are dealt round-robin to the
     // eight XCDs, so hand each XCD a contiguous run of neighbouring tiles
@@ -110,7 +117,7 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
     const int J1 = a.JX[t1], I1 = a.IX[t1], J2 = a.JY[t2], I2 = a.IY[t2];
 
     // coefficient blocks of this tile
-    for (int idx = tid; idx < 12 * 256; idx += 256) {
+    for (int idx = tid; idx < 12 * 256; idx += 512) {
         const int tl = idx >> 8, e = idx & 255;
         const T* src;
         if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
@@ -120,15 +127,24 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
         sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
     }
 
-    // this thread's entry V[j2][j1] of DOF plane j3 (zero outside the mesh)
+    // z coefficients and window starts of planes k0..k1-1, staged once: per-plane
+    // scalar loads would miss the scalar cache and stall every LDS wait
+    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 512) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
+    for (int idx = tid; idx < k1 - k0; idx += 512) {
+        sB3[idx] = a.bs3[k0 + idx];
+        sW3[idx] = a.wts3[k0 + idx];
+    }
+
+    // this thread's entry V[j2][j1] of DOF plane j3 (zero outside the mesh;
+    // only the first half of the workgroup stages V)
     const int vj1 = J1 + q1l, vj2 = J2 + q2l;
-    const bool vin = vj1 < a.n1 && vj2 < a.n2;
+    const bool vin = half == 0 && vj1 < a.n1 && vj2 < a.n2;
     auto load_v = [&](int j3) -> T {
         return (vin && j3 < a.n3) ? a.v[((size_t)j3 * a.n2 + vj2) * a.n1 + vj1] : T(0);
     };
-    // trial contraction of a DOF plane (this thread's entry: val) onto the tile's columns
+    // trial contraction of a DOF plane onto the tile's columns
     auto trial_plane = [&](T val, T& ux, T& uy, T& u0) {
-        sT[0][q2l * LD + q1l] = val;                           // V[j2][j1]
+        if (half == 0) sT[0][q2l * LD + q1l] = val;           // V[j2][j1]
         lds_barrier();
         if (wave < 2) {                                        // A_d[j2][q1] = sum_j1 V[j2][j1] B1_d[q1][j1]
             acc_t c = {0, 0, 0, 0};
@@ -136,12 +152,13 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
             store16<T>(sT[1 + wave], c, cl, kb);
         }
         lds_barrier();
-        if (wave < 3) {                                        // U[q2][q1] = sum_j2 B2_d[q2][j2] A[j2][q1]
-            const T* At = sCoef[2 + (wave == 1 ? 1 : 0)];      // U_y uses B-dot2
-            const T* Bt = sT[wave == 0 ? 2 : 1];               // U_x uses A_1 (B-dot1)
+        if (wave >= 2 && wave < 5) {                           // U[q2][q1] = sum_j2 B2_d[q2][j2] A[j2][q1]
+            const int u = wave - 2;                            // 0: U_x, 1: U_y, 2: U_0
+            const T* At = sCoef[2 + (u == 1 ? 1 : 0)];         // U_y uses B-dot2
+            const T* Bt = sT[u == 0 ? 2 : 1];                  // U_x uses A_1 (B-dot1)
             acc_t c = {0, 0, 0, 0};
             c = gemm16<T, false>(At, Bt, c, cl, kb);
-            store16<T>(sT[3 + wave], c, cl, kb);
+            store16<T>(sT[3 + u], c, cl, kb);
         }
         lds_barrier();
         ux = sT[3][q2l * LD + q1l];
@@ -149,30 +166,47 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
         u0 = sT[5][q2l * LD + q1l];
     };
 
-    // x/y test contraction of output plane i3 and atomic update of w
+    // x/y test contraction of output plane i3 and atomic update of w.  A field
+    // is contracted in x first (X = psi_f W1^T) and the y product takes X
+    // straight from the accumulator registers as its B operand (the K index of
+    // step s held by lane group kb is the accumulator row drow(kb, s), so W2 is
+    // read with the same row mapping).  Waves 0-5 take one field each
+    // (xx, xz, zx, zz, xy, zy), wave 6 the pair {yx, yz} sharing W2^2, wave 7 yy.
+    auto xpart = [&](acc_t& X, int f) {
+        const int al = f / 3, be = f % 3;
+        const int v1 = 2 * (al == 0) + (be == 0);
+        X = gemm16<T, true>(sP[f], sCoef[4 + v1], X, cl, kb);
+    };
+    auto ypart = [&](acc_t& Z, const acc_t& X, int v2) {
+        const T* A = sCoef[8 + v2];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Z = MF<T>::mma(A[cl * LD + MF<T>::drow(kb, s)], X[s], Z);
+    };
     auto flush = [&](int i3, const T* vals) {
         if (i3 < 0 || i3 >= a.n3) return;                      // uniform across the workgroup
+        if (half == 0) {
 #pragma unroll
-        for (int f = 0; f < 9; ++f) sP[f][q2l * LD + q1l] = vals[f];
-        lds_barrier();
-        for (int f = wave; f < 9; f += 4) {                    // Y_f[i2][q1] = sum_q2 W2[i2][q2] psi_f[q2][q1]
-            const int al = f / 3, be = f % 3;
-            const int v2 = 2 * (al == 1) + (be == 1);
-            acc_t c = {0, 0, 0, 0};
-            c = gemm16<T, false>(sCoef[8 + v2], sP[f], c, cl, kb);
-            store16<T>(sY[f], c, cl, kb);
+            for (int f = 0; f < 5; ++f) sP[f][q2l * LD + q1l] = vals[f];
+        } else {
+#pragma unroll
+            for (int f = 0; f < 4; ++f) sP[5 + f][q2l * LD + q1l] = vals[f];
         }
-        lds_barrier();
-        acc_t z = {0, 0, 0, 0};
-        for (int f = wave; f < 9; f += 4) {                    // Z[i2][i1] += sum_q1 Y_f[i2][q1] W1[i1][q1]
-            const int al = f / 3, be = f % 3;
-            const int v1 = 2 * (al == 0) + (be == 0);
-            z = gemm16<T, true>(sY[f], sCoef[4 + v1], z, cl, kb);
-        }
-        store16<T>(sP[wave], z, cl, kb);
         lds_barrier();
         {
-            const T s = sP[0][q2l * LD + q1l] + sP[1][q2l * LD + q1l] + sP[2][q2l * LD + q1l] + sP[3][q2l * LD + q1l];
+            // (field, y variant) per wave; wave 6 adds a second field
+            constexpr int fw[8] = {0, 2, 6, 8, 1, 7, 3, 4};
+            constexpr int vw[8] = {0, 0, 0, 0, 1, 1, 2, 3};
+            acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
+            xpart(X, fw[wave]);
+            if (wave == 6) xpart(X, 5);
+            ypart(Z, X, vw[wave]);
+            store16<T>(sR[wave], Z, cl, kb);
+        }
+        lds_barrier();
+        if (half == 0) {
+            T s = T(0);
+#pragma unroll
+            for (int w = 0; w < 8; ++w) s += sR[w][q2l * LD + q1l];
             const int i1 = I1 + q1l, i2 = I2 + q2l;
             if (i1 < a.n1 && i2 < a.n2 && s != T(0)) atomicAdd(&a.w[((size_t)i3 * a.n2 + i2) * a.n1 + i1], s);
         }
@@ -180,28 +214,40 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
     };
 
     T Ux[RT], Uy[RT], U0[RT];
-    T acc[9][RO];
+    T acc[5][RO];                                              // half 0: fields 0..4, half 1: 5..8
 #pragma unroll
-    for (int f = 0; f < 9; ++f)
+    for (int f = 0; f < 5; ++f)
 #pragma unroll
         for (int s = 0; s < RO; ++s) acc[f][s] = T(0);
 
-    int tbase = a.bs3[k0];
-    int obase = a.wts3[k0];
     lds_barrier();
+    int tbase = sB3[0];
+    int obase = sW3[0];
 #pragma unroll
     for (int s = 0; s < RT; ++s) trial_plane(load_v(tbase + s), Ux[s], Uy[s], U0[s]);
     T vnext = load_v(tbase + RT);                              // next plane to enter the window
 
+    // coefficient planes this half needs: half 0 (C11, C22, C12, C13), half 1 (C33, C13, C23)
     const size_t Nq = a.Nq;
     const size_t col = (size_t)q2 * a.nq1 + q1;
-    for (int k = k0; k < k1; ++k) {
-        // coefficient loads first: their latency overlaps the window updates below
-        T C[6];
-        const size_t q = (size_t)k * a.nq1 * a.nq2 + col;
+    const size_t plane = (size_t)a.nq1 * a.nq2;
+    const int cpl[4] = {half == 0 ? 0 : 2, half == 0 ? 1 : 4, half == 0 ? 3 : 5, 4};
+    const int ncp = half == 0 ? 4 : 3;
+    T Cn[4];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) C[c] = active ? a.C[c * Nq + q] : T(0);
-        const int bk = a.bs3[k], wk = a.wts3[k];
+    for (int c = 0; c < 4; ++c)
+        Cn[c] = (active && c < ncp) ? a.C[cpl[c] * Nq + (size_t)k0 * plane + col] : T(0);
+    for (int k = k0; k < k1; ++k) {
+        // plane k's coefficients were loaded one plane ahead; issue plane k+1's now
+        T C[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) C[c] = Cn[c];
+        if (k + 1 < k1) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                Cn[c] = (active && c < ncp) ? a.C[cpl[c] * Nq + (size_t)(k + 1) * plane + col] : T(0);
+        }
+        const int bk = sB3[k - k0], wk = sW3[k - k0];
         while (tbase < bk) {                                   // slide the trial window
 #pragma unroll
             for (int s = 0; s < RT - 1; ++s) {
@@ -215,19 +261,19 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
             ++tbase;
         }
         while (obase < wk) {                                   // retire the oldest output plane
-            T vals[9];
+            T vals[5];
 #pragma unroll
-            for (int f = 0; f < 9; ++f) vals[f] = acc[f][0];
+            for (int f = 0; f < 5; ++f) vals[f] = acc[f][0];
             flush(obase, vals);
 #pragma unroll
-            for (int f = 0; f < 9; ++f) {
+            for (int f = 0; f < 5; ++f) {
 #pragma unroll
                 for (int s = 0; s < RO - 1; ++s) acc[f][s] = acc[f][s + 1];
                 acc[f][RO - 1] = T(0);
             }
             ++obase;
         }
-        const T* cz = a.cz + (size_t)k * CZ;
+        const T* cz = sZ + (size_t)(k - k0) * CZ;
         T g[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
@@ -235,24 +281,35 @@ __global__ __launch_bounds__(256, 2) void wq_apply_fused_kernel(FusedArgs<T> a) 
             g[1] += cz[s] * Uy[s];
             g[2] += cz[RT + s] * U0[s];
         }
-        // psi_ab = C_ab g_b, plane order (C11, C22, C33, C12, C13, C23)
-        const T psi[9] = {C[0] * g[0], C[3] * g[1], C[4] * g[2],
-                          C[3] * g[0], C[1] * g[1], C[5] * g[2],
-                          C[4] * g[0], C[5] * g[1], C[2] * g[2]};
+        // psi_ab = C_ab g_b; the z weight variant of field (alpha, beta) is
+        // 2 [alpha = z] + [beta = z]
+        T psi[5];
+        int v3[5];
+        if (half == 0) {        // xx, xy, xz, yx, yy with C = (C11, C22, C12, C13)
+            psi[0] = C[0] * g[0]; v3[0] = 0;
+            psi[1] = C[2] * g[1]; v3[1] = 0;
+            psi[2] = C[3] * g[2]; v3[2] = 1;
+            psi[3] = C[2] * g[0]; v3[3] = 0;
+            psi[4] = C[1] * g[1]; v3[4] = 0;
+        } else {                // yz, zx, zy, zz with C = (C33, C13, C23)
+            psi[0] = C[2] * g[2]; v3[0] = 1;
+            psi[1] = C[1] * g[0]; v3[1] = 2;
+            psi[2] = C[2] * g[1]; v3[2] = 2;
+            psi[3] = C[0] * g[2]; v3[3] = 3;
+            psi[4] = T(0);        v3[4] = 0;
+        }
 #pragma unroll
-        for (int f = 0; f < 9; ++f) {
-            const int al = f / 3, be = f % 3;
-            const int v3 = 2 * (al == 2) + (be == 2);
-            const T* cw = cz + 2 * RT + v3 * RO;
+        for (int f = 0; f < 5; ++f) {
+            const T* cw = cz + 2 * RT + v3[f] * RO;
 #pragma unroll
             for (int s = 0; s < RO; ++s) acc[f][s] += cw[s] * psi[f];
         }
     }
 #pragma unroll
     for (int s = 0; s < RO; ++s) {
-        T vals[9];
+        T vals[5];
 #pragma unroll
-        for (int f = 0; f < 9; ++f) vals[f] = acc[f][s];
+        for (int f = 0; f < 5; ++f) vals[f] = acc[f][s];
         flush(obase + s, vals);
     }
 }
@@ -264,7 +321,7 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) 
 
 template <typename T, int P>
 hipError_t launch_p(const FusedArgs<T>& a, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(nblk), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(nblk), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
