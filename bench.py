@@ -16,12 +16,21 @@ Set-up (splines, weights, geometry, FD eigenpairs) is outside the timed region.
 value   = FP64 apply throughput, sum_p N_p * applies / sum of apply times (GDOF/s)
 roofline: algorithmic bytes of one FP64 apply = 48 N_q + 16 N (six coefficient
           planes read once, v read and w written once) over the average apply time.
+          traffic: DRAM-side bytes per launch from the committed counter summary
+          in profiles/ (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size),
+          reported only while the kernel source still matches the hash recorded
+          there.
+Equal accuracy: besides the runs to relative residual 1e-10, each degree is also
+solved at the loosest residual tolerance whose solution is within 1e-10
+(relative 2-norm) of a tight reference solve (FP64, residual 1e-13), for both
+the FP64 and the mixed solver; those times are the like-for-like comparison.
 cpu_baseline: the CPU FP64 oracle's matrix-free apply on a bounded sample
           (degree 3 of the same workload), timed on this host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -33,6 +42,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "WQ apply GDOF/s & time-to-solve to rel.res 1e-10, FP64 vs mixed, p=2..6"
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wq_apply_fused_f64_ring64_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_08565_amd", "csrc", f) for f in ("wq_fused.hip", "fused.h")]
+EQ_TOL = 1e-10
+RTOL_LADDER = [1e-10, 3e-11, 1e-11, 3e-12, 1e-12, 3e-13, 1e-13]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def committed_traffic(degrees):
+    """Mean DRAM-side bytes per FP64 apply over ``degrees`` from the counter
+    summary, or None if it is missing, stale (kernel source changed) or lacks a
+    degree."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    sha, per_p = None, {}
+    for ln in lines:
+        if ln.startswith("# kernel sha256:"):
+            sha = ln.split(":", 1)[1].strip()
+        elif ln.startswith("p=") and "traffic_bytes=" in ln:
+            kv = dict(t.split("=", 1) for t in ln.split())
+            per_p[int(kv["p"])] = float(kv["traffic_bytes"])
+    if sha != kernel_hash() or any(p not in per_p for p in degrees):
+        return None
+    return sum(per_p[p] for p in degrees) / len(degrees)
 
 
 def log(msg):
@@ -81,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-solve", action="store_true", help="time the applies only")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB per step (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU (z-slab) decomposition is a design note, "
@@ -94,6 +139,19 @@ def main():
     from paper_1712_08565_amd import problem, wqfd
 
     torch.cuda.set_device(0)
+
+    def solve(P, kind, rtol, x=None):
+        dp = P["dp"]
+        x = torch.zeros_like(P["v"]) if x is None else x.zero_()
+        if kind == "fp64":
+            _, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, x=x, rtol=rtol, maxit=2000, ws=P["kws"])
+            P["last"] = (it, 0, res)
+        else:
+            _, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, x=x, fd_prec=wqfd.WQ_BF16, rtol=rtol,
+                                                 tau_inner=1e-3, ws=P["iws"])
+            P["last"] = (outer, inner, res)
+        return x
+
     degrees = [int(x) for x in args.degrees.split(",")]
     probs = {}
     for p in degrees:
@@ -106,16 +164,38 @@ def main():
         kws = torch.empty(wqfd.lib().krylov_ws_bytes(dp.A.handle), dtype=torch.uint8, device="cuda")
         iws = torch.empty(wqfd.lib().ir_ws_bytes(dp.A.handle), dtype=torch.uint8, device="cuda")
         # reference solution for the equal-accuracy comparison (outside the timed region)
-        xref, it_ref, res_ref = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-13, maxit=2000, ws=kws,
-                                                  raise_on_noconv=False)
+        xref, it_ref, res_ref = None, 0, float("nan")
+        if not args.no_solve:
+            xref, it_ref, res_ref = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-13, maxit=2000, ws=kws,
+                                                      raise_on_noconv=False)
         probs[p] = dict(dp=dp, v=v, w=w, kws=kws, iws=iws, xref=xref, x=torch.zeros_like(v),
                         N=dp.A.N, Nq=dp.A.Nq, setup_s=time.perf_counter() - t0)
+        if not args.no_solve:
+            nref = torch.linalg.norm(xref).item()
+            P = probs[p]
+            for kind in ("fp64", "mixed"):
+                P[f"{kind}_eq_rtol"] = None
+                for rt in RTOL_LADDER:
+                    try:
+                        x = solve(P, kind, rt)
+                    except RuntimeError as e:          # no convergence at this tolerance
+                        log(f"p={p} {kind} rtol {rt:.0e}: {e}")
+                        continue
+                    if torch.linalg.norm(x - xref).item() / nref <= EQ_TOL:
+                        P[f"{kind}_eq_rtol"] = rt
+                        break
         log(f"setup p={p}: N={dp.A.N} Nq={dp.A.Nq} {probs[p]['setup_s']:.1f}s (ref solve {it_ref} it, "
-            f"relres {res_ref:.1e})")
+            f"relres {res_ref:.1e}); equal-accuracy rtol fp64 {probs[p].get('fp64_eq_rtol')} "
+            f"mixed {probs[p].get('mixed_eq_rtol')}")
 
     stream = torch.cuda.current_stream()
     rec = {p: dict(apply_ms=[], fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
-                   mix_err=[]) for p in degrees}
+                   mix_err=[], fp64_eq_ms=[], fp64_eq_err=[], fp64_eq_it=[], mixed_eq_ms=[], mixed_eq_err=[],
+                   mixed_eq_it=[]) for p in degrees}
+    probe = None
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 8
+        probe = (torch.ones(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"))
 
     def one_step(record: bool):
         for p in degrees:
@@ -139,6 +219,19 @@ def main():
                 _, outer, inner, mres = wqfd.ir_solve(dp.A, dp.P, dp.b, x=xm, fd_prec=wqfd.WQ_BF16, rtol=1e-10,
                                                       tau_inner=1e-3, ws=P["iws"])
                 m1.record(stream)
+                eq = {}
+                for kind in ("fp64", "mixed"):
+                    rt = P[f"{kind}_eq_rtol"]
+                    if rt is None:
+                        continue
+                    q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    xq = torch.zeros_like(P["x"])
+                    q0.record(stream)
+                    solve(P, kind, rt, xq)
+                    q1.record(stream)
+                    eq[kind] = (q0, q1, xq, P["last"])
+            if probe is not None:
+                probe[1].copy_(probe[0])
             torch.cuda.synchronize()
             if record:
                 r = rec[p]
@@ -152,6 +245,10 @@ def main():
                     r["mix_outer"].append(outer)
                     r["mix_inner"].append(inner)
                     r["mix_err"].append(torch.linalg.norm(xm - P["xref"]).item() / nref)
+                    for kind, (q0, q1, xq, last) in eq.items():
+                        r[f"{kind}_eq_ms"].append(q0.elapsed_time(q1))
+                        r[f"{kind}_eq_err"].append(torch.linalg.norm(xq - P["xref"]).item() / nref)
+                        r[f"{kind}_eq_it"].append(last[0] if kind == "fp64" else last[1])
 
     for i in range(args.warmup):
         one_step(False)
@@ -169,6 +266,9 @@ def main():
     tot_bytes = sum((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) * len(rec[p]["apply_ms"]) for p in degrees)
     n_apply = sum(len(rec[p]["apply_ms"]) for p in degrees)
     achieved = tot_bytes / tot_s / 1e9
+    traffic = committed_traffic(degrees)
+    if traffic is not None:
+        traffic = round(traffic)
     per_p = {}
     for p in degrees:
         r = rec[p]
@@ -184,6 +284,12 @@ def main():
                       "mixed_solve_ms": round(float(np.median(r["mix_ms"])), 2),
                       "mixed_outer": int(np.median(r["mix_outer"])), "mixed_inner": int(np.median(r["mix_inner"])),
                       "mixed_rel_err_vs_tight": float(np.max(r["mix_err"]))})
+            for kind in ("fp64", "mixed"):
+                if r[f"{kind}_eq_ms"]:
+                    d[f"{kind}_equal_accuracy"] = {
+                        "rtol": probs[p][f"{kind}_eq_rtol"], "ms": round(float(np.median(r[f"{kind}_eq_ms"])), 2),
+                        "rel_err_vs_tight": float(np.max(r[f"{kind}_eq_err"])),
+                        "iters": int(np.median(r[f"{kind}_eq_it"]))}
         per_p[f"p{p}"] = d
     out = {
         "metric": METRIC,
@@ -202,7 +308,7 @@ def main():
                                f"FP64 apply + FP64 BiCGStab/FD and mixed FP32/BF16 IR solves to rel.res 1e-10",
                    "n_el": args.n_el, "degrees": degrees, "applies_per_degree_per_step": args.reps},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "wq_apply (FP64)", "launches": n_apply,
                      "bytes_per_launch": "48 N_q + 16 N"},
         "per_degree": per_p,

@@ -226,13 +226,13 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
                 if (i < n3) c[2 * RT + v * RO + s] = (*Wv[v])[(size_t)i * nq3 + k];
             }
     }
-    // z ranges: about 1024 workgroups, but no range shorter than 3 (p + 2) planes
-    const int tiles = fh.ntile[0] * fh.ntile[1];
-    int nzc = (1024 + tiles - 1) / tiles;
-    nzc = std::max(1, std::min(nzc, nq3 / (3 * (p + 2))));
-    if (const char* e = std::getenv("WQFD_ZCHUNKS")) nzc = std::max(1, std::min(nq3, std::atoi(e)));
-    nzc = std::max(nzc, (nq3 + 63) / 64);                // the kernel stages at most 64 planes
-    fh.zchunk = (nq3 + nzc - 1) / nzc;
+    // z range length: chosen at launch from the device's resident workgroups
+    // unless fixed here (WQFD_ZCHUNKS = number of ranges)
+    fh.zchunk = 0;
+    if (const char* e = std::getenv("WQFD_ZCHUNKS")) {
+        const int nzc = std::max((nq3 + 63) / 64, std::min(nq3, std::atoi(e)));
+        fh.zchunk = (nq3 + nzc - 1) / nzc;
+    }
     return true;
 }
 

@@ -33,7 +33,7 @@ struct G<1> {                    // FP64
     using T = double;            // data
     using S = double;            // staged operand
     using Acc = d4;
-    static constexpr int BK = 16, KS = 4;
+    static constexpr int BK = 16;
     __device__ static int drow(int kb, int v) { return kb + 4 * v; }
 };
 template <>
@@ -41,7 +41,7 @@ struct G<2> {                    // FP32
     using T = float;
     using S = float;
     using Acc = f4;
-    static constexpr int BK = 16, KS = 4;
+    static constexpr int BK = 16;
     __device__ static int drow(int kb, int v) { return 4 * kb + v; }
 };
 template <>
@@ -49,7 +49,7 @@ struct G<4> {                    // BF16 operands, FP32 data
     using T = float;
     using S = __bf16;
     using Acc = f4;
-    static constexpr int BK = 32, KS = 32;
+    static constexpr int BK = 32;
     __device__ static int drow(int kb, int v) { return 4 * kb + v; }
 };
 

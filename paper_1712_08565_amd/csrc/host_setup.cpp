@@ -313,7 +313,7 @@ int geometry_at_quad(const Space1D* sp, const double* ctrl, double* detJ, double
                      std::string& err, int nthreads) {
     const Space1D &S1 = sp[0], &S2 = sp[1], &S3 = sp[2];
     const int p = S1.p;
-    const int m1 = S1.m, m2 = S2.m, m3 = S3.m;
+    const int m1 = S1.m, m2 = S2.m;
     const int nq1 = S1.nq, nq2 = S2.nq, nq3 = S3.nq;
     const size_t Nq = (size_t)nq1 * nq2 * nq3;
     // non-zero basis values at the quadrature points, per direction

@@ -24,6 +24,9 @@
 // v_mfma_f32_16x16x4f32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+
 #include "device.h"
 #include "fused.h"
 
@@ -36,7 +39,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
 constexpr int BLK = 16 * LD;
-constexpr int kMaxZ = 64;         // longest z range of one workgroup (host caps zchunk)
+constexpr int kMaxZ = 64;         // longest z range of one workgroup (the launcher caps zchunk)
 
 template <typename T>
 struct MF;
@@ -319,9 +322,45 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) 
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = T(0);
 }
 
+// Length of the z range of one workgroup.  The grid is tiles x ranges
+// workgroups; each range also pays for the p + 2 halo planes at its two ends,
+// and the launch runs in ceil(workgroups / resident slots) rounds, so the
+// estimated time is rounds x (zchunk / 2 + p + 3) DOF-plane steps.  Ranges are
+// capped at kMaxZ quadrature planes (the kernel stages their z factors in LDS).
+int choose_zchunk(int nq3, int tiles, int slots, int p) {
+    int best = kMaxZ, best_cost = -1;
+    for (int nzc = (nq3 + kMaxZ - 1) / kMaxZ; nzc <= nq3; ++nzc) {
+        const int zc = (nq3 + nzc - 1) / nzc;
+        const long rounds = ((long)tiles * nzc + slots - 1) / slots;
+        const long cost = rounds * (zc + 2 * (p + 3));          // in half DOF-plane steps
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+        if (zc <= p + 2) break;
+    }
+    return best;
+}
+
 template <typename T, int P>
-hipError_t launch_p(const FusedArgs<T>& a, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(nblk), dim3(512), 0, s, a);
+hipError_t launch_p(FusedArgs<T> a, hipStream_t s) {
+    if (a.zchunk <= 0) {
+        static std::atomic<int> occ{0};
+        if (occ.load() == 0) {
+            int o = 0;
+            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, wq_apply_fused_kernel<T, P>, 512, 0);
+            if (e != hipSuccess) return e;
+            occ.store(o > 0 ? o : 1);
+        }
+        int dev = 0, cus = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        a.zchunk = choose_zchunk(a.nq3, a.ntx * a.nty, std::max(1, cus * occ.load()), P);
+    }
+    if (a.zchunk > kMaxZ) return hipErrorInvalidValue;
+    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
+    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(512), 0, s, a);
     return hipGetLastError();
 }
 
@@ -333,15 +372,13 @@ hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
     size_t g = (N + 255) / 256;
     if (g > 4096) g = 4096;
     hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
-    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
-    const int nblk = a.ntx * a.nty * nzc;
     switch (p) {
-        case 2: return launch_p<T, 2>(a, nblk, s);
-        case 3: return launch_p<T, 3>(a, nblk, s);
-        case 4: return launch_p<T, 4>(a, nblk, s);
-        case 5: return launch_p<T, 5>(a, nblk, s);
-        case 6: return launch_p<T, 6>(a, nblk, s);
-        case 7: return launch_p<T, 7>(a, nblk, s);
+        case 2: return launch_p<T, 2>(a, s);
+        case 3: return launch_p<T, 3>(a, s);
+        case 4: return launch_p<T, 4>(a, s);
+        case 5: return launch_p<T, 5>(a, s);
+        case 6: return launch_p<T, 6>(a, s);
+        case 7: return launch_p<T, 7>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
