@@ -315,22 +315,23 @@ hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], 
         a.out = out;
         a.mat = mat;
         a.ldT = ld[axis];
-        int batches = 1;
-        if (axis == 0) {
+        if (axis == 0) {                    // columns (i3, i2): contiguous rows of length n1
             a.n = n1;
             a.C = n2 * n3;
+            a.cdiv = a.C;
             a.sj = 1;
             a.sc = (size_t)n1;
-        } else if (axis == 1) {
+        } else if (axis == 1) {             // columns (i3, i1)
             a.n = n2;
-            a.C = n1;
+            a.C = n1 * n3;
+            a.cdiv = n1;
             a.sj = (size_t)n1;
             a.sc = 1;
             a.sa = (size_t)n1 * n2;
-            batches = n3;
-        } else {
+        } else {                            // columns (i2, i1)
             a.n = n3;
             a.C = n1 * n2;
+            a.cdiv = a.C;
             a.sj = (size_t)n1 * n2;
             a.sc = 1;
         }
@@ -340,7 +341,7 @@ hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], 
             a.l3 = P.lam[2];
             a.n1 = n1;
         }
-        return launch_fd_mode(a, batches, s);
+        return launch_fd_mode(a, s);
     };
     hipError_t e;
     if ((e = mode(0, r, tmp, Tf[0], false)) != hipSuccess) return e;
