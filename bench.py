@@ -10,7 +10,10 @@ One step = for every degree p:
     stream the library runs on),
   * one FP64 right-preconditioned BiCGStab solve to relative residual 1e-10,
   * one mixed-precision solve (FP32 apply, BF16 FD, FP64 refinement) to the
-    same residual.
+    same residual,
+  * the adjoint of J = 1/2 |u|^2 at the FP64 solution: transposed solve
+    K~^T lam = u to 1e-10, then dJ/dC (six planes) and dJ/df at every
+    quadrature point, and R/4 timed transposed applies.
 Set-up (splines, weights, geometry, FD eigenpairs) is outside the timed region.
 
 value   = FP64 apply throughput, sum_p N_p * applies / sum of apply times (GDOF/s)
@@ -171,17 +174,23 @@ def main():
         probs[p] = dict(dp=dp, v=v, w=w, kws=kws, iws=iws, xref=xref, x=torch.zeros_like(v),
                         N=dp.A.N, Nq=dp.A.Nq, setup_s=time.perf_counter() - t0)
         if not args.no_solve:
+            probs[p].update(lam=torch.zeros_like(v), gK=torch.empty(6 * dp.A.Nq, dtype=torch.float64, device="cuda"),
+                            gf=torch.empty(dp.A.Nq, dtype=torch.float64, device="cuda"))
+        if not args.no_solve:
             nref = torch.linalg.norm(xref).item()
             P = probs[p]
             for kind in ("fp64", "mixed"):
                 P[f"{kind}_eq_rtol"] = None
+                # the loosest tolerance that meets the accuracy twice in a row with a
+                # factor-2 margin (the applies accumulate with atomics, so repeated
+                # solves differ in the last bits and the final error varies)
                 for rt in RTOL_LADDER:
                     try:
-                        x = solve(P, kind, rt)
+                        errs = [torch.linalg.norm(solve(P, kind, rt) - xref).item() / nref for _ in range(2)]
                     except RuntimeError as e:          # no convergence at this tolerance
                         log(f"p={p} {kind} rtol {rt:.0e}: {e}")
                         continue
-                    if torch.linalg.norm(x - xref).item() / nref <= EQ_TOL:
+                    if max(errs) <= EQ_TOL / 2:
                         P[f"{kind}_eq_rtol"] = rt
                         break
         log(f"setup p={p}: N={dp.A.N} Nq={dp.A.Nq} {probs[p]['setup_s']:.1f}s (ref solve {it_ref} it, "
@@ -191,7 +200,7 @@ def main():
     stream = torch.cuda.current_stream()
     rec = {p: dict(apply_ms=[], fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
                    mix_err=[], fp64_eq_ms=[], fp64_eq_err=[], fp64_eq_it=[], mixed_eq_ms=[], mixed_eq_err=[],
-                   mixed_eq_it=[]) for p in degrees}
+                   mixed_eq_it=[], adj_ms=[], adj_it=[], applyT_ms=[]) for p in degrees}
     probe = None
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -230,6 +239,21 @@ def main():
                     solve(P, kind, rt, xq)
                     q1.record(stream)
                     eq[kind] = (q0, q1, xq, P["last"])
+                # adjoint of J = 1/2 |u|^2 at the FP64 solution (transposed solve + gradient kernels)
+                a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                P["lam"].zero_()
+                a0.record(stream)
+                _, ait, _ = wqfd.krylov_solve(dp.A, dp.P, P["x"], x=P["lam"], transpose=True, rtol=1e-10,
+                                              maxit=2000, ws=P["kws"])
+                wqfd.wq_grad_K(dp.A, P["lam"], P["x"], P["gK"])
+                wqfd.wq_grad_f(dp.A, P["lam"], P["gf"])
+                a1.record(stream)
+                evT = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(max(1, args.reps // 4))]
+                for e0, e1 in evT:
+                    e0.record(stream)
+                    wqfd.wq_apply_T(dp.A, P["v"], P["w"])
+                    e1.record(stream)
             if probe is not None:
                 probe[1].copy_(probe[0])
             torch.cuda.synchronize()
@@ -245,6 +269,9 @@ def main():
                     r["mix_outer"].append(outer)
                     r["mix_inner"].append(inner)
                     r["mix_err"].append(torch.linalg.norm(xm - P["xref"]).item() / nref)
+                    r["adj_ms"].append(a0.elapsed_time(a1))
+                    r["adj_it"].append(ait)
+                    r["applyT_ms"] += [e0.elapsed_time(e1) for e0, e1 in evT]
                     for kind, (q0, q1, xq, last) in eq.items():
                         r[f"{kind}_eq_ms"].append(q0.elapsed_time(q1))
                         r[f"{kind}_eq_err"].append(torch.linalg.norm(xq - P["xref"]).item() / nref)
@@ -284,6 +311,9 @@ def main():
                       "mixed_solve_ms": round(float(np.median(r["mix_ms"])), 2),
                       "mixed_outer": int(np.median(r["mix_outer"])), "mixed_inner": int(np.median(r["mix_inner"])),
                       "mixed_rel_err_vs_tight": float(np.max(r["mix_err"]))})
+            d["apply_T_ms"] = round(float(np.mean(r["applyT_ms"])), 4)
+            d["adjoint_ms"] = round(float(np.median(r["adj_ms"])), 2)
+            d["adjoint_iters"] = int(np.median(r["adj_it"]))
             for kind in ("fp64", "mixed"):
                 if r[f"{kind}_eq_ms"]:
                     d[f"{kind}_equal_accuracy"] = {
