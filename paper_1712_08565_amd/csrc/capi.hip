@@ -151,7 +151,110 @@ struct FusedHost {
     std::vector<int> bs3, wts3;
     std::vector<double> cz;         // [nq3][2(p+1) + 4(p+2)]
     int zchunk = 0;
+    std::vector<int> sched;         // interval records (wqfd::FusedSched), all z ranges
+    std::vector<int> sched_off;     // first record of each z range, plus the total
 };
+
+// Length of the z range of one workgroup of the fused apply.  The grid is
+// tiles x ranges workgroups; each range also pays for the p + 2 halo planes at
+// its two ends, and the launch runs in ceil(workgroups / resident slots)
+// rounds, so the estimated time is rounds x (zchunk / 2 + p + 3) DOF-plane
+// steps.  Ranges are capped at FUSED_MAX_Z quadrature planes.
+int choose_zchunk(int nq3, int tiles, int slots, int p) {
+    const int zmax = wqfd::FUSED_MAX_Z;
+    int best = zmax;
+    long best_cost = -1;
+    for (int nzc = (nq3 + zmax - 1) / zmax; nzc <= nq3; ++nzc) {
+        const int zc = (nq3 + nzc - 1) / nzc;
+        const long rounds = ((long)tiles * nzc + slots - 1) / slots;
+        const long cost = rounds * (zc + 2 * (p + 3));          // in half DOF-plane steps
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = zc;
+        }
+        if (zc <= p + 2) break;
+    }
+    return best;
+}
+
+// Interval schedule of the fused apply for quadrature planes k0..k1-1 (the
+// pipeline described in wq_fused.hip).  Column waves: per interval up to two
+// quadrature planes, at most one trial plane entering the window and one output
+// plane retired, each placed before the plane that needs it.  MFMA waves, one
+// interval behind: contract the plane retired in the previous interval, reduce
+// the partials written in the previous interval, produce the next U plane (at
+// most NU - 1 planes ahead of the window) and stage the DOF plane after it.
+// Returns false if the windows do not advance by at most one plane per
+// quadrature plane (the kernel then is not used).
+bool fused_schedule(const std::vector<int>& bs3, const std::vector<int>& wts3, int n3, int p, int k0, int k1,
+                    std::vector<int>& out) {
+    const int RT = p + 1, RO = p + 2, NU = 3;
+    const int tmax = bs3[k1 - 1] + RT - 1;
+    int tnext = bs3[k0], nwin = 0, tprod = tnext, tstage = tnext, obase = wts3[k0], k = k0, eflush = 0;
+    int nfw = 0, nred = 0, fl_slot = 0, red_slot = 0, red_i3 = 0, fl_i3 = 0;
+    bool fl_prev = false, red_prev = false;
+    for (int guard = 0; guard < 8 * (k1 - k0) + 4 * (RT + RO) + 64; ++guard) {
+        int nv = 0, in_at = -1, out_at = -1;
+        bool done = false;
+        if (nwin < RT) {
+            if (tnext < tprod) in_at = 0;
+        } else if (k < k1) {
+            for (int j = 0; j < 2 && k + j < k1; ++j) {
+                const int bk = bs3[k + j], wk = wts3[k + j];
+                const bool need_in = tnext + (in_at >= 0) - RT < bk;
+                const bool need_out = obase + (out_at >= 0) < wk;
+                if (need_in && (in_at >= 0 || tnext >= tprod)) break;
+                if (need_out && out_at >= 0) break;
+                if (need_in) in_at = j;
+                if (need_out) out_at = j;
+                // after this plane's events the windows must sit exactly on it
+                if (tnext + (in_at >= 0) - RT != bk || obase + (out_at >= 0) != wk) return false;
+                ++nv;
+            }
+        } else if (eflush < RO) {
+            out_at = 0;
+        } else if (!fl_prev && !red_prev) {
+            done = true;
+        }
+        if (done) return true;
+        const bool c_in = in_at >= 0, c_out = out_at >= 0;
+        const int i3 = obase;
+        const bool c_wr = c_out && i3 >= 0 && i3 < n3;
+        const bool m_prod = tprod < tstage && tprod - NU < tnext && tprod <= tmax;
+        const bool m_stage = tstage <= tprod + 1 && tstage <= tmax;
+        const int f = nv | (in_at + 1) << 2 | (out_at + 1) << 4 | int(c_wr) << 6 | int(m_prod) << 7 |
+                      int(m_stage) << 8 | int(fl_prev) << 9 | int(red_prev) << 10 | (tnext % NU) << 11 |
+                      (nfw & 1) << 13 | fl_slot << 14 | red_slot << 15 | (nred & 1) << 16 | (tprod & 1) << 17 |
+                      (tprod % NU) << 18 | (tstage & 1) << 20;
+        out.insert(out.end(), {f, k, red_i3, tstage});
+        // advance
+        const bool red_now = fl_prev;
+        if (red_now) {
+            red_slot = nred & 1;
+            red_i3 = fl_i3;
+            ++nred;
+        }
+        red_prev = red_now;
+        fl_prev = c_wr;
+        if (c_wr) {
+            fl_slot = nfw & 1;
+            fl_i3 = i3;
+            ++nfw;
+        }
+        if (c_out) {
+            ++obase;
+            if (k >= k1) ++eflush;
+        }
+        if (c_in) {
+            ++tnext;
+            ++nwin;
+        }
+        k += nv;
+        if (m_prod) ++tprod;
+        if (m_stage) ++tstage;
+    }
+    return false;                                   // no progress: schedule rejected
+}
 
 bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
     if (p > 7) return false;
@@ -226,13 +329,27 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
                 if (i < n3) c[2 * RT + v * RO + s] = (*Wv[v])[(size_t)i * nq3 + k];
             }
     }
-    // z range length: chosen at launch from the device's resident workgroups
-    // unless fixed here (WQFD_ZCHUNKS = number of ranges)
-    fh.zchunk = 0;
+    // z range length from the device's resident workgroups (WQFD_ZCHUNKS fixes
+    // the number of ranges), then the interval schedule of every range
+    const int zmax = wqfd::FUSED_MAX_Z;
     if (const char* e = std::getenv("WQFD_ZCHUNKS")) {
-        const int nzc = std::max((nq3 + 63) / 64, std::min(nq3, std::atoi(e)));
+        const int nzc = std::max((nq3 + zmax - 1) / zmax, std::min(nq3, std::atoi(e)));
         fh.zchunk = (nq3 + nzc - 1) / nzc;
+    } else {
+        int slots = 0;
+        if (wqfd::fused_resident_slots(p, &slots) != hipSuccess) {
+            (void)hipGetLastError();                  // no device (size query on a host): assume 256 slots
+            slots = 256;
+        }
+        fh.zchunk = choose_zchunk(nq3, fh.ntile[0] * fh.ntile[1], slots, p);
     }
+    fh.sched.clear();
+    fh.sched_off.clear();
+    for (int k0 = 0; k0 < nq3; k0 += fh.zchunk) {
+        fh.sched_off.push_back((int)(fh.sched.size() / 4));
+        if (!fused_schedule(fh.bs3, fh.wts3, n3, p, k0, std::min(nq3, k0 + fh.zchunk), fh.sched)) return false;
+    }
+    fh.sched_off.push_back((int)(fh.sched.size() / 4));
     return true;
 }
 
@@ -315,7 +432,7 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     FusedHost fh;
     const bool fused_ok = build_fused_tables(sp, p, fh) && !std::getenv("WQFD_STAGED");
     size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0};
-    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0;
+    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_sched = 0, f_soff = 0;
     if (fused_ok) {
         for (int l = 0; l < 2; ++l) {
             f_tiles64[l] = pk.add(fh.tiles[l].data(), fh.tiles[l].size() * 8);
@@ -329,6 +446,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
         f_cz64 = pk.add(fh.cz.data(), fh.cz.size() * 8);
         std::vector<float> c32(fh.cz.begin(), fh.cz.end());
         f_cz32 = pk.add(c32.data(), c32.size() * 4);
+        f_sched = pk.add(fh.sched.data(), fh.sched.size() * sizeof(int));
+        f_soff = pk.add(fh.sched_off.data(), fh.sched_off.size() * sizeof(int));
     }
     // workspace layout
     size_t off = 0;
@@ -411,6 +530,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
             fz.ntx = fh.ntile[0];
             fz.nty = fh.ntile[1];
             fz.zchunk = fh.zchunk;
+            fz.sched = reinterpret_cast<const int*>(tb + f_sched);
+            fz.sched_off = reinterpret_cast<const int*>(tb + f_soff);
         };
         fill(o.fz64, f_tiles64[0], f_tiles64[1], f_cz64, o.C64);
         fill(o.fz32, f_tiles32[0], f_tiles32[1], f_cz32, o.C32);

@@ -7,6 +7,8 @@
 
 namespace wqfd {
 
+constexpr int FUSED_MAX_Z = 64;   // longest z range of one workgroup of the fused apply
+
 // Arguments of the fused apply.  Dense 16 x 16 blocks per 16-point tile:
 // tilesX[t][6][16][16] (x direction) and tilesY (y direction), in the order
 // B_0[q][j], B_1[q][j] (values / derivatives, q = tile quadrature point,
@@ -31,7 +33,27 @@ struct FusedArgs {
     const int* wts3 = nullptr;
     const T* cz = nullptr;
     int ntx = 0, nty = 0, zchunk = 0;
+    // interval schedule: records of four ints per interval (see FusedSched),
+    // z range r uses records sched_off[r] .. sched_off[r + 1] - 1
+    const int* sched = nullptr;
+    const int* sched_off = nullptr;
 };
+
+// One interval of the fused apply's pipeline (between two workgroup barriers),
+// computed on the host.  f packs: bits 0-1 number of quadrature planes; 2-3
+// window entry position + 1; 4-5 retirement position + 1; 6 retired plane is
+// written; 7 produce a U plane; 8 stage a DOF plane; 9 contract the retired
+// plane written last interval; 10 reduce the partials written last interval;
+// 11-12 U slot of the entering plane; 13 psi slot written; 14 psi slot read;
+// 15 partial slot reduced; 16 partial slot written; 17 V slot read; 18-19 U
+// slot written; 20 V slot written.
+struct FusedSched {
+    int f, k, red_i3, tstage;
+};
+
+// Resident workgroups of the fused FP64 apply kernel of degree p on the
+// current device (compute units x workgroups per unit).
+hipError_t fused_resident_slots(int p, int* slots);
 
 template <typename T>
 hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s);

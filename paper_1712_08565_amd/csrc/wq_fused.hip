@@ -25,7 +25,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 
 #include "device.h"
 #include "fused.h"
@@ -39,7 +38,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
 constexpr int BLK = 16 * LD;
-constexpr int kMaxZ = 64;         // longest z range of one workgroup (the launcher caps zchunk)
+constexpr int kMaxZ = FUSED_MAX_Z;   // longest z range of one workgroup
 
 template <typename T>
 struct MF;
@@ -60,12 +59,14 @@ struct MF<float> {
 // (BT = false) or Bt[n][k] (BT = true).
 template <typename T, bool BT>
 __device__ inline typename MF<T>::acc gemm16(const T* At, const T* Bt, typename MF<T>::acc c, int cl, int kb) {
+    T a[4], b[4];                        // all operands first: one LDS round trip
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const T a = At[cl * LD + 4 * s + kb];
-        const T b = BT ? Bt[cl * LD + 4 * s + kb] : Bt[(4 * s + kb) * LD + cl];
-        c = MF<T>::mma(a, b, c);
+        a[s] = At[cl * LD + 4 * s + kb];
+        b[s] = BT ? Bt[cl * LD + 4 * s + kb] : Bt[(4 * s + kb) * LD + cl];
     }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = MF<T>::mma(a[s], b[s], c);
     return c;
 }
 
@@ -80,27 +81,39 @@ __device__ inline void store16(T* tile, const typename MF<T>::acc& c, int cl, in
     for (int v = 0; v < 4; ++v) tile[MF<T>::drow(kb, v) * LD + cl] = c[v];
 }
 
-// 512 threads: two per quadrature column.  Threads 0..255 (waves 0-3) carry
-// the test fields f = 3 alpha + beta = 0..4, threads 256..511 (waves 4-7) the
-// fields 5..8, which halves the per-thread register windows; the x/y work of a
-// retired output plane is spread over all eight waves.
+// 1024 threads in two roles, one barrier per interval (one quadrature plane).
+//   Column waves 0-11: wave group beta = wave / 4 (trial derivative direction x,
+//     y, z) owns the fields f = 3 alpha + beta, alpha = x, y, z, of all 256
+//     columns; a thread keeps the window of the p+1 trial planes of U_beta
+//     (U_x, U_y or U_0) it needs, the coefficients C_(alpha beta) of the
+//     current plane and a register ring of the p+2 output planes per field.
+//   MFMA waves 12-15: one interval behind the column waves, they turn staged DOF
+//     planes into U planes (a ring of NU planes in LDS), contract retired
+//     output planes in x and y, and add the 16 x 16 DOF block to w.
+// Every buffer a role writes in an interval is read by the other role only
+// after the closing barrier, and is not rewritten before the reader's interval
+// has ended; the schedule is computed identically by every wave.
 template <typename T, int P>
-__global__ __launch_bounds__(512, 1) void wq_apply_fused_kernel(FusedArgs<T> a) {
+__global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a) {
     constexpr int RT = P + 1;              // trial window (DOF planes)
     constexpr int RO = P + 2;              // test window (output planes)
     constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
+    constexpr int NU = 3;                  // U planes in flight
     __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
-    __shared__ T sT[6][BLK];               // V, A_0, A_1, U_x, U_y, U_0
-    __shared__ T sP[9][BLK];               // psi_f of the plane being retired
-    __shared__ T sR[8][BLK];               // per-wave partial output blocks
-    __shared__ T sZ[kMaxZ * CZ];            // z coefficients of this workgroup's planes
-    __shared__ int sB3[kMaxZ], sW3[kMaxZ];  // z window starts of these planes
+    __shared__ T sV[2][BLK];               // staged DOF planes
+    __shared__ T sU[NU][3][BLK];           // U_x, U_y, U_0 of produced planes
+    __shared__ T sP[2][9][BLK];            // psi_f of retired output planes
+    __shared__ T sR[2][5][BLK];            // partial output blocks of the x/y test contraction
+    __shared__ T sZ[kMaxZ * CZ];           // z coefficients of this workgroup's planes
 
     using acc_t = typename MF<T>::acc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int half = tid >> 8, ct = tid & 255;
+    const bool mrole = wave >= 12;         // MFMA role (wave-uniform)
+    const int ct = tid & 255;              // column of a column thread / lane slot of an MFMA thread
     const int cl = lane & 15, kb = lane >> 4;
     const int q1l = ct & 15, q2l = ct >> 4;
+    const int beta = wave >> 2;            // column waves: 0, 1, 2
+    const int mw = wave - 12;              // MFMA waves: 0..3
 
     // workgroup -> (t1, t2, zc); consecutive blocks are dealt round-robin to the
     // eight XCDs, so hand each XCD a contiguous run of neighbouring tiles
@@ -117,10 +130,11 @@ __global__ __launch_bounds__(512, 1) void wq_apply_fused_kernel(FusedArgs<T> a) 
     const int Q1 = t1 * 16, Q2 = t2 * 16;
     const int q1 = Q1 + q1l, q2 = Q2 + q2l;
     const bool active = q1 < a.nq1 && q2 < a.nq2;
-    const int J1 = a.JX[t1], I1 = a.IX[t1], J2 = a.JY[t2], I2 = a.IY[t2];
+    const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
+    const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
-    // coefficient blocks of this tile
-    for (int idx = tid; idx < 12 * 256; idx += 512) {
+    // coefficient blocks of this tile, z coefficients and window starts
+    for (int idx = tid; idx < 12 * 256; idx += 1024) {
         const int tl = idx >> 8, e = idx & 255;
         const T* src;
         if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
@@ -129,191 +143,225 @@ __global__ __launch_bounds__(512, 1) void wq_apply_fused_kernel(FusedArgs<T> a) 
         else src = a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;
         sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
     }
+    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
+    // this range's interval records (uniform: read through the scalar cache)
+    const int r0 = a.sched_off[zc], nrec = a.sched_off[zc + 1] - r0;
+    const int* __restrict__ rec = a.sched + 4 * (size_t)r0;
 
-    // z coefficients and window starts of planes k0..k1-1, staged once: per-plane
-    // scalar loads would miss the scalar cache and stall every LDS wait
-    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 512) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
-    for (int idx = tid; idx < k1 - k0; idx += 512) {
-        sB3[idx] = a.bs3[k0 + idx];
-        sW3[idx] = a.wts3[k0 + idx];
-    }
+    // ---- MFMA-role helpers ------------------------------------------------
+    // A operand for a product whose B operand is an accumulator: the K index of
+    // step s held by lane group kb is the accumulator row drow(kb, s)
+    auto ld_accA = [&](T (&av)[4], const T* A) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[s] = A[cl * LD + MF<T>::drow(kb, s)];
+    };
+    auto mm_acc = [&](acc_t& Z, const T (&av)[4], const acc_t& X) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Z = MF<T>::mma(av[s], X[s], Z);
+    };
+    auto v1_of = [](int f) { return 2 * (f / 3 == 0) + (f % 3 == 0); };   // 2[alpha = x] + [beta = x]
 
-    // this thread's entry V[j2][j1] of DOF plane j3 (zero outside the mesh;
-    // only the first half of the workgroup stages V)
-    const int vj1 = J1 + q1l, vj2 = J2 + q2l;
-    const bool vin = half == 0 && vj1 < a.n1 && vj2 < a.n2;
-    auto load_v = [&](int j3) -> T {
-        return (vin && j3 < a.n3) ? a.v[((size_t)j3 * a.n2 + vj2) * a.n1 + vj1] : T(0);
-    };
-    // trial contraction of a DOF plane onto the tile's columns
-    auto trial_plane = [&](T val, T& ux, T& uy, T& u0) {
-        if (half == 0) sT[0][q2l * LD + q1l] = val;           // V[j2][j1]
-        lds_barrier();
-        if (wave < 2) {                                        // A_d[j2][q1] = sum_j1 V[j2][j1] B1_d[q1][j1]
-            acc_t c = {0, 0, 0, 0};
-            c = gemm16<T, true>(sT[0], sCoef[wave], c, cl, kb);
-            store16<T>(sT[1 + wave], c, cl, kb);
-        }
-        lds_barrier();
-        if (wave >= 2 && wave < 5) {                           // U[q2][q1] = sum_j2 B2_d[q2][j2] A[j2][q1]
-            const int u = wave - 2;                            // 0: U_x, 1: U_y, 2: U_0
-            const T* At = sCoef[2 + (u == 1 ? 1 : 0)];         // U_y uses B-dot2
-            const T* Bt = sT[u == 0 ? 2 : 1];                  // U_x uses A_1 (B-dot1)
-            acc_t c = {0, 0, 0, 0};
-            c = gemm16<T, false>(At, Bt, c, cl, kb);
-            store16<T>(sT[3 + u], c, cl, kb);
-        }
-        lds_barrier();
-        ux = sT[3][q2l * LD + q1l];
-        uy = sT[4][q2l * LD + q1l];
-        u0 = sT[5][q2l * LD + q1l];
-    };
+    // ---- column-role state ------------------------------------------------
+    T Uw[RT];                               // trial window of U_beta
+    T acc[3][RO];                           // output ring of fields 3 alpha + beta
+#pragma unroll
+    for (int s = 0; s < RT; ++s) Uw[s] = T(0);
+#pragma unroll
+    for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int s = 0; s < RO; ++s) acc[al][s] = T(0);
+    // coefficient planes C_(alpha beta) of this thread's three fields
+    // (stored planes C11, C22, C33, C12, C13, C23 = 0..5; the offsets are wave-uniform)
+    const int pidx = __builtin_amdgcn_readfirstlane(beta == 0 ? 0x430 : beta == 1 ? 0x513 : 0x254);
+    const size_t Nq = a.Nq;
+    const size_t plane = (size_t)a.nq1 * a.nq2;
+    const size_t poff[3] = {((pidx >> 0) & 15) * Nq, ((pidx >> 4) & 15) * Nq, ((pidx >> 8) & 15) * Nq};
+    const bool cload = !mrole && active;
+    const T* Ccol = a.C + ((size_t)q2 * a.nq1 + q1);
+    T Cn[3];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) Cn[al] = cload ? Ccol[poff[al] + (size_t)k0 * plane] : T(0);
 
-    // x/y test contraction of output plane i3 and atomic update of w.  A field
-    // is contracted in x first (X = psi_f W1^T) and the y product takes X
-    // straight from the accumulator registers as its B operand (the K index of
-    // step s held by lane group kb is the accumulator row drow(kb, s), so W2 is
-    // read with the same row mapping).  Waves 0-5 take one field each
-    // (xx, xz, zx, zz, xy, zy), wave 6 the pair {yx, yz} sharing W2^2, wave 7 yy.
-    auto xpart = [&](acc_t& X, int f) {
-        const int al = f / 3, be = f % 3;
-        const int v1 = 2 * (al == 0) + (be == 0);
-        X = gemm16<T, true>(sP[f], sCoef[4 + v1], X, cl, kb);
-    };
-    auto ypart = [&](acc_t& Z, const acc_t& X, int v2) {
-        const T* A = sCoef[8 + v2];
+    // one quadrature plane of column work: g = (z trial row) . window,
+    // psi_alpha = C_(alpha beta) g, ring += (z test rows) psi
+    auto valu_plane = [&](int kq) {
+        T C[3];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) Z = MF<T>::mma(A[cl * LD + MF<T>::drow(kb, s)], X[s], Z);
-    };
-    auto flush = [&](int i3, const T* vals) {
-        if (i3 < 0 || i3 >= a.n3) return;                      // uniform across the workgroup
-        if (half == 0) {
+        for (int al = 0; al < 3; ++al) C[al] = Cn[al];
+        if (kq + 1 < k1) {
+            const size_t ko = (size_t)(kq + 1) * plane;
 #pragma unroll
-            for (int f = 0; f < 5; ++f) sP[f][q2l * LD + q1l] = vals[f];
-        } else {
-#pragma unroll
-            for (int f = 0; f < 4; ++f) sP[5 + f][q2l * LD + q1l] = vals[f];
+            for (int al = 0; al < 3; ++al) Cn[al] = cload ? Ccol[poff[al] + ko] : T(0);
         }
-        lds_barrier();
-        {
-            // (field, y variant) per wave; wave 6 adds a second field
-            constexpr int fw[8] = {0, 2, 6, 8, 1, 7, 3, 4};
-            constexpr int vw[8] = {0, 0, 0, 0, 1, 1, 2, 3};
-            acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
-            xpart(X, fw[wave]);
-            if (wave == 6) xpart(X, 5);
-            ypart(Z, X, vw[wave]);
-            store16<T>(sR[wave], Z, cl, kb);
-        }
-        lds_barrier();
-        if (half == 0) {
-            T s = T(0);
+        const T* cz = sZ + (size_t)(kq - k0) * CZ;
+        const T* ct3 = cz + (beta == 2 ? RT : 0);               // B3 row, or B-dot3 for beta = z
+        T g = T(0);
 #pragma unroll
-            for (int w = 0; w < 8; ++w) s += sR[w][q2l * LD + q1l];
-            const int i1 = I1 + q1l, i2 = I2 + q2l;
-            if (i1 < a.n1 && i2 < a.n2 && s != T(0)) atomicAdd(&a.w[((size_t)i3 * a.n2 + i2) * a.n1 + i1], s);
+        for (int s = 0; s < RT; ++s) g += ct3[s] * Uw[s];
+        // z weight variant of field (alpha, beta): 2 [alpha = z] + [beta = z]
+        const T* w01 = cz + 2 * RT + (beta == 2 ? 1 : 0) * RO;
+        const T* w2 = cz + 2 * RT + (beta == 2 ? 3 : 2) * RO;
+        const T p0 = C[0] * g, p1 = C[1] * g, p2 = C[2] * g;
+#pragma unroll
+        for (int s = 0; s < RO; ++s) {
+            acc[0][s] += w01[s] * p0;
+            acc[1][s] += w01[s] * p1;
+            acc[2][s] += w2[s] * p2;
         }
-        lds_barrier();
     };
-
-    T Ux[RT], Uy[RT], U0[RT];
-    T acc[5][RO];                                              // half 0: fields 0..4, half 1: 5..8
-#pragma unroll
-    for (int f = 0; f < 5; ++f)
-#pragma unroll
-        for (int s = 0; s < RO; ++s) acc[f][s] = T(0);
 
     lds_barrier();
-    int tbase = sB3[0];
-    int obase = sW3[0];
-#pragma unroll
-    for (int s = 0; s < RT; ++s) trial_plane(load_v(tbase + s), Ux[s], Uy[s], U0[s]);
-    T vnext = load_v(tbase + RT);                              // next plane to enter the window
 
-    // coefficient planes this half needs: half 0 (C11, C22, C12, C13), half 1 (C33, C13, C23)
-    const size_t Nq = a.Nq;
-    const size_t col = (size_t)q2 * a.nq1 + q1;
-    const size_t plane = (size_t)a.nq1 * a.nq2;
-    const int cpl[4] = {half == 0 ? 0 : 2, half == 0 ? 1 : 4, half == 0 ? 3 : 5, 4};
-    const int ncp = half == 0 ? 4 : 3;
-    T Cn[4];
+    // ---- the interval loop: every wave walks the same host-computed records ----
+    if (mrole) {
+        // x/y test contraction of the plane retired in the previous interval.
+        // Fields sharing the y weight variant v2 = 2[alpha = y] + [beta = y] are
+        // summed after their x products (X = sum_f psi_f W1^(v1_f)T, Z = W2^(v2) X):
+        //   wave 12: {xx, xz};  wave 13: {zx, zz} (v2 = 0);  wave 14: {xy, zy} (v2 = 1);
+        //   wave 15: {yx, yz} (v2 = 2); {yy} (v2 = 3) runs on column wave 3.
+        // The factor operands are the same in every interval and stay in registers.
+        // Wave 15 also sums the partial blocks and adds them to w: it issues no
+        // loads, so its atomics never delay a wait for loaded data.
+        const int fa = mw == 0 ? 0 : mw == 1 ? 6 : mw == 2 ? 1 : 3;
+        const int fb = mw == 0 ? 2 : mw == 1 ? 8 : mw == 2 ? 7 : 5;
+        const int v2 = mw == 0 ? 0 : mw == 1 ? 0 : mw == 2 ? 1 : 2;
+        T ba[4], bb[4], w2a[4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
-        Cn[c] = (active && c < ncp) ? a.C[cpl[c] * Nq + (size_t)k0 * plane + col] : T(0);
-    for (int k = k0; k < k1; ++k) {
-        // plane k's coefficients were loaded one plane ahead; issue plane k+1's now
-        T C[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) C[c] = Cn[c];
-        if (k + 1 < k1) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                Cn[c] = (active && c < ncp) ? a.C[cpl[c] * Nq + (size_t)(k + 1) * plane + col] : T(0);
+        for (int q = 0; q < 4; ++q) {
+            ba[q] = sCoef[4 + v1_of(fa)][cl * LD + 4 * q + kb];
+            bb[q] = sCoef[4 + v1_of(fb)][cl * LD + 4 * q + kb];
         }
-        const int bk = sB3[k - k0], wk = sW3[k - k0];
-        while (tbase < bk) {                                   // slide the trial window
+        ld_accA(w2a, sCoef[8 + v2]);
+        // waves 12 and 13 stage the DOF planes, loaded two intervals ahead
+        // (entries lane + 64 (2 mw + q) of the 16 x 16 block)
+        const bool stager = mw < 2;
+        T vq0[2], vq1[2];
+        auto vload = [&](T (&dst)[2], int j3) {
 #pragma unroll
-            for (int s = 0; s < RT - 1; ++s) {
-                Ux[s] = Ux[s + 1];
-                Uy[s] = Uy[s + 1];
-                U0[s] = U0[s + 1];
+            for (int q = 0; q < 2; ++q) {
+                const int e = lane + 64 * (2 * mw + q);
+                const int j1 = J1 + (e & 15), j2 = J2 + (e >> 4);
+                dst[q] = (j1 < a.n1 && j2 < a.n2 && j3 >= 0 && j3 < a.n3)
+                             ? a.v[((size_t)j3 * a.n2 + j2) * a.n1 + j1] : T(0);
             }
-            const T vcur = vnext;
-            vnext = load_v(tbase + RT + 1);                    // issue the following load early
-            trial_plane(vcur, Ux[RT - 1], Uy[RT - 1], U0[RT - 1]);
-            ++tbase;
+        };
+        if (stager && nrec > 0) {
+            const int t0 = rec[3];
+            vload((t0 & 1) ? vq1 : vq0, t0);
+            vload((t0 & 1) ? vq0 : vq1, t0 + 1);
         }
-        while (obase < wk) {                                   // retire the oldest output plane
-            T vals[5];
+        for (int r = 0; r < nrec; ++r) {
+            const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
+            if ((fl >> 9) & 1) {
+                const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
+                T xa[4], xb[4];
 #pragma unroll
-            for (int f = 0; f < 5; ++f) vals[f] = acc[f][0];
-            flush(obase, vals);
+                for (int q = 0; q < 4; ++q) {
+                    xa[q] = sP[ps][fa][cl * LD + 4 * q + kb];
+                    xb[q] = sP[ps][fb][cl * LD + 4 * q + kb];
+                }
+                acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
 #pragma unroll
-            for (int f = 0; f < 5; ++f) {
+                for (int q = 0; q < 4; ++q) X = MF<T>::mma(xa[q], ba[q], X);
 #pragma unroll
-                for (int s = 0; s < RO - 1; ++s) acc[f][s] = acc[f][s + 1];
-                acc[f][RO - 1] = T(0);
+                for (int q = 0; q < 4; ++q) X = MF<T>::mma(xb[q], bb[q], X);
+                mm_acc(Z, w2a, X);
+                store16<T>(sR[rs][mw], Z, cl, kb);
             }
-            ++obase;
+            if (stager && ((fl >> 8) & 1)) {
+                const int sl = (fl >> 20) & 1;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const int e = lane + 64 * (2 * mw + q);
+                    sV[sl][(e >> 4) * LD + (e & 15)] = sl ? vq1[q] : vq0[q];
+                }
+                if (sl) vload(vq1, ts + 2); else vload(vq0, ts + 2);
+            }
+            if (mw == 3 && ((fl >> 10) & 1)) {
+                const int rs = (fl >> 15) & 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = lane + 64 * q;
+                    const int el = (e >> 4) * LD + (e & 15);
+                    const T sum = sR[rs][0][el] + sR[rs][1][el] + sR[rs][2][el] + sR[rs][3][el] + sR[rs][4][el];
+                    const int i1 = I1 + (e & 15), i2 = I2 + (e >> 4);
+                    if (i1 < a.n1 && i2 < a.n2 && sum != T(0))
+                        atomicAdd(&a.w[((size_t)red_i3 * a.n2 + i2) * a.n1 + i1], sum);
+                }
+            }
+            lds_barrier();
         }
-        const T* cz = sZ + (size_t)(k - k0) * CZ;
-        T g[3] = {T(0), T(0), T(0)};
+    } else {
+        // Besides their planes, column waves produce the U planes (wave 0:
+        // U_x = B2 A_1, wave 5: U_y = B-dot2 A_0, wave 10: U_0 = B2 A_0 with
+        // A_d = V B1_d^T) and contract the {yy} field of the retired plane (wave 3).
+        const bool producer = wave == 0 || wave == 5 || wave == 10;
+        for (int r = 0; r < nrec; ++r) {
+            const int fl = rec[4 * r], kq = rec[4 * r + 1];
+            const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
+            const int nsteps = max(nv, max(in_at, out_at) + 1);
+            if (producer && ((fl >> 7) & 1)) {
+                const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
+                const T* Bt = sCoef[beta == 0 ? 1 : 0];
+                acc_t A = {0, 0, 0, 0}, U = {0, 0, 0, 0};
+                {
+                    T av[4], bv[4];
 #pragma unroll
-        for (int s = 0; s < RT; ++s) {
-            g[0] += cz[s] * Ux[s];
-            g[1] += cz[s] * Uy[s];
-            g[2] += cz[RT + s] * U0[s];
+                    for (int q = 0; q < 4; ++q) {
+                        av[q] = sV[vs][cl * LD + 4 * q + kb];
+                        bv[q] = Bt[cl * LD + 4 * q + kb];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) A = MF<T>::mma(av[q], bv[q], A);
+                }
+                T ua[4];
+                ld_accA(ua, sCoef[beta == 1 ? 3 : 2]);
+                mm_acc(U, ua, A);
+                store16<T>(sU[us][beta], U, cl, kb);
+            }
+            if (wave == 3 && ((fl >> 9) & 1)) {
+                const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
+                const T* Bt = sCoef[4 + v1_of(4)];
+                acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
+                {
+                    T xv[4], bv[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        xv[q] = sP[ps][4][cl * LD + 4 * q + kb];
+                        bv[q] = Bt[cl * LD + 4 * q + kb];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) X = MF<T>::mma(xv[q], bv[q], X);
+                }
+                T wv[4];
+                ld_accA(wv, sCoef[8 + 3]);
+                mm_acc(Z, wv, X);
+                store16<T>(sR[rs][4], Z, cl, kb);
+            }
+
+            for (int j = 0; j < nsteps; ++j) {
+                if (j == in_at) {
+#pragma unroll
+                    for (int s = 0; s < RT - 1; ++s) Uw[s] = Uw[s + 1];
+                    Uw[RT - 1] = sU[(fl >> 11) & 3][beta][q2l * LD + q1l];
+                }
+                if (j == out_at) {
+                    if ((fl >> 6) & 1) {
+                        const int ps = (fl >> 13) & 1;
+#pragma unroll
+                        for (int al = 0; al < 3; ++al) sP[ps][3 * al + beta][q2l * LD + q1l] = acc[al][0];
+                    }
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) {
+#pragma unroll
+                        for (int s = 0; s < RO - 1; ++s) acc[al][s] = acc[al][s + 1];
+                        acc[al][RO - 1] = T(0);
+                    }
+                }
+                if (j < nv) valu_plane(kq + j);
+            }
+            lds_barrier();
         }
-        // psi_ab = C_ab g_b; the z weight variant of field (alpha, beta) is
-        // 2 [alpha = z] + [beta = z]
-        T psi[5];
-        int v3[5];
-        if (half == 0) {        // xx, xy, xz, yx, yy with C = (C11, C22, C12, C13)
-            psi[0] = C[0] * g[0]; v3[0] = 0;
-            psi[1] = C[2] * g[1]; v3[1] = 0;
-            psi[2] = C[3] * g[2]; v3[2] = 1;
-            psi[3] = C[2] * g[0]; v3[3] = 0;
-            psi[4] = C[1] * g[1]; v3[4] = 0;
-        } else {                // yz, zx, zy, zz with C = (C33, C13, C23)
-            psi[0] = C[2] * g[2]; v3[0] = 1;
-            psi[1] = C[1] * g[0]; v3[1] = 2;
-            psi[2] = C[2] * g[1]; v3[2] = 2;
-            psi[3] = C[0] * g[2]; v3[3] = 3;
-            psi[4] = T(0);        v3[4] = 0;
-        }
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            const T* cw = cz + 2 * RT + v3[f] * RO;
-#pragma unroll
-            for (int s = 0; s < RO; ++s) acc[f][s] += cw[s] * psi[f];
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < RO; ++s) {
-        T vals[5];
-#pragma unroll
-        for (int f = 0; f < 5; ++f) vals[f] = acc[f][s];
-        flush(obase + s, vals);
     }
 }
 
@@ -322,46 +370,23 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) 
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = T(0);
 }
 
-// Length of the z range of one workgroup.  The grid is tiles x ranges
-// workgroups; each range also pays for the p + 2 halo planes at its two ends,
-// and the launch runs in ceil(workgroups / resident slots) rounds, so the
-// estimated time is rounds x (zchunk / 2 + p + 3) DOF-plane steps.  Ranges are
-// capped at kMaxZ quadrature planes (the kernel stages their z factors in LDS).
-int choose_zchunk(int nq3, int tiles, int slots, int p) {
-    int best = kMaxZ, best_cost = -1;
-    for (int nzc = (nq3 + kMaxZ - 1) / kMaxZ; nzc <= nq3; ++nzc) {
-        const int zc = (nq3 + nzc - 1) / nzc;
-        const long rounds = ((long)tiles * nzc + slots - 1) / slots;
-        const long cost = rounds * (zc + 2 * (p + 3));          // in half DOF-plane steps
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = zc;
-        }
-        if (zc <= p + 2) break;
-    }
-    return best;
+template <typename T, int P>
+hipError_t launch_p(const FusedArgs<T>& a, hipStream_t s) {
+    if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.sched || !a.sched_off) return hipErrorInvalidValue;
+    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
+    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    return hipGetLastError();
 }
 
-template <typename T, int P>
-hipError_t launch_p(FusedArgs<T> a, hipStream_t s) {
-    if (a.zchunk <= 0) {
-        static std::atomic<int> occ{0};
-        if (occ.load() == 0) {
-            int o = 0;
-            hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, wq_apply_fused_kernel<T, P>, 512, 0);
-            if (e != hipSuccess) return e;
-            occ.store(o > 0 ? o : 1);
-        }
-        int dev = 0, cus = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return e;
-        a.zchunk = choose_zchunk(a.nq3, a.ntx * a.nty, std::max(1, cus * occ.load()), P);
-    }
-    if (a.zchunk > kMaxZ) return hipErrorInvalidValue;
-    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
-    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(512), 0, s, a);
-    return hipGetLastError();
+template <int P>
+hipError_t slots_p(int* slots) {
+    int occ = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wq_apply_fused_kernel<double, P>, 1024, 0);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *slots = std::max(1, std::max(occ, 1) * cus);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -379,6 +404,18 @@ hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
         case 5: return launch_p<T, 5>(a, s);
         case 6: return launch_p<T, 6>(a, s);
         case 7: return launch_p<T, 7>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t fused_resident_slots(int p, int* slots) {
+    switch (p) {
+        case 2: return slots_p<2>(slots);
+        case 3: return slots_p<3>(slots);
+        case 4: return slots_p<4>(slots);
+        case 5: return slots_p<5>(slots);
+        case 6: return slots_p<6>(slots);
+        case 7: return slots_p<7>(slots);
         default: return hipErrorInvalidValue;
     }
 }
