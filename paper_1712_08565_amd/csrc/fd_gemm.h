@@ -24,6 +24,26 @@ struct FdModeArgs {
     int n1 = 1;
 };
 
+// Whole preconditioner application in three fused passes (n <= 144): forward
+// x and y per z-plane, forward z + eigenvalue scaling + backward z per column
+// block, backward x and y.  U[l] / UT[l] row-major n_l x n_l; tmp: N scratch
+// entries; r and z may alias.
+template <typename T>
+struct FdFusedArgs {
+    const T* r = nullptr;
+    T* z = nullptr;
+    T* tmp = nullptr;
+    const T* U[3] = {nullptr, nullptr, nullptr};
+    const T* UT[3] = {nullptr, nullptr, nullptr};
+    const double* l1 = nullptr;
+    const double* l2 = nullptr;
+    const double* l3 = nullptr;
+    int n1 = 0, n2 = 0, n3 = 0;
+};
+
+hipError_t launch_fd_fused(const FdFusedArgs<double>& f, hipStream_t s);
+hipError_t launch_fd_fused(const FdFusedArgs<float>& f, hipStream_t s);
+
 hipError_t launch_fd_mode(const FdModeArgs<double, double>& p, hipStream_t s);
 hipError_t launch_fd_mode(const FdModeArgs<float, float>& p, hipStream_t s);
 hipError_t launch_fd_mode(const FdModeArgs<float, __bf16>& p, hipStream_t s);

@@ -147,10 +147,183 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused passes of the whole preconditioner (FP64 and FP32, n <= 144), three
+// launches per application instead of six:
+//   xy pass, per z-plane i3 and 16-column block of i1:
+//     Q[j2][i1] = sum_j1 in[i3][j2][j1] T1[i1][j1]   (wave t: rows j2 of block t)
+//     out[i3][i2][i1] = sum_j2 T2[i2][j2] Q[j2][i1]   (Q through LDS)
+//   z pass, per 16-column block of g = (i2, i1):
+//     Y[i3][g] = sum_j3 T3f[i3][j3] in[j3][g] / (l1[i1] + l2[i2] + l3[i3])
+//     out[i3][g] = sum_j3 T3b[i3][j3] Y[j3][g]       (Y through LDS; in may be out)
+// One wave per 16-row block (KB = ceil(n / 16) waves), operands of the first
+// product loaded up front.
+constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
+
+template <int PREC, int KB>
+__global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T* __restrict__ in,
+                                                      typename G<PREC>::T* __restrict__ out,
+                                                      const typename G<PREC>::T* __restrict__ T1,
+                                                      const typename G<PREC>::T* __restrict__ T2, int n1, int n2) {
+    using T = typename G<PREC>::T;
+    using Acc = typename G<PREC>::Acc;
+    constexpr int NKS = 4 * KB;
+    __shared__ T sQ[16 * KB * FLD];
+    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int c0 = blockIdx.x * 16;                      // first i1 of this block
+    const size_t pl = (size_t)blockIdx.y * n1 * n2;       // z-plane offset
+    // Q block t: rows j2 = 16 t + ., columns i1 = c0 + .
+    T a[NKS], b[NKS];
+    const int j2 = 16 * t + cl, i1 = c0 + cl;
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kb;                        // j1
+        a[s] = (j2 < n2 && k < n1) ? in[pl + (size_t)j2 * n1 + k] : T(0);
+        b[s] = (i1 < n1 && k < n1) ? T1[(size_t)i1 * n1 + k] : T(0);
+    }
+    Acc q = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        if constexpr (PREC == 1)
+            q = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], q, 0, 0, 0);
+        else
+            q = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], q, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sQ[(16 * t + G<PREC>::drow(kb, v)) * FLD + cl] = q[v];
+    __syncthreads();
+    // out block t: rows i2 = 16 t + ., contraction over j2 with Q from LDS
+    const int i2 = 16 * t + cl;
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kb;                        // j2
+        a[s] = (i2 < n2 && k < n2) ? T2[(size_t)i2 * n2 + k] : T(0);
+        b[s] = sQ[k * FLD + cl];                         // rows j2 >= n2 hold zeros
+    }
+    Acc r = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        if constexpr (PREC == 1)
+            r = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], r, 0, 0, 0);
+        else
+            r = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], r, 0, 0, 0);
+    }
+    if (i1 >= n1) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ii = 16 * t + G<PREC>::drow(kb, v);
+        if (ii < n2) out[pl + (size_t)ii * n1 + i1] = r[v];
+    }
+}
+
+template <int PREC, int KB>
+__global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* in, typename G<PREC>::T* out,
+                                                     const typename G<PREC>::T* __restrict__ T3f,
+                                                     const typename G<PREC>::T* __restrict__ T3b,
+                                                     const double* __restrict__ l1, const double* __restrict__ l2,
+                                                     const double* __restrict__ l3, int n1, int n2, int n3) {
+    using T = typename G<PREC>::T;
+    using Acc = typename G<PREC>::Acc;
+    constexpr int NKS = 4 * KB;
+    __shared__ T sY[16 * KB * FLD];
+    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int C = n1 * n2;
+    const int g = blockIdx.x * 16 + cl;
+    const bool gin = g < C;
+    const int i3r = 16 * t + cl;                         // row of T3 (A operand)
+    T a[NKS], b[NKS];
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kb;                        // j3
+        a[s] = (i3r < n3 && k < n3) ? T3f[(size_t)i3r * n3 + k] : T(0);
+        b[s] = (gin && k < n3) ? in[(size_t)k * C + g] : T(0);
+    }
+    Acc y = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        if constexpr (PREC == 1)
+            y = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], y, 0, 0, 0);
+        else
+            y = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], y, 0, 0, 0);
+    }
+    double l12 = 0.0;
+    if (gin) {
+        const int i2 = g / n1, i1 = g - i2 * n1;
+        l12 = l1[i1] + l2[i2];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i3 = 16 * t + G<PREC>::drow(kb, v);
+        sY[(16 * t + G<PREC>::drow(kb, v)) * FLD + cl] =
+            (gin && i3 < n3) ? (T)((double)y[v] / (l12 + l3[i3])) : T(0);
+    }
+    __syncthreads();                                     // every read of `in` by this block is done
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        const int k = 4 * s + kb;
+        a[s] = (i3r < n3 && k < n3) ? T3b[(size_t)i3r * n3 + k] : T(0);
+        b[s] = sY[k * FLD + cl];
+    }
+    Acc z = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        if constexpr (PREC == 1)
+            z = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], z, 0, 0, 0);
+        else
+            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], z, 0, 0, 0);
+    }
+    if (!gin) return;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i3 = 16 * t + G<PREC>::drow(kb, v);
+        if (i3 < n3) out[(size_t)i3 * C + g] = z[v];
+    }
+}
+
+template <int PREC, int KB>
+hipError_t fused_kb(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
+    using T = typename G<PREC>::T;
+    hipError_t e;
+    // forward x and y
+    dim3 gxy((f.n1 + 15) / 16, f.n3);
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.UT[0], f.UT[1], f.n1, f.n2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // forward z, scaling, backward z (in place on tmp)
+    dim3 gz((f.n1 * f.n2 + 15) / 16);
+    hipLaunchKernelGGL((fd_z_pass<PREC, KB>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.UT[2], f.U[2],
+                       f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // backward x and y
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.U[0], f.U[1], f.n1,
+                       f.n2);
+    return hipGetLastError();
+}
+
+template <int PREC>
+hipError_t fused_any(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
+    const int nmax = f.n1 > f.n2 ? (f.n1 > f.n3 ? f.n1 : f.n3) : (f.n2 > f.n3 ? f.n2 : f.n3);
+    switch ((nmax + 15) / 16) {
+        case 1: return fused_kb<PREC, 1>(f, s);
+        case 2: return fused_kb<PREC, 2>(f, s);
+        case 3: return fused_kb<PREC, 3>(f, s);
+        case 4: return fused_kb<PREC, 4>(f, s);
+        case 5: return fused_kb<PREC, 5>(f, s);
+        case 6: return fused_kb<PREC, 6>(f, s);
+        case 7: return fused_kb<PREC, 7>(f, s);
+        case 8: return fused_kb<PREC, 8>(f, s);
+        case 9: return fused_kb<PREC, 9>(f, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_fd_mode(const FdModeArgs<double, double>& p, hipStream_t s) { return launch_any<1>(p, s); }
 hipError_t launch_fd_mode(const FdModeArgs<float, float>& p, hipStream_t s) { return launch_any<2>(p, s); }
 hipError_t launch_fd_mode(const FdModeArgs<float, __bf16>& p, hipStream_t s) { return launch_any<4>(p, s); }
+hipError_t launch_fd_fused(const FdFusedArgs<double>& f, hipStream_t s) { return fused_any<1>(f, s); }
+hipError_t launch_fd_fused(const FdFusedArgs<float>& f, hipStream_t s) { return fused_any<2>(f, s); }
 
 }  // namespace wqfd
