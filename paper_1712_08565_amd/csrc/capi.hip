@@ -153,6 +153,7 @@ struct FusedHost {
     int zchunk = 0;
     std::vector<int> sched;         // interval records (wqfd::FusedSched), all z ranges
     std::vector<int> sched_off;     // first record of each z range, plus the total
+    std::vector<int> schedT, schedT_off;   // the same for the transposed apply
 };
 
 // Length of the z range of one workgroup of the fused apply.  The grid is
@@ -186,9 +187,14 @@ int choose_zchunk(int nq3, int tiles, int slots, int p) {
 // most NU - 1 planes ahead of the window) and stage the DOF plane after it.
 // Returns false if the windows do not advance by at most one plane per
 // quadrature plane (the kernel then is not used).
-bool fused_schedule(const std::vector<int>& bs3, const std::vector<int>& wts3, int n3, int p, int k0, int k1,
-                    std::vector<int>& out) {
-    const int RT = p + 1, RO = p + 2, NU = 3;
+// ins/IN: start and length of the input window of DOF planes per quadrature
+// plane (forward: B3 band, p + 1; transposed: W3 band, p + 2); outs/OUT: the
+// same for the output ring (forward: W3, p + 2; transposed: B3, p + 1).
+bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>& outs, int OUT, int n3, int k0,
+                    int k1, std::vector<int>& out) {
+    const int RT = IN, RO = OUT, NU = 3;
+    const std::vector<int>& bs3 = ins;
+    const std::vector<int>& wts3 = outs;
     const int tmax = bs3[k1 - 1] + RT - 1;
     int tnext = bs3[k0], nwin = 0, tprod = tnext, tstage = tnext, obase = wts3[k0], k = k0, eflush = 0;
     int nfw = 0, nred = 0, fl_slot = 0, red_slot = 0, red_i3 = 0, fl_i3 = 0;
@@ -345,11 +351,17 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
     }
     fh.sched.clear();
     fh.sched_off.clear();
+    fh.schedT.clear();
+    fh.schedT_off.clear();
     for (int k0 = 0; k0 < nq3; k0 += fh.zchunk) {
+        const int k1 = std::min(nq3, k0 + fh.zchunk);
         fh.sched_off.push_back((int)(fh.sched.size() / 4));
-        if (!fused_schedule(fh.bs3, fh.wts3, n3, p, k0, std::min(nq3, k0 + fh.zchunk), fh.sched)) return false;
+        fh.schedT_off.push_back((int)(fh.schedT.size() / 4));
+        if (!fused_schedule(fh.bs3, RT, fh.wts3, RO, n3, k0, k1, fh.sched)) return false;
+        if (!fused_schedule(fh.wts3, RO, fh.bs3, RT, n3, k0, k1, fh.schedT)) return false;
     }
     fh.sched_off.push_back((int)(fh.sched.size() / 4));
+    fh.schedT_off.push_back((int)(fh.schedT.size() / 4));
     return true;
 }
 
@@ -432,7 +444,7 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     FusedHost fh;
     const bool fused_ok = build_fused_tables(sp, p, fh) && !std::getenv("WQFD_STAGED");
     size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0};
-    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_sched = 0, f_soff = 0;
+    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_sched = 0, f_soff = 0, f_schedT = 0, f_soffT = 0;
     if (fused_ok) {
         for (int l = 0; l < 2; ++l) {
             f_tiles64[l] = pk.add(fh.tiles[l].data(), fh.tiles[l].size() * 8);
@@ -448,6 +460,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
         f_cz32 = pk.add(c32.data(), c32.size() * 4);
         f_sched = pk.add(fh.sched.data(), fh.sched.size() * sizeof(int));
         f_soff = pk.add(fh.sched_off.data(), fh.sched_off.size() * sizeof(int));
+        f_schedT = pk.add(fh.schedT.data(), fh.schedT.size() * sizeof(int));
+        f_soffT = pk.add(fh.schedT_off.data(), fh.schedT_off.size() * sizeof(int));
     }
     // workspace layout
     size_t off = 0;
@@ -532,6 +546,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
             fz.zchunk = fh.zchunk;
             fz.sched = reinterpret_cast<const int*>(tb + f_sched);
             fz.sched_off = reinterpret_cast<const int*>(tb + f_soff);
+            fz.schedT = reinterpret_cast<const int*>(tb + f_schedT);
+            fz.schedT_off = reinterpret_cast<const int*>(tb + f_soffT);
         };
         fill(o.fz64, f_tiles64[0], f_tiles64[1], f_cz64, o.C64);
         fill(o.fz32, f_tiles32[0], f_tiles32[1], f_cz32, o.C32);

@@ -37,6 +37,9 @@ struct FusedArgs {
     // z range r uses records sched_off[r] .. sched_off[r + 1] - 1
     const int* sched = nullptr;
     const int* sched_off = nullptr;
+    // the same for the transposed apply (input window W3, output ring B3)
+    const int* schedT = nullptr;
+    const int* schedT_off = nullptr;
 };
 
 // One interval of the fused apply's pipeline (between two workgroup barriers),
@@ -57,5 +60,7 @@ hipError_t fused_resident_slots(int p, int* slots);
 
 template <typename T>
 hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_apply_T(const FusedArgs<T>& a, int p, hipStream_t s);
 
 }  // namespace wqfd

@@ -365,6 +365,261 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused transposed apply w = K~^T v = sum_ab B^(b)T D^(ab) W^(ab)T v, the same
+// pipeline with the roles of the factors exchanged:
+//   input side (MFMA waves): each DOF plane i3 of v entering the z window is
+//     transformed in x and y with the transposed weights of all nine fields,
+//       Y_f[q2][q1] = sum_i2 W2^(v2)[i2][q2] sum_i1 W1^(v1)[i1][q1] V[i2][i1],
+//     (one x product per weight variant v1 shared by its fields), into a ring
+//     of NU planes of nine blocks in LDS;
+//   column waves (group beta): keep the last p+2 planes of Y_(alpha beta),
+//     alpha = x, y, z, per column, contract them with W3 (z), form
+//     phi_beta = sum_alpha C_(alpha beta) Y_(alpha beta) and accumulate
+//     B3^(b3)T phi_beta into a ring of the p+1 output planes it touches;
+//   retired output planes (3 fields): x and y products with the transposed B
+//     factors (fields x and z share B2 and are summed before it) and atomics.
+// Operands with transposed LDS reads use the accumulator row mapping as K
+// index, as in the forward kernel.
+template <typename T, int P>
+__global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> a) {
+    constexpr int RT = P + 1;              // output ring (DOF planes, B band)
+    constexpr int RO = P + 2;              // input window (DOF planes, W band)
+    constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
+    constexpr int NU = 3;                  // input planes in flight
+    __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
+    __shared__ T sV[2][BLK];               // staged planes of v (input block IX, IY)
+    __shared__ T sU[NU][9][BLK];           // Y_f of produced planes
+    __shared__ T sP[2][3][BLK];            // phi_beta of retired output planes
+    __shared__ T sR[2][2][BLK];            // partial output blocks
+    __shared__ T sZ[kMaxZ * CZ];           // z coefficients of this workgroup's planes
+
+    using acc_t = typename MF<T>::acc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool mrole = wave >= 12;
+    const int ct = tid & 255;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int q1l = ct & 15, q2l = ct >> 4;
+    const int beta = wave >> 2;
+    const int mw = wave - 12;
+
+    const int nblk = gridDim.x, b = blockIdx.x;
+    const int base = nblk / 8, rem = nblk % 8, xcd = b % 8, slot = b / 8;
+    const int lin = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
+    const int t1 = lin % a.ntx;
+    const int t2 = (lin / a.ntx) % a.nty;
+    const int zc = lin / (a.ntx * a.nty);
+    const int k0 = zc * a.zchunk;
+    const int k1 = min(a.nq3, k0 + a.zchunk);
+    if (k0 >= k1) return;
+
+    const int q1 = t1 * 16 + q1l, q2 = t2 * 16 + q2l;
+    const bool active = q1 < a.nq1 && q2 < a.nq2;
+    const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
+    const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
+
+    for (int idx = tid; idx < 12 * 256; idx += 1024) {
+        const int tl = idx >> 8, e = idx & 255;
+        const T* src;
+        if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
+        else if (tl < 4) src = a.tilesY + ((size_t)t2 * 6 + (tl - 2)) * 256;
+        else if (tl < 8) src = a.tilesX + ((size_t)t1 * 6 + 2 + (tl - 4)) * 256;
+        else src = a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;
+        sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
+    }
+    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
+    const int r0 = a.schedT_off[zc], nrec = a.schedT_off[zc + 1] - r0;
+    const int* __restrict__ rec = a.schedT + 4 * (size_t)r0;
+
+    // A operand read transposed from a [k][m] LDS block, K index = accumulator row
+    auto ld_accAt = [&](T (&av)[4], const T* A) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) av[s] = A[MF<T>::drow(kb, s) * LD + cl];
+    };
+    auto mm_acc = [&](acc_t& Z, const T (&av)[4], const acc_t& X) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Z = MF<T>::mma(av[s], X[s], Z);
+    };
+    // x product with the B operand read as [k][n] from LDS: c += A[m][k] B[k][n]
+    auto mm_x = [&](acc_t& c, const T* A, const T* B) {
+        T av[4], bv[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            av[s] = A[cl * LD + 4 * s + kb];
+            bv[s] = B[(4 * s + kb) * LD + cl];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) c = MF<T>::mma(av[s], bv[s], c);
+    };
+
+    lds_barrier();
+
+    if (mrole) {
+        // MFMA waves.  Input planes: the x product with W1^(v1), then the y
+        // products of the fields with that v1 (field f = 3 alpha + beta has
+        // v1 = 2[alpha = x] + [beta = x], v2 = 2[alpha = y] + [beta = y]):
+        //   wave 12: v1 = 0 -> {yy, yz, zy, zz};  wave 13: v1 = 1 -> {yx, zx};
+        //   wave 14: v1 = 2 -> {xy, xz} and v1 = 3 -> {xx}.
+        // Retired planes: wave 13 field y (B1, then B-dot2), wave 15 fields x and z
+        // (X = R_x B-dot1 + R_z B1, then B2), wave 15 also reduces and adds to w.
+        // Wave 14 stages the planes of v (loaded two intervals ahead).
+        const bool stager = mw == 2;
+        T vq0[4], vq1[4];
+        auto vload = [&](T (&dst)[4], int i3) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = lane + 64 * q;
+                const int i1 = I1 + (e & 15), i2 = I2 + (e >> 4);
+                dst[q] = (i1 < a.n1 && i2 < a.n2 && i3 >= 0 && i3 < a.n3)
+                             ? a.v[((size_t)i3 * a.n2 + i2) * a.n1 + i1] : T(0);
+            }
+        };
+        if (stager && nrec > 0) {
+            const int t0 = rec[3];
+            vload((t0 & 1) ? vq1 : vq0, t0);
+            vload((t0 & 1) ? vq0 : vq1, t0 + 1);
+        }
+        // y products of one x result: fields given as (f, v2) pairs
+        auto yprods = [&](const acc_t& A, int us, int f, int v2) {
+            T wv[4];
+            ld_accAt(wv, sCoef[8 + v2]);
+            acc_t Y = {0, 0, 0, 0};
+            mm_acc(Y, wv, A);
+            store16<T>(sU[us][f], Y, cl, kb);
+        };
+        for (int r = 0; r < nrec; ++r) {
+            const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
+            if (((fl >> 7) & 1) && mw < 3) {
+                const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
+                if (mw == 0) {
+                    acc_t A = {0, 0, 0, 0};
+                    mm_x(A, sV[vs], sCoef[4 + 0]);
+                    yprods(A, us, 4, 3);
+                    yprods(A, us, 5, 2);
+                    yprods(A, us, 7, 1);
+                    yprods(A, us, 8, 0);
+                } else if (mw == 1) {
+                    acc_t A = {0, 0, 0, 0};
+                    mm_x(A, sV[vs], sCoef[4 + 1]);
+                    yprods(A, us, 3, 2);
+                    yprods(A, us, 6, 0);
+                } else {
+                    acc_t A2 = {0, 0, 0, 0}, A3 = {0, 0, 0, 0};
+                    mm_x(A2, sV[vs], sCoef[4 + 2]);
+                    mm_x(A3, sV[vs], sCoef[4 + 3]);
+                    yprods(A2, us, 1, 1);
+                    yprods(A2, us, 2, 0);
+                    yprods(A3, us, 0, 0);
+                }
+            }
+            if (((fl >> 9) & 1) && (mw == 1 || mw == 3)) {
+                const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
+                acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
+                T wv[4];
+                if (mw == 1) {                                   // beta = y: B1, then B-dot2
+                    mm_x(X, sP[ps][1], sCoef[0]);
+                    ld_accAt(wv, sCoef[3]);
+                } else {                                         // beta = x (B-dot1) and z (B1), then B2
+                    mm_x(X, sP[ps][0], sCoef[1]);
+                    mm_x(X, sP[ps][2], sCoef[0]);
+                    ld_accAt(wv, sCoef[2]);
+                }
+                mm_acc(Z, wv, X);
+                store16<T>(sR[rs][mw == 1 ? 0 : 1], Z, cl, kb);
+            }
+            if (stager && ((fl >> 8) & 1)) {
+                const int sl = (fl >> 20) & 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = lane + 64 * q;
+                    sV[sl][(e >> 4) * LD + (e & 15)] = sl ? vq1[q] : vq0[q];
+                }
+                if (sl) vload(vq1, ts + 2); else vload(vq0, ts + 2);
+            }
+            if (mw == 3 && ((fl >> 10) & 1)) {
+                const int rs = (fl >> 15) & 1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = lane + 64 * q;
+                    const int el = (e >> 4) * LD + (e & 15);
+                    const T sum = sR[rs][0][el] + sR[rs][1][el];
+                    const int j1 = J1 + (e & 15), j2 = J2 + (e >> 4);
+                    if (j1 < a.n1 && j2 < a.n2 && sum != T(0))
+                        atomicAdd(&a.w[((size_t)red_i3 * a.n2 + j2) * a.n1 + j1], sum);
+                }
+            }
+            lds_barrier();
+        }
+    } else {
+        // column waves: fields (alpha, beta), alpha = x, y, z
+        T Yw[3][RO];                        // input window of Y_(alpha beta)
+        T orng[RT];                         // output ring of B3^T phi_beta
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int s = 0; s < RO; ++s) Yw[al][s] = T(0);
+#pragma unroll
+        for (int s = 0; s < RT; ++s) orng[s] = T(0);
+        const int pidx = __builtin_amdgcn_readfirstlane(beta == 0 ? 0x430 : beta == 1 ? 0x513 : 0x254);
+        const size_t Nq = a.Nq;
+        const size_t plane = (size_t)a.nq1 * a.nq2;
+        const size_t poff[3] = {((pidx >> 0) & 15) * Nq, ((pidx >> 4) & 15) * Nq, ((pidx >> 8) & 15) * Nq};
+        const T* Ccol = a.C + ((size_t)q2 * a.nq1 + q1);
+        T Cn[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) Cn[al] = active ? Ccol[poff[al] + (size_t)k0 * plane] : T(0);
+        auto valu_plane = [&](int kq) {
+            T C[3];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) C[al] = Cn[al];
+            if (kq + 1 < k1) {
+                const size_t ko = (size_t)(kq + 1) * plane;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) Cn[al] = active ? Ccol[poff[al] + ko] : T(0);
+            }
+            const T* cz = sZ + (size_t)(kq - k0) * CZ;
+            // z weight variant of field (alpha, beta): 2 [alpha = z] + [beta = z]
+            const T* w01 = cz + 2 * RT + (beta == 2 ? 1 : 0) * RO;
+            const T* w2 = cz + 2 * RT + (beta == 2 ? 3 : 2) * RO;
+            T y0 = T(0), y1 = T(0), y2 = T(0);
+#pragma unroll
+            for (int s = 0; s < RO; ++s) {
+                y0 += w01[s] * Yw[0][s];
+                y1 += w01[s] * Yw[1][s];
+                y2 += w2[s] * Yw[2][s];
+            }
+            const T phi = C[0] * y0 + C[1] * y1 + C[2] * y2;
+            const T* bz = cz + (beta == 2 ? RT : 0);                // B3 row, or B-dot3 for beta = z
+#pragma unroll
+            for (int s = 0; s < RT; ++s) orng[s] += bz[s] * phi;
+        };
+        for (int r = 0; r < nrec; ++r) {
+            const int fl = rec[4 * r], kq = rec[4 * r + 1];
+            const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
+            const int nsteps = max(nv, max(in_at, out_at) + 1);
+            for (int j = 0; j < nsteps; ++j) {
+                if (j == in_at) {
+                    const int us = (fl >> 11) & 3;
+#pragma unroll
+                    for (int al = 0; al < 3; ++al) {
+#pragma unroll
+                        for (int s = 0; s < RO - 1; ++s) Yw[al][s] = Yw[al][s + 1];
+                        Yw[al][RO - 1] = sU[us][3 * al + beta][q2l * LD + q1l];
+                    }
+                }
+                if (j == out_at) {
+                    if ((fl >> 6) & 1) sP[(fl >> 13) & 1][beta][q2l * LD + q1l] = orng[0];
+#pragma unroll
+                    for (int s = 0; s < RT - 1; ++s) orng[s] = orng[s + 1];
+                    orng[RT - 1] = T(0);
+                }
+                if (j < nv) valu_plane(kq + j);
+            }
+            lds_barrier();
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = T(0);
@@ -375,6 +630,14 @@ hipError_t launch_p(const FusedArgs<T>& a, hipStream_t s) {
     if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.sched || !a.sched_off) return hipErrorInvalidValue;
     const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
     hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t launch_tp(const FusedArgs<T>& a, hipStream_t s) {
+    if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.schedT || !a.schedT_off) return hipErrorInvalidValue;
+    const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
+    hipLaunchKernelGGL((wq_apply_T_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
@@ -407,6 +670,26 @@ hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
 }
+
+template <typename T>
+hipError_t launch_fused_apply_T(const FusedArgs<T>& a, int p, hipStream_t s) {
+    const size_t N = (size_t)a.n1 * a.n2 * a.n3;
+    size_t g = (N + 255) / 256;
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    switch (p) {
+        case 2: return launch_tp<T, 2>(a, s);
+        case 3: return launch_tp<T, 3>(a, s);
+        case 4: return launch_tp<T, 4>(a, s);
+        case 5: return launch_tp<T, 5>(a, s);
+        case 6: return launch_tp<T, 6>(a, s);
+        case 7: return launch_tp<T, 7>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_fused_apply_T<double>(const FusedArgs<double>&, int, hipStream_t);
+template hipError_t launch_fused_apply_T<float>(const FusedArgs<float>&, int, hipStream_t);
 
 hipError_t fused_resident_slots(int p, int* slots) {
     switch (p) {
