@@ -9,8 +9,8 @@ One step = for every degree p:
   * R timed FP64 operator applies w = K~ v (HIP events around each launch on the
     stream the library runs on),
   * one FP64 right-preconditioned BiCGStab solve to relative residual 1e-10,
-  * one mixed-precision solve (FP32 apply, BF16 FD, FP64 refinement) to the
-    same residual,
+  * one mixed-precision solve (FP32 apply, FP32 FD by default, FP64 refinement)
+    to the same residual,
   * the adjoint of J = 1/2 |u|^2 at the FP64 solution: transposed solve
     K~^T lam = u to 1e-10, then dJ/dC (six planes) and dJ/df at every
     quadrature point, and R/4 timed transposed applies.
@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-solve", action="store_true", help="time the applies only")
+    ap.add_argument("--mixed-fd", choices=("f32", "bf16"), default="f32", help="FD precision of the inner solves")
+    ap.add_argument("--mixed-tau", type=float, default=1e-4, help="inner relative tolerance of the refinement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB per step (counter calibration)")
     args = ap.parse_args()
@@ -142,6 +144,8 @@ def main():
     from paper_1712_08565_amd import problem, wqfd
 
     torch.cuda.set_device(0)
+    MIX_FD = wqfd.WQ_F32 if args.mixed_fd == "f32" else wqfd.WQ_BF16
+    MIX_TAU = args.mixed_tau
 
     def solve(P, kind, rtol, x=None):
         dp = P["dp"]
@@ -150,8 +154,8 @@ def main():
             _, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, x=x, rtol=rtol, maxit=2000, ws=P["kws"])
             P["last"] = (it, 0, res)
         else:
-            _, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, x=x, fd_prec=wqfd.WQ_BF16, rtol=rtol,
-                                                 tau_inner=1e-3, ws=P["iws"])
+            _, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, x=x, fd_prec=MIX_FD, rtol=rtol,
+                                                 tau_inner=MIX_TAU, ws=P["iws"])
             P["last"] = (outer, inner, res)
         return x
 
@@ -225,8 +229,8 @@ def main():
                 xm = torch.zeros_like(P["x"])
                 m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 m0.record(stream)
-                _, outer, inner, mres = wqfd.ir_solve(dp.A, dp.P, dp.b, x=xm, fd_prec=wqfd.WQ_BF16, rtol=1e-10,
-                                                      tau_inner=1e-3, ws=P["iws"])
+                _, outer, inner, mres = wqfd.ir_solve(dp.A, dp.P, dp.b, x=xm, fd_prec=MIX_FD, rtol=1e-10,
+                                                      tau_inner=MIX_TAU, ws=P["iws"])
                 m1.record(stream)
                 eq = {}
                 for kind in ("fp64", "mixed"):
@@ -335,8 +339,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded spline ring geometry, K = I, oscillating source)",
         "config": {"workload": f"thick quarter ring, {args.n_el}^3 elements, degrees {args.degrees}, "
-                               f"FP64 apply + FP64 BiCGStab/FD and mixed FP32/BF16 IR solves to rel.res 1e-10",
-                   "n_el": args.n_el, "degrees": degrees, "applies_per_degree_per_step": args.reps},
+                               f"FP64 apply + FP64 BiCGStab/FD and mixed-precision IR solves to rel.res 1e-10, "
+                               f"adjoint gradient",
+                   "n_el": args.n_el, "degrees": degrees, "applies_per_degree_per_step": args.reps,
+                   "mixed": {"inner_fd": args.mixed_fd, "inner_apply": "f32", "tau_inner": args.mixed_tau}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "wq_apply (FP64)", "launches": n_apply,

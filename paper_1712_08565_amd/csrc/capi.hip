@@ -875,7 +875,8 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
         HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
         int it = 0;
         double rel = 0;
-        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tau_inner, maxit_inner, kws, &it, &rel, err, s);
+        const double tol = std::max(tau_inner, 0.5 * rtol * nb / nr);
+        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s);
         *inner_total += it;
         if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
         HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");
