@@ -799,11 +799,15 @@ int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x, do
     wqfd::LinOp Aop = [op, transpose](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_apply(*op, WQ_F64, in, o, transpose != 0, st);
     };
+    wqfd::LinOp Aacc = [op, transpose](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F64, in, o, transpose != 0, st, true);
+    };
     wqfd::LinOp Mop = [pc](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_fd_apply(*pc, WQ_F64, in, o, st);
     };
     std::string err;
-    int rc = wqfd::bicgstab<double>(Aop, Mop, op->N, b, x, false, rtol, maxit, ws, iters, relres, err, s);
+    int rc = wqfd::bicgstab<double>(Aop, Mop, op->N, b, x, false, rtol, maxit, ws, iters, relres, err, s,
+                                    op->fused ? &Aacc : nullptr);
     if (rc) return fail(rc, err);
     return WQ_OK;
 }
@@ -845,6 +849,9 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     wqfd::LinOp A32 = [op](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_apply(*op, WQ_F32, in, o, false, st);
     };
+    wqfd::LinOp A32acc = [op](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F32, in, o, false, st, true);
+    };
     wqfd::LinOp M32 = [pc, fd_prec](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_fd_apply(*pc, fd_prec, in, o, st);
     };
@@ -876,7 +883,8 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
         int it = 0;
         double rel = 0;
         const double tol = std::max(tau_inner, 0.5 * rtol * nb / nr);
-        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s);
+        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s,
+                                   op->fused ? &A32acc : nullptr);
         *inner_total += it;
         if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
         HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");

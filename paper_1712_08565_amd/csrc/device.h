@@ -79,7 +79,9 @@ struct FdPc {
 // MF-WQ operator (wq_kernels.hip)
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask);
 hipError_t launch_set_coef(const WqOp& op, int k_kind, const double* K_q, hipStream_t s);
-hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s);
+// w_zeroed: the caller has cleared w (the fused kernels then skip their own clear)
+hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s,
+                        bool w_zeroed = false);
 hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s);
 hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s);
 hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s);

@@ -40,6 +40,7 @@ struct FusedArgs {
     // the same for the transposed apply (input window W3, output ring B3)
     const int* schedT = nullptr;
     const int* schedT_off = nullptr;
+    bool w_zeroed = false;          // w already cleared by the caller
 };
 
 // One interval of the fused apply's pipeline (between two workgroup barriers),

@@ -106,33 +106,69 @@ __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part,
     }
 }
 
-// p = r + beta (p - omega v),  beta = (rho / rho_old) (alpha / omega)
+// Sum of nb partials, identical in every block (same partition and order), so
+// a kernel can finish a reduction itself instead of a separate launch.
+__device__ inline double sum_partials(const double* __restrict__ part, int nb, double* sh) {
+    double a = 0;
+    for (int i = threadIdx.x; i < nb; i += kT) a += part[i];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) sh[kT / 64] = a;
+    __syncthreads();
+    const double r = sh[kT / 64];
+    __syncthreads();
+    return r;
+}
+
+// p = r + beta (p - omega v),  beta = (rho / rho_old) (alpha / omega); v is
+// then cleared when the next product accumulates into it
 template <typename T>
-__global__ __launch_bounds__(kT) void upd_p(T* __restrict__ p, const T* __restrict__ r, const T* __restrict__ v,
-                                            const double* __restrict__ sc, size_t n, int first) {
+__global__ __launch_bounds__(kT) void upd_p(T* __restrict__ p, const T* __restrict__ r, T* __restrict__ v,
+                                            const double* __restrict__ sc, size_t n, int first, int clear_v) {
     const double beta = first ? 0.0 : (sc[S_RHO] / sc[S_RHO_OLD]) * (sc[S_ALPHA] / sc[S_OMEGA]);
     const double om = sc[S_OMEGA];
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
         p[i] = first ? r[i] : (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
+        if (clear_v) v[i] = T(0);
+    }
 }
 
-// s = r - alpha v
+// alpha = rho / (r^, v) from the partials of (r^, v);  s = r - alpha v;
+// t cleared for the next accumulating product
 template <typename T>
 __global__ __launch_bounds__(kT) void upd_s(T* __restrict__ s, const T* __restrict__ r, const T* __restrict__ v,
-                                            const double* __restrict__ sc, size_t n) {
-    const double al = sc[S_ALPHA];
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
+                                            T* __restrict__ t, double* __restrict__ sc, const double* __restrict__ part,
+                                            int nb, size_t n, int clear_t) {
+    __shared__ double sh[kT / 64 + 1];
+    const double rv = sum_partials(part, nb, sh);
+    const double al = sc[S_RHO] / rv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_RV] = rv;
+        sc[S_ALPHA] = al;
+    }
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
         s[i] = (T)((double)r[i] - al * (double)v[i]);
+        if (clear_t) t[i] = T(0);
+    }
 }
 
-// x += alpha p^ + omega s^ ; r = s - omega t ; partial (r^, r) and (r, r)
+// omega = (t, s) / (t, t) from their partials;  x += alpha p^ + omega s^ ;
+// r = s - omega t ; partials of (r^, r) and (r, r) into part_out
 template <typename T>
 __global__ __launch_bounds__(kT) void upd_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ ph,
                                              const T* __restrict__ sh_, const T* __restrict__ s,
                                              const T* __restrict__ t, const T* __restrict__ rh,
-                                             const double* __restrict__ sc, size_t n, double* __restrict__ part) {
-    __shared__ double sh[kT / 64];
-    const double al = sc[S_ALPHA], om = sc[S_OMEGA];
+                                             double* __restrict__ sc, const double* __restrict__ part_in, int nb,
+                                             size_t n, double* __restrict__ part) {
+    __shared__ double sh[kT / 64 + 1];
+    const double ts = sum_partials(part_in, nb, sh);
+    const double tt = sum_partials(part_in + nb, nb, sh);
+    const double om = tt != 0.0 ? ts / tt : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[S_TS] = ts;
+        sc[S_TT] = tt;
+        sc[S_OMEGA] = om;
+    }
+    const double al = sc[S_ALPHA];
     double a0 = 0, a1 = 0;
     for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
         x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)sh_[i]);
@@ -201,13 +237,13 @@ constexpr int WQ_EHIP_CODE = -5;
 template <typename T>
 struct Vecs {
     T *r, *rh, *p, *v, *s, *t, *ph, *sh;
-    double *sc, *part;
+    double *sc, *part, *part2;
 };
 
 template <typename T>
 size_t vec_bytes(size_t N) {
     const size_t v = (N * sizeof(T) + 255) / 256 * 256;
-    return 8 * v + 256 + (size_t)3 * kMaxBlocks * sizeof(double) + 256;
+    return 8 * v + 256 + (size_t)5 * kMaxBlocks * sizeof(double) + 256;
 }
 
 template <typename T>
@@ -223,6 +259,7 @@ Vecs<T> carve(void* ws, size_t N) {
     V.sc = reinterpret_cast<double*>(c);
     c += 256;
     V.part = reinterpret_cast<double*>(c);
+    V.part2 = V.part + 3 * kMaxBlocks;
     return V;
 }
 
@@ -242,7 +279,11 @@ hipError_t launch_axpy_f32_to_f64(const float* d, double* x, size_t n, double sc
 
 template <typename T>
 int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0_zero, double tol, int maxit,
-             void* ws, int* iters, double* relres, std::string& err, hipStream_t s) {
+             void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc) {
+    // A_acc: the same operator adding into a cleared output (the update kernels
+    // clear v and t just before the products that fill them)
+    const LinOp& Aa = A_acc ? *A_acc : A;
+    const int clear = A_acc ? 1 : 0;
     Vecs<T> V = carve<T>(ws, N);
     const int nb = nblocks(N);
     const dim3 g(nb), blk(kT);
@@ -295,20 +336,18 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
         return 0;
     }
     for (int it = 1; it <= maxit; ++it) {
-        hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, it == 1 ? 1 : 0);
+        hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, it == 1 ? 1 : 0, clear);
         KR_TRY(M(V.p, V.ph, s));
-        KR_TRY(A(V.ph, V.v, s));
+        KR_TRY(Aa(V.ph, V.v, s));
         hipLaunchKernelGGL((dot_partial<T, 1>), g, blk, 0, s, V.rh, V.v, (const T*)nullptr, (const T*)nullptr,
                            (const T*)nullptr, (const T*)nullptr, N, V.part);
-        hipLaunchKernelGGL((dot_final<1>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_ALPHA);
-        hipLaunchKernelGGL(upd_s<T>, g, blk, 0, s, V.s, V.r, V.v, V.sc, N);
+        hipLaunchKernelGGL(upd_s<T>, g, blk, 0, s, V.s, V.r, V.v, V.t, V.sc, V.part, nb, N, clear);
         KR_TRY(M(V.s, V.sh, s));
-        KR_TRY(A(V.sh, V.t, s));
+        KR_TRY(Aa(V.sh, V.t, s));
         hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.s, V.t, V.t, (const T*)nullptr,
                            (const T*)nullptr, N, V.part);
-        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_OMEGA);
-        hipLaunchKernelGGL(upd_xr<T>, g, blk, 0, s, x, V.r, V.ph, V.sh, V.s, V.t, V.rh, V.sc, N, V.part);
-        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, 0, (int)F_RHO_RR);
+        hipLaunchKernelGGL(upd_xr<T>, g, blk, 0, s, x, V.r, V.ph, V.sh, V.s, V.t, V.rh, V.sc, V.part, nb, N, V.part2);
+        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part2, nb, V.sc, 0, (int)F_RHO_RR);
         KR_TRY(hipGetLastError());
         KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
         KR_TRY(hipStreamSynchronize(s));
@@ -348,9 +387,9 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
 }
 
 template int bicgstab<double>(const LinOp&, const LinOp&, size_t, const double*, double*, bool, double, int,
-                              void*, int*, double*, std::string&, hipStream_t);
+                              void*, int*, double*, std::string&, hipStream_t, const LinOp*);
 template int bicgstab<float>(const LinOp&, const LinOp&, size_t, const float*, float*, bool, double, int, void*,
-                             int*, double*, std::string&, hipStream_t);
+                             int*, double*, std::string&, hipStream_t, const LinOp*);
 
 // FP64 norm of a vector (two-pass), synchronising.
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s) {

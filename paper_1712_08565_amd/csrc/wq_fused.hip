@@ -659,7 +659,7 @@ hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
     const size_t N = (size_t)a.n1 * a.n2 * a.n3;
     size_t g = (N + 255) / 256;
     if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    if (!a.w_zeroed) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
     switch (p) {
         case 2: return launch_p<T, 2>(a, s);
         case 3: return launch_p<T, 3>(a, s);
@@ -676,7 +676,7 @@ hipError_t launch_fused_apply_T(const FusedArgs<T>& a, int p, hipStream_t s) {
     const size_t N = (size_t)a.n1 * a.n2 * a.n3;
     size_t g = (N + 255) / 256;
     if (g > 4096) g = 4096;
-    hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    if (!a.w_zeroed) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
     switch (p) {
         case 2: return launch_tp<T, 2>(a, s);
         case 3: return launch_tp<T, 3>(a, s);

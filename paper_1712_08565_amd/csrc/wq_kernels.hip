@@ -326,17 +326,20 @@ hipError_t launch_set_coef(const WqOp& op, int k_kind, const double* K_q, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s) {
+hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool transpose, hipStream_t s,
+                        bool w_zeroed) {
     if (op.fused) {
         if (prec == 1) {
             FusedArgs<double> a = op.fz64;
             a.v = static_cast<const double*>(v);
             a.w = static_cast<double*>(w);
+            a.w_zeroed = w_zeroed;
             return transpose ? launch_fused_apply_T<double>(a, op.p, s) : launch_fused_apply<double>(a, op.p, s);
         }
         FusedArgs<float> a = op.fz32;
         a.v = static_cast<const float*>(v);
         a.w = static_cast<float*>(w);
+        a.w_zeroed = w_zeroed;
         return transpose ? launch_fused_apply_T<float>(a, op.p, s) : launch_fused_apply<float>(a, op.p, s);
     }
     if (prec == 1) {
