@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-solve", action="store_true", help="time the applies only")
+    ap.add_argument("--workloads", default="",
+                    help="comma-separated named workloads instead of the default ring (e.g. ring96_p5,twist128_p6)")
     ap.add_argument("--mixed-fd", choices=("f32", "bf16"), default="f32", help="FD precision of the inner solves")
     ap.add_argument("--mixed-tau", type=float, default=1e-4, help="inner relative tolerance of the refinement")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -160,9 +162,14 @@ def main():
         return x
 
     degrees = [int(x) for x in args.degrees.split(",")]
+    if args.workloads:                       # named workloads (other full-size configurations)
+        cases = [(name, synth.workload(name)) for name in args.workloads.split(",")]
+    else:
+        cases = [(f"p{p}", synth.Workload(f"ring{args.n_el}_p{p}", args.n_el, p, "ring", 0.02, "identity", "paper"))
+                 for p in degrees]
+    keys = [k for k, _ in cases]
     probs = {}
-    for p in degrees:
-        wl = synth.Workload(f"ring{args.n_el}_p{p}", args.n_el, p, "ring", 0.02, "identity", "paper")
+    for p, wl in cases:
         t0 = time.perf_counter()
         dp = problem.build(wl, wqfd.WQ_F64 | wqfd.WQ_F32, wqfd.WQ_F64 | wqfd.WQ_F32 | wqfd.WQ_BF16)
         torch.cuda.synchronize()
@@ -178,7 +185,9 @@ def main():
         probs[p] = dict(dp=dp, v=v, w=w, kws=kws, iws=iws, xref=xref, x=torch.zeros_like(v),
                         N=dp.A.N, Nq=dp.A.Nq, setup_s=time.perf_counter() - t0)
         if not args.no_solve:
-            probs[p].update(lam=torch.zeros_like(v), gK=torch.empty(6 * dp.A.Nq, dtype=torch.float64, device="cuda"),
+            planes = 1 if dp.A.k_kind == wqfd.WQ_K_SCALAR else 6
+            probs[p].update(lam=torch.zeros_like(v),
+                            gK=torch.empty(planes * dp.A.Nq, dtype=torch.float64, device="cuda"),
                             gf=torch.empty(dp.A.Nq, dtype=torch.float64, device="cuda"))
         if not args.no_solve:
             nref = torch.linalg.norm(xref).item()
@@ -204,14 +213,14 @@ def main():
     stream = torch.cuda.current_stream()
     rec = {p: dict(apply_ms=[], fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
                    mix_err=[], fp64_eq_ms=[], fp64_eq_err=[], fp64_eq_it=[], mixed_eq_ms=[], mixed_eq_err=[],
-                   mixed_eq_it=[], adj_ms=[], adj_it=[], applyT_ms=[]) for p in degrees}
+                   mixed_eq_it=[], adj_ms=[], adj_it=[], applyT_ms=[]) for p in keys}
     probe = None
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
         probe = (torch.ones(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"))
 
     def one_step(record: bool):
-        for p in degrees:
+        for p in keys:
             P = probs[p]
             dp = P["dp"]
             evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -292,16 +301,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    tot_dof = sum(probs[p]["N"] * len(rec[p]["apply_ms"]) for p in degrees)
-    tot_s = sum(sum(rec[p]["apply_ms"]) for p in degrees) / 1e3
-    tot_bytes = sum((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) * len(rec[p]["apply_ms"]) for p in degrees)
-    n_apply = sum(len(rec[p]["apply_ms"]) for p in degrees)
+    tot_dof = sum(probs[p]["N"] * len(rec[p]["apply_ms"]) for p in keys)
+    tot_s = sum(sum(rec[p]["apply_ms"]) for p in keys) / 1e3
+    tot_bytes = sum((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) * len(rec[p]["apply_ms"]) for p in keys)
+    n_apply = sum(len(rec[p]["apply_ms"]) for p in keys)
     achieved = tot_bytes / tot_s / 1e9
-    traffic = committed_traffic(degrees)
+    traffic = None if args.workloads else committed_traffic(degrees)
     if traffic is not None:
         traffic = round(traffic)
     per_p = {}
-    for p in degrees:
+    for p in keys:
         r = rec[p]
         t_ap = float(np.mean(r["apply_ms"]))
         d = {"N": probs[p]["N"], "Nq": probs[p]["Nq"], "apply_ms": round(t_ap, 4),
@@ -324,7 +333,7 @@ def main():
                         "rtol": probs[p][f"{kind}_eq_rtol"], "ms": round(float(np.median(r[f"{kind}_eq_ms"])), 2),
                         "rel_err_vs_tight": float(np.max(r[f"{kind}_eq_err"])),
                         "iters": int(np.median(r[f"{kind}_eq_it"]))}
-        per_p[f"p{p}"] = d
+        per_p[p] = d
     out = {
         "metric": METRIC,
         "value": round(tot_dof / tot_s / 1e9, 4),
@@ -338,10 +347,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded spline ring geometry, K = I, oscillating source)",
-        "config": {"workload": f"thick quarter ring, {args.n_el}^3 elements, degrees {args.degrees}, "
-                               f"FP64 apply + FP64 BiCGStab/FD and mixed-precision IR solves to rel.res 1e-10, "
-                               f"adjoint gradient",
-                   "n_el": args.n_el, "degrees": degrees, "applies_per_degree_per_step": args.reps,
+        "config": {"workload": (f"thick quarter ring, {args.n_el}^3 elements, degrees {args.degrees}, "
+                                f"FP64 apply + FP64 BiCGStab/FD and mixed-precision IR solves to rel.res 1e-10, "
+                                f"adjoint gradient") if not args.workloads else
+                   f"named workloads {args.workloads}: same step",
+                   "n_el": args.n_el, "degrees": degrees if not args.workloads else None,
+                   "workloads": keys, "applies_per_degree_per_step": args.reps,
                    "mixed": {"inner_fd": args.mixed_fd, "inner_apply": "f32", "tau_inner": args.mixed_tau}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
