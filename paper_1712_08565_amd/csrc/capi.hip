@@ -148,6 +148,7 @@ struct FusedHost {
     int ntile[2] = {0, 0};
     std::vector<double> tiles[2];   // [t][6][256]
     std::vector<int> J[2], I[2];
+    std::vector<int> band[2];       // [tile][16]: first nonzero (local) j of the B / B-dot rows of the tile's points
     std::vector<int> bs3, wts3;
     std::vector<double> cz;         // [nq3][2(p+1) + 4(p+2)]
     int zchunk = 0;
@@ -271,6 +272,7 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
         fh.tiles[l].assign((size_t)nt * 6 * 256, 0.0);
         fh.J[l].assign(nt, 0);
         fh.I[l].assign(nt, 0);
+        fh.band[l].assign((size_t)nt * 16, 0);
         const std::vector<double>* Wv[4] = {&S.W[0][0], &S.W[0][1], &S.W[1][0], &S.W[1][1]};
         for (int t = 0; t < nt; ++t) {
             const int Q = 16 * t, qe = std::min(Q + 16, nq);
@@ -295,6 +297,21 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
             if (jmax - jmin >= 16 || imax - imin >= 16) return false;
             fh.J[l][t] = jmin;
             fh.I[l][t] = imin;
+            // per point: local start of the p + 1 trial functions that can be nonzero there
+            for (int a = 0; a < 16; ++a) {
+                const int q = Q + a;
+                int lo = -1, hi = -1;
+                if (q < nq)
+                    for (int j = 0; j < n; ++j)
+                        if (S.B[0][(size_t)q * n + j] != 0.0 || S.B[1][(size_t)q * n + j] != 0.0) {
+                            if (lo < 0) lo = j;
+                            hi = j;
+                        }
+                int st = lo < 0 ? 0 : lo - jmin;
+                if (lo >= 0 && hi - lo > p) return false;   // more than p + 1 functions at one point
+                st = std::max(0, std::min(st, 16 - (p + 1)));
+                fh.band[l][(size_t)t * 16 + a] = st;
+            }
             double* blk = &fh.tiles[l][(size_t)t * 6 * 256];
             for (int a = 0; a < 16; ++a)
                 for (int b = 0; b < 16; ++b) {
@@ -443,7 +460,7 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     // fused-apply tables, both precisions
     FusedHost fh;
     const bool fused_ok = build_fused_tables(sp, p, fh) && !std::getenv("WQFD_STAGED");
-    size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0};
+    size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0}, f_band[2] = {0, 0};
     size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_sched = 0, f_soff = 0, f_schedT = 0, f_soffT = 0;
     if (fused_ok) {
         for (int l = 0; l < 2; ++l) {
@@ -451,6 +468,7 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
             std::vector<float> t32(fh.tiles[l].begin(), fh.tiles[l].end());
             f_tiles32[l] = pk.add(t32.data(), t32.size() * 4);
             f_J[l] = pk.add(fh.J[l].data(), fh.J[l].size() * sizeof(int));
+            f_band[l] = pk.add(fh.band[l].data(), fh.band[l].size() * sizeof(int));
             f_I[l] = pk.add(fh.I[l].data(), fh.I[l].size() * sizeof(int));
         }
         f_bs3 = pk.add(fh.bs3.data(), fh.bs3.size() * sizeof(int));
@@ -538,6 +556,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
             fz.IX = reinterpret_cast<const int*>(tb + f_I[0]);
             fz.JY = reinterpret_cast<const int*>(tb + f_J[1]);
             fz.IY = reinterpret_cast<const int*>(tb + f_I[1]);
+            fz.bandX = reinterpret_cast<const int*>(tb + f_band[0]);
+            fz.bandY = reinterpret_cast<const int*>(tb + f_band[1]);
             fz.bs3 = reinterpret_cast<const int*>(tb + f_bs3);
             fz.wts3 = reinterpret_cast<const int*>(tb + f_wts3);
             fz.cz = reinterpret_cast<const T*>(tb + ocz);

@@ -29,6 +29,8 @@ struct FusedArgs {
     const int* IX = nullptr;
     const int* JY = nullptr;
     const int* IY = nullptr;
+    const int* bandX = nullptr;     // [tile][16] local start of the p + 1 trial functions at each point
+    const int* bandY = nullptr;
     const int* bs3 = nullptr;
     const int* wts3 = nullptr;
     const T* cz = nullptr;

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     constexpr int NU = 3;                  // U planes in flight
     __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
     __shared__ T sV[2][BLK];               // staged DOF planes
-    __shared__ T sU[NU][3][BLK];           // U_x, U_y, U_0 of produced planes
+    __shared__ T sA[NU][2][BLK];           // x products A_0, A_1 of produced planes
     __shared__ T sP[2][9][BLK];            // psi_f of retired output planes
     __shared__ T sR[2][5][BLK];            // partial output blocks of the x/y test contraction
     __shared__ T sZ[kMaxZ * CZ];           // z coefficients of this workgroup's planes
@@ -232,6 +232,17 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             bb[q] = sCoef[4 + v1_of(fb)][cl * LD + 4 * q + kb];
         }
         ld_accA(w2a, sCoef[8 + v2]);
+        // x products of the staged plane on the vector units, exact band:
+        // thread (q1, j2) = (mt & 15, mt >> 4) forms A_d[j2][q1] =
+        // sum_s B1_d[q1][js + s] V[j2][js + s] over the p + 1 functions at point q1
+        const int mt = tid - 768, xq1 = mt & 15, xj2 = mt >> 4;
+        const int jsx = a.bandX[t1 * 16 + xq1];
+        T cb0[RT], cb1[RT];
+#pragma unroll
+        for (int s = 0; s < RT; ++s) {
+            cb0[s] = sCoef[0][xq1 * LD + jsx + s];
+            cb1[s] = sCoef[1][xq1 * LD + jsx + s];
+        }
         // waves 12 and 13 stage the DOF planes, loaded two intervals ahead
         // (entries lane + 64 (2 mw + q) of the 16 x 16 block)
         const bool stager = mw < 2;
@@ -252,6 +263,18 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         }
         for (int r = 0; r < nrec; ++r) {
             const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
+            if ((fl >> 7) & 1) {                                 // produce: x products of plane tprod
+                const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
+                T a0 = T(0), a1 = T(0);
+#pragma unroll
+                for (int s = 0; s < RT; ++s) {
+                    const T vv = sV[vs][xj2 * LD + jsx + s];
+                    a0 += cb0[s] * vv;
+                    a1 += cb1[s] * vv;
+                }
+                sA[us][0][xj2 * LD + xq1] = a0;
+                sA[us][1][xj2 * LD + xq1] = a1;
+            }
             if ((fl >> 9) & 1) {
                 const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
                 T xa[4], xb[4];
@@ -292,33 +315,17 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             lds_barrier();
         }
     } else {
-        // Besides their planes, column waves produce the U planes (wave 0:
-        // U_x = B2 A_1, wave 5: U_y = B-dot2 A_0, wave 10: U_0 = B2 A_0 with
-        // A_d = V B1_d^T) and contract the {yy} field of the retired plane (wave 3).
-        const bool producer = wave == 0 || wave == 5 || wave == 10;
+        // Besides their planes, column waves form the entering U value themselves
+        // (y products with the exact band: U_beta[q2][q1] = sum_s B2_e[q2][js + s]
+        // A_b[js + s][q1]; beta = x: B2 A_1, y: B-dot2 A_0, z: B2 A_0) and wave 3
+        // contracts the {yy} field of the retired plane.
+        const int jsy = a.bandY[t2 * 16 + q2l];
+        const T* cbY = sCoef[beta == 1 ? 3 : 2] + q2l * LD + jsy;
+        const int ab = beta == 0 ? 1 : 0;
         for (int r = 0; r < nrec; ++r) {
             const int fl = rec[4 * r], kq = rec[4 * r + 1];
             const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
             const int nsteps = max(nv, max(in_at, out_at) + 1);
-            if (producer && ((fl >> 7) & 1)) {
-                const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
-                const T* Bt = sCoef[beta == 0 ? 1 : 0];
-                acc_t A = {0, 0, 0, 0}, U = {0, 0, 0, 0};
-                {
-                    T av[4], bv[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        av[q] = sV[vs][cl * LD + 4 * q + kb];
-                        bv[q] = Bt[cl * LD + 4 * q + kb];
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) A = MF<T>::mma(av[q], bv[q], A);
-                }
-                T ua[4];
-                ld_accA(ua, sCoef[beta == 1 ? 3 : 2]);
-                mm_acc(U, ua, A);
-                store16<T>(sU[us][beta], U, cl, kb);
-            }
             if (wave == 3 && ((fl >> 9) & 1)) {
                 const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
                 const T* Bt = sCoef[4 + v1_of(4)];
@@ -343,7 +350,11 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                 if (j == in_at) {
 #pragma unroll
                     for (int s = 0; s < RT - 1; ++s) Uw[s] = Uw[s + 1];
-                    Uw[RT - 1] = sU[(fl >> 11) & 3][beta][q2l * LD + q1l];
+                    const T* A = sA[(fl >> 11) & 3][ab] + jsy * LD + q1l;
+                    T u = T(0);
+#pragma unroll
+                    for (int s = 0; s < RT; ++s) u += cbY[s] * A[s * LD];
+                    Uw[RT - 1] = u;
                 }
                 if (j == out_at) {
                     if ((fl >> 6) & 1) {
