@@ -40,6 +40,14 @@ constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
 constexpr int BLK = 16 * LD;
 constexpr int kMaxZ = FUSED_MAX_Z;   // longest z range of one workgroup
 
+// Schedule records are read-only for the whole launch and uniform across a
+// wave: reading them through the constant address space makes them scalar
+// loads, which leave the vector memory counter (and the loads it tracks) alone.
+typedef const __attribute__((address_space(4))) int cint;
+
+// s_waitcnt immediate for gfx9: vmcnt 0, expcnt and lgkmcnt left at their maxima
+constexpr int kVmcnt0 = 0x0F70;
+
 template <typename T>
 struct MF;
 template <>
@@ -107,7 +115,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     __shared__ T sZ[kMaxZ * CZ];           // z coefficients of this workgroup's planes
 
     using acc_t = typename MF<T>::acc;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: role branches are scalar
     const bool mrole = wave >= 12;         // MFMA role (wave-uniform)
     const int ct = tid & 255;              // column of a column thread / lane slot of an MFMA thread
     const int cl = lane & 15, kb = lane >> 4;
@@ -129,7 +138,6 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
 
     const int Q1 = t1 * 16, Q2 = t2 * 16;
     const int q1 = Q1 + q1l, q2 = Q2 + q2l;
-    const bool active = q1 < a.nq1 && q2 < a.nq2;
     const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
     const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
     // this range's interval records (uniform: read through the scalar cache)
     const int r0 = a.sched_off[zc], nrec = a.sched_off[zc + 1] - r0;
-    const int* __restrict__ rec = a.sched + 4 * (size_t)r0;
+    const cint* rec = (const cint*)(a.sched + 4 * (size_t)r0);
 
     // ---- MFMA-role helpers ------------------------------------------------
     // A operand for a product whose B operand is an accumulator: the K index of
@@ -176,23 +184,24 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     const size_t Nq = a.Nq;
     const size_t plane = (size_t)a.nq1 * a.nq2;
     const size_t poff[3] = {((pidx >> 0) & 15) * Nq, ((pidx >> 4) & 15) * Nq, ((pidx >> 8) & 15) * Nq};
-    const bool cload = !mrole && active;
-    const T* Ccol = a.C + ((size_t)q2 * a.nq1 + q1);
-    T Cn[3];
+    // Coefficients are loaded one interval ahead (an interval covers at most two
+    // quadrature planes) into two register slots, each reloaded right after its
+    // use at a fixed point of the interval.  The loads are unconditional (columns
+    // outside the grid read a clamped address; their trial values are exactly 0),
+    // so every interval issues the same loads in the same order and a use waits
+    // only for its own slot, not for the loads issued after it.
+    // (plane base in scalar registers, the column's byte offset in a vector one)
+    const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
+    auto cload3 = [&](T (&dst)[3], int kq) {
+        const size_t ko = (size_t)min(kq, k1 - 1) * plane;
 #pragma unroll
-    for (int al = 0; al < 3; ++al) Cn[al] = cload ? Ccol[poff[al] + (size_t)k0 * plane] : T(0);
+        for (int al = 0; al < 3; ++al)
+            dst[al] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a.C + poff[al] + ko) + cbyte);
+    };
 
     // one quadrature plane of column work: g = (z trial row) . window,
     // psi_alpha = C_(alpha beta) g, ring += (z test rows) psi
-    auto valu_plane = [&](int kq) {
-        T C[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) C[al] = Cn[al];
-        if (kq + 1 < k1) {
-            const size_t ko = (size_t)(kq + 1) * plane;
-#pragma unroll
-            for (int al = 0; al < 3; ++al) Cn[al] = cload ? Ccol[poff[al] + ko] : T(0);
-        }
+    auto valu_plane = [&](int kq, const T (&C)[3]) {
         const T* cz = sZ + (size_t)(kq - k0) * CZ;
         const T* ct3 = cz + (beta == 2 ? RT : 0);               // B3 row, or B-dot3 for beta = z
         T g = T(0);
@@ -218,7 +227,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         // Fields sharing the y weight variant v2 = 2[alpha = y] + [beta = y] are
         // summed after their x products (X = sum_f psi_f W1^(v1_f)T, Z = W2^(v2) X):
         //   wave 12: {xx, xz};  wave 13: {zx, zz} (v2 = 0);  wave 14: {xy, zy} (v2 = 1);
-        //   wave 15: {yx, yz} (v2 = 2); {yy} (v2 = 3) runs on column wave 3.
+        //   wave 15: {yx, yz} (v2 = 2); {yy} (v2 = 3) runs on column wave 2, whose SIMD
+        //   holds the MFMA wave with no staging or reduction duties.
         // The factor operands are the same in every interval and stay in registers.
         // Wave 15 also sums the partial blocks and adds them to w: it issues no
         // loads, so its atomics never delay a wait for loaded data.
@@ -243,24 +253,27 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             cb0[s] = sCoef[0][xq1 * LD + jsx + s];
             cb1[s] = sCoef[1][xq1 * LD + jsx + s];
         }
-        // waves 12 and 13 stage the DOF planes, loaded two intervals ahead
-        // (entries lane + 64 (2 mw + q) of the 16 x 16 block)
+        // waves 12 and 13 stage the DOF planes (entries lane + 64 (2 mw + q) of the
+        // 16 x 16 block); each plane is loaded at the previous staging, at least one
+        // interval earlier, from a clamped address, and masked when it is stored
         const bool stager = mw < 2;
-        T vq0[2], vq1[2];
-        auto vload = [&](T (&dst)[2], int j3) {
+        T vq[2];
+        unsigned voff[2];
+        bool vok[2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int e = lane + 64 * (2 * mw + q);
-                const int j1 = J1 + (e & 15), j2 = J2 + (e >> 4);
-                dst[q] = (j1 < a.n1 && j2 < a.n2 && j3 >= 0 && j3 < a.n3)
-                             ? a.v[((size_t)j3 * a.n2 + j2) * a.n1 + j1] : T(0);
-            }
-        };
-        if (stager && nrec > 0) {
-            const int t0 = rec[3];
-            vload((t0 & 1) ? vq1 : vq0, t0);
-            vload((t0 & 1) ? vq0 : vq1, t0 + 1);
+        for (int q = 0; q < 2; ++q) {
+            const int e = lane + 64 * (2 * mw + q);
+            const int j1 = J1 + (e & 15), j2 = J2 + (e >> 4);
+            vok[q] = j1 < a.n1 && j2 < a.n2;
+            voff[q] = (unsigned)(min(j2, a.n2 - 1) * a.n1 + min(j1, a.n1 - 1));
         }
+        const size_t vplane = (size_t)a.n1 * a.n2;
+        auto vload = [&](int j3) {
+            const T* vp = a.v + (size_t)min(max(j3, 0), a.n3 - 1) * vplane;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) vq[q] = vp[voff[q]];
+        };
+        if (stager && nrec > 0) vload(rec[3]);
         for (int r = 0; r < nrec; ++r) {
             const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
             if ((fl >> 7) & 1) {                                 // produce: x products of plane tprod
@@ -293,12 +306,13 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             }
             if (stager && ((fl >> 8) & 1)) {
                 const int sl = (fl >> 20) & 1;
+                const bool zin = ts >= 0 && ts < a.n3;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const int e = lane + 64 * (2 * mw + q);
-                    sV[sl][(e >> 4) * LD + (e & 15)] = sl ? vq1[q] : vq0[q];
+                    sV[sl][(e >> 4) * LD + (e & 15)] = (vok[q] && zin) ? vq[q] : T(0);
                 }
-                if (sl) vload(vq1, ts + 2); else vload(vq0, ts + 2);
+                vload(ts + 1);
             }
             if (mw == 3 && ((fl >> 10) & 1)) {
                 const int rs = (fl >> 15) & 1;
@@ -317,16 +331,24 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     } else {
         // Besides their planes, column waves form the entering U value themselves
         // (y products with the exact band: U_beta[q2][q1] = sum_s B2_e[q2][js + s]
-        // A_b[js + s][q1]; beta = x: B2 A_1, y: B-dot2 A_0, z: B2 A_0) and wave 3
+        // A_b[js + s][q1]; beta = x: B2 A_1, y: B-dot2 A_0, z: B2 A_0) and wave 2
         // contracts the {yy} field of the retired plane.
         const int jsy = a.bandY[t2 * 16 + q2l];
         const T* cbY = sCoef[beta == 1 ? 3 : 2] + q2l * LD + jsy;
         const int ab = beta == 0 ? 1 : 0;
+        // slot j holds plane kq + j of the interval.  The first interval's slots
+        // are waited for before the loop, so the waits inside it are set by the
+        // loop's own load order alone (use of a slot: the other slot's three
+        // loads may still be in flight).
+        T Cs[2][3];
+        cload3(Cs[0], k0);
+        cload3(Cs[1], k0 + 1);
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);
         for (int r = 0; r < nrec; ++r) {
             const int fl = rec[4 * r], kq = rec[4 * r + 1];
             const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
-            const int nsteps = max(nv, max(in_at, out_at) + 1);
-            if (wave == 3 && ((fl >> 9) & 1)) {
+            const int nsteps = max(nv, max(in_at, out_at) + 1);   // <= 2
+            if (wave == 2 && ((fl >> 9) & 1)) {
                 const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
                 const T* Bt = sCoef[4 + v1_of(4)];
                 acc_t X = {0, 0, 0, 0}, Z = {0, 0, 0, 0};
@@ -346,8 +368,9 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                 store16<T>(sR[rs][4], Z, cl, kb);
             }
 
-            for (int j = 0; j < nsteps; ++j) {
-                if (j == in_at) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (j < nsteps && j == in_at) {
 #pragma unroll
                     for (int s = 0; s < RT - 1; ++s) Uw[s] = Uw[s + 1];
                     const T* A = sA[(fl >> 11) & 3][ab] + jsy * LD + q1l;
@@ -356,7 +379,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                     for (int s = 0; s < RT; ++s) u += cbY[s] * A[s * LD];
                     Uw[RT - 1] = u;
                 }
-                if (j == out_at) {
+                if (j < nsteps && j == out_at) {
                     if ((fl >> 6) & 1) {
                         const int ps = (fl >> 13) & 1;
 #pragma unroll
@@ -369,7 +392,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                         acc[al][RO - 1] = T(0);
                     }
                 }
-                if (j < nv) valu_plane(kq + j);
+                if (j < nv) valu_plane(kq + j, Cs[j]);
+                cload3(Cs[j], kq + nv + j);  // plane j of the next interval
             }
             lds_barrier();
         }
@@ -406,7 +430,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     __shared__ T sZ[kMaxZ * CZ];           // z coefficients of this workgroup's planes
 
     using acc_t = typename MF<T>::acc;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: role branches are scalar
     const bool mrole = wave >= 12;
     const int ct = tid & 255;
     const int cl = lane & 15, kb = lane >> 4;
@@ -425,7 +450,6 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     if (k0 >= k1) return;
 
     const int q1 = t1 * 16 + q1l, q2 = t2 * 16 + q2l;
-    const bool active = q1 < a.nq1 && q2 < a.nq2;
     const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
     const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
@@ -440,7 +464,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     }
     for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
     const int r0 = a.schedT_off[zc], nrec = a.schedT_off[zc + 1] - r0;
-    const int* __restrict__ rec = a.schedT + 4 * (size_t)r0;
+    const cint* rec = (const cint*)(a.schedT + 4 * (size_t)r0);
 
     // A operand read transposed from a [k][m] LDS block, K index = accumulator row
     auto ld_accAt = [&](T (&av)[4], const T* A) {
@@ -473,23 +497,25 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         //   wave 14: v1 = 2 -> {xy, xz} and v1 = 3 -> {xx}.
         // Retired planes: wave 13 field y (B1, then B-dot2), wave 15 fields x and z
         // (X = R_x B-dot1 + R_z B1, then B2), wave 15 also reduces and adds to w.
-        // Wave 14 stages the planes of v (loaded two intervals ahead).
+        // Wave 14 stages the planes of v (each loaded at the previous staging).
         const bool stager = mw == 2;
-        T vq0[4], vq1[4];
-        auto vload = [&](T (&dst)[4], int i3) {
+        T vq[4];
+        unsigned voff[4];
+        bool vok[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = lane + 64 * q;
-                const int i1 = I1 + (e & 15), i2 = I2 + (e >> 4);
-                dst[q] = (i1 < a.n1 && i2 < a.n2 && i3 >= 0 && i3 < a.n3)
-                             ? a.v[((size_t)i3 * a.n2 + i2) * a.n1 + i1] : T(0);
-            }
-        };
-        if (stager && nrec > 0) {
-            const int t0 = rec[3];
-            vload((t0 & 1) ? vq1 : vq0, t0);
-            vload((t0 & 1) ? vq0 : vq1, t0 + 1);
+        for (int q = 0; q < 4; ++q) {
+            const int e = lane + 64 * q;
+            const int i1 = I1 + (e & 15), i2 = I2 + (e >> 4);
+            vok[q] = i1 < a.n1 && i2 < a.n2;
+            voff[q] = (unsigned)(min(i2, a.n2 - 1) * a.n1 + min(i1, a.n1 - 1));
         }
+        const size_t vplane = (size_t)a.n1 * a.n2;
+        auto vload = [&](int i3) {
+            const T* vp = a.v + (size_t)min(max(i3, 0), a.n3 - 1) * vplane;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vq[q] = vp[voff[q]];
+        };
+        if (stager && nrec > 0) vload(rec[3]);
         // y products of one x result: fields given as (f, v2) pairs
         auto yprods = [&](const acc_t& A, int us, int f, int v2) {
             T wv[4];
@@ -540,12 +566,13 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
             }
             if (stager && ((fl >> 8) & 1)) {
                 const int sl = (fl >> 20) & 1;
+                const bool zin = ts >= 0 && ts < a.n3;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int e = lane + 64 * q;
-                    sV[sl][(e >> 4) * LD + (e & 15)] = sl ? vq1[q] : vq0[q];
+                    sV[sl][(e >> 4) * LD + (e & 15)] = (vok[q] && zin) ? vq[q] : T(0);
                 }
-                if (sl) vload(vq1, ts + 2); else vload(vq0, ts + 2);
+                vload(ts + 1);
             }
             if (mw == 3 && ((fl >> 10) & 1)) {
                 const int rs = (fl >> 15) & 1;
@@ -575,19 +602,15 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         const size_t Nq = a.Nq;
         const size_t plane = (size_t)a.nq1 * a.nq2;
         const size_t poff[3] = {((pidx >> 0) & 15) * Nq, ((pidx >> 4) & 15) * Nq, ((pidx >> 8) & 15) * Nq};
-        const T* Ccol = a.C + ((size_t)q2 * a.nq1 + q1);
-        T Cn[3];
+        // coefficient slots loaded one interval ahead, as in the forward kernel
+        const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
+        auto cload3 = [&](T (&dst)[3], int kq) {
+            const size_t ko = (size_t)min(kq, k1 - 1) * plane;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) Cn[al] = active ? Ccol[poff[al] + (size_t)k0 * plane] : T(0);
-        auto valu_plane = [&](int kq) {
-            T C[3];
-#pragma unroll
-            for (int al = 0; al < 3; ++al) C[al] = Cn[al];
-            if (kq + 1 < k1) {
-                const size_t ko = (size_t)(kq + 1) * plane;
-#pragma unroll
-                for (int al = 0; al < 3; ++al) Cn[al] = active ? Ccol[poff[al] + ko] : T(0);
-            }
+            for (int al = 0; al < 3; ++al)
+                dst[al] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a.C + poff[al] + ko) + cbyte);
+        };
+        auto valu_plane = [&](int kq, const T (&C)[3]) {
             const T* cz = sZ + (size_t)(kq - k0) * CZ;
             // z weight variant of field (alpha, beta): 2 [alpha = z] + [beta = z]
             const T* w01 = cz + 2 * RT + (beta == 2 ? 1 : 0) * RO;
@@ -604,12 +627,17 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
 #pragma unroll
             for (int s = 0; s < RT; ++s) orng[s] += bz[s] * phi;
         };
+        T Cs[2][3];
+        cload3(Cs[0], k0);
+        cload3(Cs[1], k0 + 1);
+        __builtin_amdgcn_s_waitcnt(kVmcnt0);
         for (int r = 0; r < nrec; ++r) {
             const int fl = rec[4 * r], kq = rec[4 * r + 1];
             const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
-            const int nsteps = max(nv, max(in_at, out_at) + 1);
-            for (int j = 0; j < nsteps; ++j) {
-                if (j == in_at) {
+            const int nsteps = max(nv, max(in_at, out_at) + 1);   // <= 2
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                if (j < nsteps && j == in_at) {
                     const int us = (fl >> 11) & 3;
 #pragma unroll
                     for (int al = 0; al < 3; ++al) {
@@ -618,13 +646,14 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
                         Yw[al][RO - 1] = sU[us][3 * al + beta][q2l * LD + q1l];
                     }
                 }
-                if (j == out_at) {
+                if (j < nsteps && j == out_at) {
                     if ((fl >> 6) & 1) sP[(fl >> 13) & 1][beta][q2l * LD + q1l] = orng[0];
 #pragma unroll
                     for (int s = 0; s < RT - 1; ++s) orng[s] = orng[s + 1];
                     orng[RT - 1] = T(0);
                 }
-                if (j < nv) valu_plane(kq + j);
+                if (j < nv) valu_plane(kq + j, Cs[j]);
+                cload3(Cs[j], kq + nv + j);
             }
             lds_barrier();
         }
