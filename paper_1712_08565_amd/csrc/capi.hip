@@ -192,7 +192,7 @@ int choose_zchunk(int nq3, int tiles, int slots, int p) {
 // plane (forward: B3 band, p + 1; transposed: W3 band, p + 2); outs/OUT: the
 // same for the output ring (forward: W3, p + 2; transposed: B3, p + 1).
 bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>& outs, int OUT, int n3, int k0,
-                    int k1, std::vector<int>& out) {
+                    int k1, int CZ, std::vector<int>& out) {
     const int RT = IN, RO = OUT, NU = 3;
     const std::vector<int>& bs3 = ins;
     const std::vector<int>& wts3 = outs;
@@ -233,7 +233,12 @@ bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>&
                       int(m_stage) << 8 | int(fl_prev) << 9 | int(red_prev) << 10 | (tnext % NU) << 11 |
                       (nfw & 1) << 13 | fl_slot << 14 | red_slot << 15 | (nred & 1) << 16 | (tprod & 1) << 17 |
                       (tprod % NU) << 18 | (tstage & 1) << 20;
-        out.insert(out.end(), {f, k, red_i3, tstage});
+        // column-role events per step j = 0, 1: entry, retirement, plane processed
+        int ev = 0;
+        for (int j = 0; j < 2; ++j)
+            ev |= (int(in_at == j) | int(out_at == j) << 1 | int(nv > j) << 2) << (3 * j);
+        const int cn0 = std::min(k + nv, k1 - 1), cn1 = std::min(k + nv + 1, k1 - 1);
+        out.insert(out.end(), {f, k, red_i3, tstage, ev, (std::min(k, k1 - 1) - k0) * CZ, cn0, cn1});
         // advance
         const bool red_now = fl_prev;
         if (red_now) {
@@ -265,6 +270,10 @@ bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>&
 
 bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
     if (p > 7) return false;
+    // the kernels address one coefficient plane and one vector with 32-bit
+    // byte offsets (buffer loads)
+    const size_t Nq_all = (size_t)sp[0].nq * sp[1].nq * sp[2].nq, N_all = (size_t)sp[0].n * sp[1].n * sp[2].n;
+    if (Nq_all * sizeof(double) >= (size_t(1) << 31) || N_all * sizeof(double) >= (size_t(1) << 31)) return false;
     for (int l = 0; l < 2; ++l) {
         const wqfd::Space1D& S = sp[l];
         const int n = S.n, nq = S.nq, nt = (nq + 15) / 16;
@@ -372,13 +381,16 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
     fh.schedT_off.clear();
     for (int k0 = 0; k0 < nq3; k0 += fh.zchunk) {
         const int k1 = std::min(nq3, k0 + fh.zchunk);
-        fh.sched_off.push_back((int)(fh.sched.size() / 4));
-        fh.schedT_off.push_back((int)(fh.schedT.size() / 4));
-        if (!fused_schedule(fh.bs3, RT, fh.wts3, RO, n3, k0, k1, fh.sched)) return false;
-        if (!fused_schedule(fh.wts3, RO, fh.bs3, RT, n3, k0, k1, fh.schedT)) return false;
+        fh.sched_off.push_back((int)(fh.sched.size() / wqfd::FUSED_REC));
+        fh.schedT_off.push_back((int)(fh.schedT.size() / wqfd::FUSED_REC));
+        if (!fused_schedule(fh.bs3, RT, fh.wts3, RO, n3, k0, k1, CZ, fh.sched)) return false;
+        if (!fused_schedule(fh.wts3, RO, fh.bs3, RT, n3, k0, k1, CZ, fh.schedT)) return false;
     }
-    fh.sched_off.push_back((int)(fh.sched.size() / 4));
-    fh.schedT_off.push_back((int)(fh.schedT.size() / 4));
+    fh.sched_off.push_back((int)(fh.sched.size() / wqfd::FUSED_REC));
+    fh.schedT_off.push_back((int)(fh.schedT.size() / wqfd::FUSED_REC));
+    // the kernels hold a range's records one per lane of a wave
+    for (size_t r = 0; r + 1 < fh.sched_off.size(); ++r)
+        if (fh.sched_off[r + 1] - fh.sched_off[r] > 64 || fh.schedT_off[r + 1] - fh.schedT_off[r] > 64) return false;
     return true;
 }
 

@@ -150,82 +150,97 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
 // ---------------------------------------------------------------------------
 // Fused passes of the whole preconditioner (FP64 and FP32, n <= 144), three
 // launches per application instead of six:
-//   xy pass, per z-plane i3 and 16-column block of i1:
-//     Q[j2][i1] = sum_j1 in[i3][j2][j1] T1[i1][j1]   (wave t: rows j2 of block t)
-//     out[i3][i2][i1] = sum_j2 T2[i2][j2] Q[j2][i1]   (Q through LDS)
+//   xy pass, per z-plane i3 and 16-row block of i2 (the y product first, so the
+//   data is read and written along contiguous x rows):
+//     Q[i2][j1] = sum_j2 T2[i2][j2] in[i3][j2][j1]    (wave t: columns j1 of block t)
+//     out[i3][i2][i1] = sum_j1 Q[i2][j1] T1[i1][j1]   (Q through LDS; wave t: i1 of block t)
 //   z pass, per 16-column block of g = (i2, i1):
 //     Y[i3][g] = sum_j3 T3f[i3][j3] in[j3][g] / (l1[i1] + l2[i2] + l3[i3])
 //     out[i3][g] = sum_j3 T3b[i3][j3] Y[j3][g]       (Y through LDS; in may be out)
-// One wave per 16-row block (KB = ceil(n / 16) waves), operands of the first
-// product loaded up front.
+// The small matrices are passed transposed (Tt[j][i] = T[i][j]), so that the 16
+// lanes of an operand column read 16 consecutive entries.
+// One wave per 16-wide block (KB = ceil(n / 16) waves).  Every operand that
+// does not depend on the first product, the second product's matrix included,
+// is loaded before the first product (for KB <= PRELOAD_KB; larger blocks load
+// the second matrix after it, to bound registers), and contraction steps past
+// the true length are skipped.
 constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
+constexpr int PRELOAD_KB = 6;
+
+template <int PREC>
+__device__ inline typename G<PREC>::Acc mma_step(typename G<PREC>::T a, typename G<PREC>::T b,
+                                                 typename G<PREC>::Acc c) {
+    if constexpr (PREC == 1)
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
 
 template <int PREC, int KB>
 __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T* __restrict__ in,
                                                       typename G<PREC>::T* __restrict__ out,
-                                                      const typename G<PREC>::T* __restrict__ T1,
-                                                      const typename G<PREC>::T* __restrict__ T2, int n1, int n2) {
+                                                      const typename G<PREC>::T* __restrict__ T1t,
+                                                      const typename G<PREC>::T* __restrict__ T2t, int n1, int n2) {
     using T = typename G<PREC>::T;
     using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
-    __shared__ T sQ[16 * KB * FLD];
+    constexpr int LDQ = 16 * KB + 1;                     // odd row length of the Q block
+    constexpr bool PRE = KB <= PRELOAD_KB;
+    __shared__ T sQ[16 * LDQ];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
-    const int c0 = blockIdx.x * 16;                      // first i1 of this block
+    const int r0 = blockIdx.x * 16;                      // first i2 of this block
     const size_t pl = (size_t)blockIdx.y * n1 * n2;       // z-plane offset
-    // Q block t: rows j2 = 16 t + ., columns i1 = c0 + .
-    T a[NKS], b[NKS];
-    const int j2 = 16 * t + cl, i1 = c0 + cl;
+    const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;  // contraction steps of the two products
+    const int i2a = r0 + cl, jc = 16 * t + cl;           // A row (i2) and B column (j1, then i1)
+    T a[NKS], b[NKS], c[PRE ? NKS : 1];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;                        // j1
-        a[s] = (j2 < n2 && k < n1) ? in[pl + (size_t)j2 * n1 + k] : T(0);
-        b[s] = (i1 < n1 && k < n1) ? T1[(size_t)i1 * n1 + k] : T(0);
+        const int k = 4 * s + kb;
+        a[s] = (i2a < n2 && k < n2) ? T2t[(size_t)k * n2 + i2a] : T(0);
+        b[s] = (jc < n1 && k < n2) ? in[pl + (size_t)k * n1 + jc] : T(0);
+        if constexpr (PRE) c[s] = (jc < n1 && k < n1) ? T1t[(size_t)k * n1 + jc] : T(0);
     }
     Acc q = Acc{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        if constexpr (PREC == 1)
-            q = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], q, 0, 0, 0);
-        else
-            q = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], q, 0, 0, 0);
-    }
+    for (int s = 0; s < NKS; ++s)
+        if (s < ks2) q = mma_step<PREC>(a[s], b[s], q);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) sQ[(16 * t + G<PREC>::drow(kb, v)) * FLD + cl] = q[v];
+    for (int v = 0; v < 4; ++v) sQ[G<PREC>::drow(kb, v) * LDQ + jc] = q[v];   // columns >= n1 hold zeros
     __syncthreads();
-    // out block t: rows i2 = 16 t + ., contraction over j2 with Q from LDS
-    const int i2 = 16 * t + cl;
-#pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;                        // j2
-        a[s] = (i2 < n2 && k < n2) ? T2[(size_t)i2 * n2 + k] : T(0);
-        b[s] = sQ[k * FLD + cl];                         // rows j2 >= n2 hold zeros
-    }
     Acc r = Acc{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
-        if constexpr (PREC == 1)
-            r = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], r, 0, 0, 0);
-        else
-            r = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], r, 0, 0, 0);
+        const int k = 4 * s + kb;
+        a[s] = sQ[cl * LDQ + k];
+        if constexpr (!PRE) b[s] = (jc < n1 && k < n1) ? T1t[(size_t)k * n1 + jc] : T(0);
     }
-    if (i1 >= n1) return;
+#pragma unroll
+    for (int s = 0; s < NKS; ++s) {
+        if constexpr (PRE) {
+            if (s < ks1) r = mma_step<PREC>(a[s], c[s], r);
+        } else {
+            if (s < ks1) r = mma_step<PREC>(a[s], b[s], r);
+        }
+    }
+    if (jc >= n1) return;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        const int ii = 16 * t + G<PREC>::drow(kb, v);
-        if (ii < n2) out[pl + (size_t)ii * n1 + i1] = r[v];
+        const int i2 = r0 + G<PREC>::drow(kb, v);
+        if (i2 < n2) out[pl + (size_t)i2 * n1 + jc] = r[v];
     }
 }
 
 template <int PREC, int KB>
 __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* in, typename G<PREC>::T* out,
-                                                     const typename G<PREC>::T* __restrict__ T3f,
-                                                     const typename G<PREC>::T* __restrict__ T3b,
+                                                     const typename G<PREC>::T* __restrict__ T3ft,
+                                                     const typename G<PREC>::T* __restrict__ T3bt,
                                                      const double* __restrict__ l1, const double* __restrict__ l2,
                                                      const double* __restrict__ l3, int n1, int n2, int n3) {
     using T = typename G<PREC>::T;
     using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
+    constexpr bool PRE = KB <= PRELOAD_KB;
     __shared__ T sY[16 * KB * FLD];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
@@ -233,21 +248,19 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     const int g = blockIdx.x * 16 + cl;
     const bool gin = g < C;
     const int i3r = 16 * t + cl;                         // row of T3 (A operand)
-    T a[NKS], b[NKS];
+    const int ks3 = (n3 + 3) >> 2;
+    T a[NKS], b[NKS], c[PRE ? NKS : 1];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
         const int k = 4 * s + kb;                        // j3
-        a[s] = (i3r < n3 && k < n3) ? T3f[(size_t)i3r * n3 + k] : T(0);
+        a[s] = (i3r < n3 && k < n3) ? T3ft[(size_t)k * n3 + i3r] : T(0);
         b[s] = (gin && k < n3) ? in[(size_t)k * C + g] : T(0);
+        if constexpr (PRE) c[s] = (i3r < n3 && k < n3) ? T3bt[(size_t)k * n3 + i3r] : T(0);
     }
     Acc y = Acc{0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        if constexpr (PREC == 1)
-            y = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], y, 0, 0, 0);
-        else
-            y = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], y, 0, 0, 0);
-    }
+    for (int s = 0; s < NKS; ++s)
+        if (s < ks3) y = mma_step<PREC>(a[s], b[s], y);
     double l12 = 0.0;
     if (gin) {
         const int i2 = g / n1, i1 = g - i2 * n1;
@@ -263,16 +276,17 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
         const int k = 4 * s + kb;
-        a[s] = (i3r < n3 && k < n3) ? T3b[(size_t)i3r * n3 + k] : T(0);
+        if constexpr (!PRE) a[s] = (i3r < n3 && k < n3) ? T3bt[(size_t)k * n3 + i3r] : T(0);
         b[s] = sY[k * FLD + cl];
     }
     Acc z = Acc{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
-        if constexpr (PREC == 1)
-            z = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], z, 0, 0, 0);
-        else
-            z = __builtin_amdgcn_mfma_f32_16x16x4f32(a[s], b[s], z, 0, 0, 0);
+        if constexpr (PRE) {
+            if (s < ks3) z = mma_step<PREC>(c[s], b[s], z);
+        } else {
+            if (s < ks3) z = mma_step<PREC>(a[s], b[s], z);
+        }
     }
     if (!gin) return;
 #pragma unroll
@@ -287,16 +301,17 @@ hipError_t fused_kb(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
     using T = typename G<PREC>::T;
     hipError_t e;
     // forward x and y
-    dim3 gxy((f.n1 + 15) / 16, f.n3);
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.UT[0], f.UT[1], f.n1, f.n2);
+    dim3 gxy((f.n2 + 15) / 16, f.n3);
+    // (T = U^T forward, U backward; each passed transposed)
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.U[0], f.U[1], f.n1, f.n2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // forward z, scaling, backward z (in place on tmp)
     dim3 gz((f.n1 * f.n2 + 15) / 16);
-    hipLaunchKernelGGL((fd_z_pass<PREC, KB>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.UT[2], f.U[2],
+    hipLaunchKernelGGL((fd_z_pass<PREC, KB>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.U[2], f.UT[2],
                        f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // backward x and y
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.U[0], f.U[1], f.n1,
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.UT[0], f.UT[1], f.n1,
                        f.n2);
     return hipGetLastError();
 }

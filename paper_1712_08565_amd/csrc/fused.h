@@ -35,7 +35,7 @@ struct FusedArgs {
     const int* wts3 = nullptr;
     const T* cz = nullptr;
     int ntx = 0, nty = 0, zchunk = 0;
-    // interval schedule: records of four ints per interval (see FusedSched),
+    // interval schedule: records of FUSED_REC ints per interval (see FusedSched),
     // z range r uses records sched_off[r] .. sched_off[r + 1] - 1
     const int* sched = nullptr;
     const int* sched_off = nullptr;
@@ -52,10 +52,16 @@ struct FusedArgs {
 // plane written last interval; 10 reduce the partials written last interval;
 // 11-12 U slot of the entering plane; 13 psi slot written; 14 psi slot read;
 // 15 partial slot reduced; 16 partial slot written; 17 V slot read; 18-19 U
-// slot written; 20 V slot written.
+// slot written; 20 V slot written.  The column role reads its events already
+// split by step: ev bits 3j, 3j + 1, 3j + 2 = window entry, retirement, plane
+// k + j processed, at step j = 0, 1; czo = (k - k0) CZ, the offset of plane k's
+// z coefficients in the range's table; cnext0/1 = the planes (clamped to the
+// range) whose coefficients are loaded for the next interval.
 struct FusedSched {
-    int f, k, red_i3, tstage;
+    int f, k, red_i3, tstage, ev, czo, cnext0, cnext1;
 };
+constexpr int FUSED_REC = 8;      // ints per interval record
+static_assert(sizeof(FusedSched) == FUSED_REC * sizeof(int), "record layout");
 
 // Resident workgroups of the fused FP64 apply kernel of degree p on the
 // current device (compute units x workgroups per unit).

@@ -40,13 +40,22 @@ constexpr int LD = 17;            // padded row length of 16 x 16 LDS blocks
 constexpr int BLK = 16 * LD;
 constexpr int kMaxZ = FUSED_MAX_Z;   // longest z range of one workgroup
 
-// Schedule records are read-only for the whole launch and uniform across a
-// wave: reading them through the constant address space makes them scalar
-// loads, which leave the vector memory counter (and the loads it tracks) alone.
-typedef const __attribute__((address_space(4))) int cint;
-
 // s_waitcnt immediate for gfx9: vmcnt 0, expcnt and lgkmcnt left at their maxima
 constexpr int kVmcnt0 = 0x0F70;
+
+// Raw buffer access (base and plane offset in scalar registers, the lane's
+// offset in a vector register), so that streaming loads need no 64-bit vector
+// address arithmetic.  Offsets are in bytes and below 2^31 (checked on the host).
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
+}
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
 
 template <typename T>
 struct MF;
@@ -152,9 +161,12 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
     }
     for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
-    // this range's interval records (uniform: read through the scalar cache)
     const int r0 = a.sched_off[zc], nrec = a.sched_off[zc + 1] - r0;
-    const cint* rec = (const cint*)(a.sched + 4 * (size_t)r0);
+    // the range's interval records, one per lane (at most 64, checked on the
+    // host); interval r's fields are read with readlane into scalar registers
+    const int* lrec = a.sched + FUSED_REC * (size_t)(r0 + (lane < nrec ? lane : 0));
+    const int Rf = lrec[0], Rred = lrec[2], Rts = lrec[3], Rev = lrec[4], Rczo = lrec[5], Rc0 = lrec[6],
+              Rc1 = lrec[7];
 
     // ---- MFMA-role helpers ------------------------------------------------
     // A operand for a product whose B operand is an accumulator: the K index of
@@ -190,19 +202,19 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     // outside the grid read a clamped address; their trial values are exactly 0),
     // so every interval issues the same loads in the same order and a use waits
     // only for its own slot, not for the loads issued after it.
-    // (plane base in scalar registers, the column's byte offset in a vector one)
     const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
-    auto cload3 = [&](T (&dst)[3], int kq) {
-        const size_t ko = (size_t)min(kq, k1 - 1) * plane;
+    const unsigned pbytes = (unsigned)(plane * sizeof(T));
+    const __amdgpu_buffer_rsrc_t rC[3] = {buf_rsrc(a.C + poff[0]), buf_rsrc(a.C + poff[1]), buf_rsrc(a.C + poff[2])};
+    auto cload3 = [&](T (&dst)[3], int kq) {              // kq: a plane of this range
 #pragma unroll
-        for (int al = 0; al < 3; ++al)
-            dst[al] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a.C + poff[al] + ko) + cbyte);
+        for (int al = 0; al < 3; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
     };
 
     // one quadrature plane of column work: g = (z trial row) . window,
-    // psi_alpha = C_(alpha beta) g, ring += (z test rows) psi
-    auto valu_plane = [&](int kq, const T (&C)[3]) {
-        const T* cz = sZ + (size_t)(kq - k0) * CZ;
+    // psi_alpha = C_(alpha beta) g, ring += (z test rows) psi; czo = offset of
+    // the plane's z coefficients
+    auto valu_plane = [&](int czo, const T (&C)[3]) {
+        const T* cz = sZ + czo;
         const T* ct3 = cz + (beta == 2 ? RT : 0);               // B3 row, or B-dot3 for beta = z
         T g = T(0);
 #pragma unroll
@@ -223,6 +235,9 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
 
     // ---- the interval loop: every wave walks the same host-computed records ----
     if (mrole) {
+        // wave 15 (contraction, reduction and atomics) ends each interval last:
+        // it gets the first issue slots of its SIMD
+        if (mw == 3) __builtin_amdgcn_s_setprio(2);
         // x/y test contraction of the plane retired in the previous interval.
         // Fields sharing the y weight variant v2 = 2[alpha = y] + [beta = y] are
         // summed after their x products (X = sum_f psi_f W1^(v1_f)T, Z = W2^(v2) X):
@@ -267,15 +282,17 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             vok[q] = j1 < a.n1 && j2 < a.n2;
             voff[q] = (unsigned)(min(j2, a.n2 - 1) * a.n1 + min(j1, a.n1 - 1));
         }
-        const size_t vplane = (size_t)a.n1 * a.n2;
+        const unsigned vpbytes = (unsigned)((size_t)a.n1 * a.n2 * sizeof(T));
+        const __amdgpu_buffer_rsrc_t rV = buf_rsrc(a.v);
         auto vload = [&](int j3) {
-            const T* vp = a.v + (size_t)min(max(j3, 0), a.n3 - 1) * vplane;
+            const unsigned so = (unsigned)min(max(j3, 0), a.n3 - 1) * vpbytes;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) vq[q] = vp[voff[q]];
+            for (int q = 0; q < 2; ++q) vq[q] = buf_load<T>(rV, voff[q] * (unsigned)sizeof(T), so);
         };
-        if (stager && nrec > 0) vload(rec[3]);
+        if (stager && nrec > 0) vload(__builtin_amdgcn_readlane(Rts, 0));
         for (int r = 0; r < nrec; ++r) {
-            const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
+            const int fl = __builtin_amdgcn_readlane(Rf, r), red_i3 = __builtin_amdgcn_readlane(Rred, r),
+                      ts = __builtin_amdgcn_readlane(Rts, r);
             if ((fl >> 7) & 1) {                                 // produce: x products of plane tprod
                 const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
                 T a0 = T(0), a1 = T(0);
@@ -342,12 +359,12 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         // loads may still be in flight).
         T Cs[2][3];
         cload3(Cs[0], k0);
-        cload3(Cs[1], k0 + 1);
+        cload3(Cs[1], min(k0 + 1, k1 - 1));
         __builtin_amdgcn_s_waitcnt(kVmcnt0);
         for (int r = 0; r < nrec; ++r) {
-            const int fl = rec[4 * r], kq = rec[4 * r + 1];
-            const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
-            const int nsteps = max(nv, max(in_at, out_at) + 1);   // <= 2
+            const int fl = __builtin_amdgcn_readlane(Rf, r), ev = __builtin_amdgcn_readlane(Rev, r);
+            const int czo = __builtin_amdgcn_readlane(Rczo, r), cn0 = __builtin_amdgcn_readlane(Rc0, r),
+                      cn1 = __builtin_amdgcn_readlane(Rc1, r);
             if (wave == 2 && ((fl >> 9) & 1)) {
                 const int ps = (fl >> 14) & 1, rs = (fl >> 16) & 1;
                 const T* Bt = sCoef[4 + v1_of(4)];
@@ -370,7 +387,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
 
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (j < nsteps && j == in_at) {
+                if ((ev >> (3 * j)) & 1) {                       // window entry
 #pragma unroll
                     for (int s = 0; s < RT - 1; ++s) Uw[s] = Uw[s + 1];
                     const T* A = sA[(fl >> 11) & 3][ab] + jsy * LD + q1l;
@@ -379,7 +396,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                     for (int s = 0; s < RT; ++s) u += cbY[s] * A[s * LD];
                     Uw[RT - 1] = u;
                 }
-                if (j < nsteps && j == out_at) {
+                if ((ev >> (3 * j + 1)) & 1) {                   // retirement
                     if ((fl >> 6) & 1) {
                         const int ps = (fl >> 13) & 1;
 #pragma unroll
@@ -392,8 +409,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
                         acc[al][RO - 1] = T(0);
                     }
                 }
-                if (j < nv) valu_plane(kq + j, Cs[j]);
-                cload3(Cs[j], kq + nv + j);  // plane j of the next interval
+                if ((ev >> (3 * j + 2)) & 1) valu_plane(czo + j * CZ, Cs[j]);
+                cload3(Cs[j], j ? cn1 : cn0);                    // plane j of the next interval
             }
             lds_barrier();
         }
@@ -464,7 +481,11 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     }
     for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
     const int r0 = a.schedT_off[zc], nrec = a.schedT_off[zc + 1] - r0;
-    const cint* rec = (const cint*)(a.schedT + 4 * (size_t)r0);
+    // the range's interval records, one per lane (at most 64, checked on the
+    // host); interval r's fields are read with readlane into scalar registers
+    const int* lrec = a.schedT + FUSED_REC * (size_t)(r0 + (lane < nrec ? lane : 0));
+    const int Rf = lrec[0], Rred = lrec[2], Rts = lrec[3], Rev = lrec[4], Rczo = lrec[5], Rc0 = lrec[6],
+              Rc1 = lrec[7];
 
     // A operand read transposed from a [k][m] LDS block, K index = accumulator row
     auto ld_accAt = [&](T (&av)[4], const T* A) {
@@ -490,6 +511,9 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     lds_barrier();
 
     if (mrole) {
+        // the MFMA waves' chains are the long ones of an interval (measured: a
+        // higher issue priority helps up to p = 5)
+        if constexpr (P <= 5) __builtin_amdgcn_s_setprio(1);
         // MFMA waves.  Input planes: the x product with W1^(v1), then the y
         // products of the fields with that v1 (field f = 3 alpha + beta has
         // v1 = 2[alpha = x] + [beta = x], v2 = 2[alpha = y] + [beta = y]):
@@ -509,13 +533,14 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
             vok[q] = i1 < a.n1 && i2 < a.n2;
             voff[q] = (unsigned)(min(i2, a.n2 - 1) * a.n1 + min(i1, a.n1 - 1));
         }
-        const size_t vplane = (size_t)a.n1 * a.n2;
+        const unsigned vpbytes = (unsigned)((size_t)a.n1 * a.n2 * sizeof(T));
+        const __amdgpu_buffer_rsrc_t rV = buf_rsrc(a.v);
         auto vload = [&](int i3) {
-            const T* vp = a.v + (size_t)min(max(i3, 0), a.n3 - 1) * vplane;
+            const unsigned so = (unsigned)min(max(i3, 0), a.n3 - 1) * vpbytes;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) vq[q] = vp[voff[q]];
+            for (int q = 0; q < 4; ++q) vq[q] = buf_load<T>(rV, voff[q] * (unsigned)sizeof(T), so);
         };
-        if (stager && nrec > 0) vload(rec[3]);
+        if (stager && nrec > 0) vload(__builtin_amdgcn_readlane(Rts, 0));
         // y products of one x result: fields given as (f, v2) pairs
         auto yprods = [&](const acc_t& A, int us, int f, int v2) {
             T wv[4];
@@ -525,7 +550,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
             store16<T>(sU[us][f], Y, cl, kb);
         };
         for (int r = 0; r < nrec; ++r) {
-            const int fl = rec[4 * r], red_i3 = rec[4 * r + 2], ts = rec[4 * r + 3];
+            const int fl = __builtin_amdgcn_readlane(Rf, r), red_i3 = __builtin_amdgcn_readlane(Rred, r),
+                      ts = __builtin_amdgcn_readlane(Rts, r);
             if (((fl >> 7) & 1) && mw < 3) {
                 const int vs = (fl >> 17) & 1, us = (fl >> 18) & 3;
                 if (mw == 0) {
@@ -604,14 +630,15 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         const size_t poff[3] = {((pidx >> 0) & 15) * Nq, ((pidx >> 4) & 15) * Nq, ((pidx >> 8) & 15) * Nq};
         // coefficient slots loaded one interval ahead, as in the forward kernel
         const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
+        const unsigned pbytes = (unsigned)(plane * sizeof(T));
+        const __amdgpu_buffer_rsrc_t rC[3] = {buf_rsrc(a.C + poff[0]), buf_rsrc(a.C + poff[1]),
+                                              buf_rsrc(a.C + poff[2])};
         auto cload3 = [&](T (&dst)[3], int kq) {
-            const size_t ko = (size_t)min(kq, k1 - 1) * plane;
 #pragma unroll
-            for (int al = 0; al < 3; ++al)
-                dst[al] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(a.C + poff[al] + ko) + cbyte);
+            for (int al = 0; al < 3; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
         };
-        auto valu_plane = [&](int kq, const T (&C)[3]) {
-            const T* cz = sZ + (size_t)(kq - k0) * CZ;
+        auto valu_plane = [&](int czo, const T (&C)[3]) {
+            const T* cz = sZ + czo;
             // z weight variant of field (alpha, beta): 2 [alpha = z] + [beta = z]
             const T* w01 = cz + 2 * RT + (beta == 2 ? 1 : 0) * RO;
             const T* w2 = cz + 2 * RT + (beta == 2 ? 3 : 2) * RO;
@@ -629,15 +656,15 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         };
         T Cs[2][3];
         cload3(Cs[0], k0);
-        cload3(Cs[1], k0 + 1);
+        cload3(Cs[1], min(k0 + 1, k1 - 1));
         __builtin_amdgcn_s_waitcnt(kVmcnt0);
         for (int r = 0; r < nrec; ++r) {
-            const int fl = rec[4 * r], kq = rec[4 * r + 1];
-            const int nv = fl & 3, in_at = ((fl >> 2) & 3) - 1, out_at = ((fl >> 4) & 3) - 1;
-            const int nsteps = max(nv, max(in_at, out_at) + 1);   // <= 2
+            const int fl = __builtin_amdgcn_readlane(Rf, r), ev = __builtin_amdgcn_readlane(Rev, r);
+            const int czo = __builtin_amdgcn_readlane(Rczo, r), cn0 = __builtin_amdgcn_readlane(Rc0, r),
+                      cn1 = __builtin_amdgcn_readlane(Rc1, r);
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                if (j < nsteps && j == in_at) {
+                if ((ev >> (3 * j)) & 1) {                       // window entry
                     const int us = (fl >> 11) & 3;
 #pragma unroll
                     for (int al = 0; al < 3; ++al) {
@@ -646,14 +673,14 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
                         Yw[al][RO - 1] = sU[us][3 * al + beta][q2l * LD + q1l];
                     }
                 }
-                if (j < nsteps && j == out_at) {
+                if ((ev >> (3 * j + 1)) & 1) {                   // retirement
                     if ((fl >> 6) & 1) sP[(fl >> 13) & 1][beta][q2l * LD + q1l] = orng[0];
 #pragma unroll
                     for (int s = 0; s < RT - 1; ++s) orng[s] = orng[s + 1];
                     orng[RT - 1] = T(0);
                 }
-                if (j < nv) valu_plane(kq + j, Cs[j]);
-                cload3(Cs[j], kq + nv + j);
+                if ((ev >> (3 * j + 2)) & 1) valu_plane(czo + j * CZ, Cs[j]);
+                cload3(Cs[j], j ? cn1 : cn0);
             }
             lds_barrier();
         }
