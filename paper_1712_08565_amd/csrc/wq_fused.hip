@@ -98,6 +98,55 @@ __device__ inline void store16(T* tile, const typename MF<T>::acc& c, int cl, in
     for (int v = 0; v < 4; ++v) tile[MF<T>::drow(kb, v) * LD + cl] = c[v];
 }
 
+// Set-up of a workgroup: the tile's twelve factor blocks (three entries per
+// thread) and the range's z coefficients.  All loads are issued together and
+// written to LDS afterwards, so the set-up costs one memory latency.
+template <typename T, int CZ>
+struct SetupRegs {
+    static constexpr int ZL = (kMaxZ * CZ + 1023) / 1024;
+    T cv[3];
+    T zv[ZL];
+};
+
+template <typename T>
+__device__ inline const T* setup_src(const FusedArgs<T>& a, int tl, int t1, int t2) {
+    if (tl < 2) return a.tilesX + ((size_t)t1 * 6 + tl) * 256;                 // B1_d
+    if (tl < 4) return a.tilesY + ((size_t)t2 * 6 + (tl - 2)) * 256;           // B2_d
+    if (tl < 8) return a.tilesX + ((size_t)t1 * 6 + 2 + (tl - 4)) * 256;       // W1_v
+    return a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;                   // W2_v
+}
+
+template <typename T, int CZ>
+__device__ inline void setup_load(SetupRegs<T, CZ>& su, const FusedArgs<T>& a, int tid, int t1, int t2, int k0,
+                                  int k1) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int idx = tid + 1024 * i;
+        su.cv[i] = setup_src(a, idx >> 8, t1, t2)[idx & 255];
+    }
+    const int nz = (k1 - k0) * CZ;
+#pragma unroll
+    for (int i = 0; i < SetupRegs<T, CZ>::ZL; ++i) {
+        const int idx = tid + 1024 * i;
+        su.zv[i] = idx < nz ? a.cz[(size_t)k0 * CZ + idx] : T(0);
+    }
+}
+
+template <typename T, int CZ>
+__device__ inline void setup_store(const SetupRegs<T, CZ>& su, T (*sCoef)[BLK], T* sZ, int tid, int k0, int k1) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int idx = tid + 1024 * i, e = idx & 255;
+        sCoef[idx >> 8][(e >> 4) * LD + (e & 15)] = su.cv[i];
+    }
+    const int nz = (k1 - k0) * CZ;
+#pragma unroll
+    for (int i = 0; i < SetupRegs<T, CZ>::ZL; ++i) {
+        const int idx = tid + 1024 * i;
+        if (idx < nz) sZ[idx] = su.zv[i];
+    }
+}
+
 // 1024 threads in two roles, one barrier per interval (one quadrature plane).
 //   Column waves 0-11: wave group beta = wave / 4 (trial derivative direction x,
 //     y, z) owns the fields f = 3 alpha + beta, alpha = x, y, z, of all 256
@@ -150,17 +199,10 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
     const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
-    // coefficient blocks of this tile, z coefficients and window starts
-    for (int idx = tid; idx < 12 * 256; idx += 1024) {
-        const int tl = idx >> 8, e = idx & 255;
-        const T* src;
-        if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
-        else if (tl < 4) src = a.tilesY + ((size_t)t2 * 6 + (tl - 2)) * 256;
-        else if (tl < 8) src = a.tilesX + ((size_t)t1 * 6 + 2 + (tl - 4)) * 256;
-        else src = a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;
-        sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
-    }
-    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
+    // coefficient blocks of this tile and z coefficients: loads issued here, LDS
+    // written just before the first barrier
+    SetupRegs<T, CZ> su;
+    setup_load(su, a, tid, t1, t2, k0, k1);
     const int r0 = a.sched_off[zc], nrec = a.sched_off[zc + 1] - r0;
     // the range's interval records, one per lane (at most 64, checked on the
     // host); interval r's fields are read with readlane into scalar registers
@@ -231,6 +273,15 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         }
     };
 
+    // band starts (MFMA waves: of point q1 = tid % 16; column waves: of q2) and
+    // the column waves' first coefficient slots, loaded with the set-up
+    const int bX = a.bandX[t1 * 16 + (tid & 15)], bY = a.bandY[t2 * 16 + q2l];
+    T Cs[2][3];
+    if (!mrole) {
+        cload3(Cs[0], k0);
+        cload3(Cs[1], min(k0 + 1, k1 - 1));
+    }
+    setup_store(su, sCoef, sZ, tid, k0, k1);
     lds_barrier();
 
     // ---- the interval loop: every wave walks the same host-computed records ----
@@ -261,7 +312,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         // thread (q1, j2) = (mt & 15, mt >> 4) forms A_d[j2][q1] =
         // sum_s B1_d[q1][js + s] V[j2][js + s] over the p + 1 functions at point q1
         const int mt = tid - 768, xq1 = mt & 15, xj2 = mt >> 4;
-        const int jsx = a.bandX[t1 * 16 + xq1];
+        const int jsx = bX;
         T cb0[RT], cb1[RT];
 #pragma unroll
         for (int s = 0; s < RT; ++s) {
@@ -350,16 +401,13 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
         // (y products with the exact band: U_beta[q2][q1] = sum_s B2_e[q2][js + s]
         // A_b[js + s][q1]; beta = x: B2 A_1, y: B-dot2 A_0, z: B2 A_0) and wave 2
         // contracts the {yy} field of the retired plane.
-        const int jsy = a.bandY[t2 * 16 + q2l];
+        const int jsy = bY;
         const T* cbY = sCoef[beta == 1 ? 3 : 2] + q2l * LD + jsy;
         const int ab = beta == 0 ? 1 : 0;
         // slot j holds plane kq + j of the interval.  The first interval's slots
         // are waited for before the loop, so the waits inside it are set by the
         // loop's own load order alone (use of a slot: the other slot's three
         // loads may still be in flight).
-        T Cs[2][3];
-        cload3(Cs[0], k0);
-        cload3(Cs[1], min(k0 + 1, k1 - 1));
         __builtin_amdgcn_s_waitcnt(kVmcnt0);
         for (int r = 0; r < nrec; ++r) {
             const int fl = __builtin_amdgcn_readlane(Rf, r), ev = __builtin_amdgcn_readlane(Rev, r);
@@ -470,16 +518,8 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     const int J1 = __builtin_amdgcn_readfirstlane(a.JX[t1]), I1 = __builtin_amdgcn_readfirstlane(a.IX[t1]);
     const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
-    for (int idx = tid; idx < 12 * 256; idx += 1024) {
-        const int tl = idx >> 8, e = idx & 255;
-        const T* src;
-        if (tl < 2) src = a.tilesX + ((size_t)t1 * 6 + tl) * 256;
-        else if (tl < 4) src = a.tilesY + ((size_t)t2 * 6 + (tl - 2)) * 256;
-        else if (tl < 8) src = a.tilesX + ((size_t)t1 * 6 + 2 + (tl - 4)) * 256;
-        else src = a.tilesY + ((size_t)t2 * 6 + 2 + (tl - 8)) * 256;
-        sCoef[tl][(e >> 4) * LD + (e & 15)] = src[e];
-    }
-    for (int idx = tid; idx < (k1 - k0) * CZ; idx += 1024) sZ[idx] = a.cz[(size_t)k0 * CZ + idx];
+    SetupRegs<T, CZ> su;
+    setup_load(su, a, tid, t1, t2, k0, k1);
     const int r0 = a.schedT_off[zc], nrec = a.schedT_off[zc + 1] - r0;
     // the range's interval records, one per lane (at most 64, checked on the
     // host); interval r's fields are read with readlane into scalar registers
@@ -508,6 +548,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         for (int s = 0; s < 4; ++s) c = MF<T>::mma(av[s], bv[s], c);
     };
 
+    setup_store(su, sCoef, sZ, tid, k0, k1);
     lds_barrier();
 
     if (mrole) {
