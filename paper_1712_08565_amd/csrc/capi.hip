@@ -700,6 +700,16 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
         o_ubf[l] = off;
         if (prec_mask & WQ_BF16) off += al256(2 * np * np * 2);
     }
+    const int nmax = std::max(f.n[0], std::max(f.n[1], f.n[2]));
+    const int ldp = nmax <= 144 ? (nmax + 15) / 16 * 16 : 0;
+    size_t o_pad64 = 0, o_pad32 = 0;
+    if (ldp) {
+        const size_t blk = al256((size_t)ldp * ldp * 8);
+        o_pad64 = off;
+        off += 6 * blk;
+        o_pad32 = off;
+        if (prec_mask & WQ_F32) off += 6 * al256((size_t)ldp * ldp * 4);
+    }
     const size_t o_scr = off;
     off += al256(f.N * 8);
     if (ws_needed) *ws_needed = off;
@@ -737,6 +747,31 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
                 }
             f.Ubf[l] = reinterpret_cast<uint16_t*>(base + o_ubf[l]);
             HIP_TRY(hipMemcpy(f.Ubf[l], ub.data(), ub.size() * 2, hipMemcpyHostToDevice), "upload Ubf");
+        }
+    }
+    if (ldp) {
+        f.ldp = ldp;
+        const size_t blk64 = al256((size_t)ldp * ldp * 8), blk32 = al256((size_t)ldp * ldp * 4);
+        for (int l = 0; l < 3; ++l) {
+            const int n = f.n[l];
+            std::vector<double> up((size_t)ldp * ldp, 0.0), utp((size_t)ldp * ldp, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    up[(size_t)i * ldp + j] = f.hU[l][(size_t)i * n + j];
+                    utp[(size_t)i * ldp + j] = f.hU[l][(size_t)j * n + i];
+                }
+            f.Up64[l] = reinterpret_cast<double*>(base + o_pad64 + (2 * l) * blk64);
+            f.UTp64[l] = reinterpret_cast<double*>(base + o_pad64 + (2 * l + 1) * blk64);
+            HIP_TRY(hipMemcpy(f.Up64[l], up.data(), up.size() * 8, hipMemcpyHostToDevice), "upload padded U");
+            HIP_TRY(hipMemcpy(f.UTp64[l], utp.data(), utp.size() * 8, hipMemcpyHostToDevice), "upload padded U^T");
+            if (prec_mask & WQ_F32) {
+                std::vector<float> up32(up.begin(), up.end()), utp32(utp.begin(), utp.end());
+                f.Up32[l] = reinterpret_cast<float*>(base + o_pad32 + (2 * l) * blk32);
+                f.UTp32[l] = reinterpret_cast<float*>(base + o_pad32 + (2 * l + 1) * blk32);
+                HIP_TRY(hipMemcpy(f.Up32[l], up32.data(), up32.size() * 4, hipMemcpyHostToDevice), "upload padded U32");
+                HIP_TRY(hipMemcpy(f.UTp32[l], utp32.data(), utp32.size() * 4, hipMemcpyHostToDevice),
+                        "upload padded U32^T");
+            }
         }
     }
     f.scratch = base + o_scr;

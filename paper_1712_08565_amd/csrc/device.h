@@ -70,6 +70,13 @@ struct FdPc {
     float* UT32[3] = {nullptr, nullptr, nullptr};
     uint16_t* Ubf[3] = {nullptr, nullptr, nullptr};  // bf16 copies (raw bits)
     float* Ubf_padded = nullptr;
+    // fused passes (every n <= 144): U and U^T zero-padded to ldp = 16 ceil(max n / 16)
+    // in both dimensions, so the kernels read them without bounds checks
+    int ldp = 0;
+    double* Up64[3] = {nullptr, nullptr, nullptr};
+    double* UTp64[3] = {nullptr, nullptr, nullptr};
+    float* Up32[3] = {nullptr, nullptr, nullptr};
+    float* UTp32[3] = {nullptr, nullptr, nullptr};
     double* lam[3] = {nullptr, nullptr, nullptr};    // eigenvalues (device)
     std::vector<double> hlam[3], hU[3];
     void* scratch = nullptr;    // one N-sized buffer of the widest precision

@@ -39,6 +39,7 @@ struct FdFusedArgs {
     const double* l2 = nullptr;
     const double* l3 = nullptr;
     int n1 = 0, n2 = 0, n3 = 0;
+    int ldp = 0;                     // U, UT: zero-padded ldp x ldp, ldp = 16 ceil(max n / 16)
 };
 
 hipError_t launch_fd_fused(const FdFusedArgs<double>& f, hipStream_t s);

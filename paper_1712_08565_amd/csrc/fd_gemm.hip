@@ -19,6 +19,7 @@
 // epilogue.
 #include <hip/hip_runtime.h>
 
+#include "buffer.h"
 #include "device.h"
 #include "fd_gemm.h"
 
@@ -157,15 +158,18 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
 //   z pass, per 16-column block of g = (i2, i1):
 //     Y[i3][g] = sum_j3 T3f[i3][j3] in[j3][g] / (l1[i1] + l2[i2] + l3[i3])
 //     out[i3][g] = sum_j3 T3b[i3][j3] Y[j3][g]       (Y through LDS; in may be out)
-// The small matrices are passed transposed (Tt[j][i] = T[i][j]), so that the 16
-// lanes of an operand column read 16 consecutive entries.
-// One wave per 16-wide block (KB = ceil(n / 16) waves).  Every operand that
-// does not depend on the first product, the second product's matrix included,
-// is loaded before the first product (for KB <= PRELOAD_KB; larger blocks load
-// the second matrix after it, to bound registers), and contraction steps past
-// the true length are skipped.
+// The small matrices are passed transposed (Tt[j][i] = T[i][j]) and zero-padded
+// to ldp x ldp, ldp = 16 KB: an operand column is 16 consecutive entries and no
+// load needs a bounds check.  Data loads are unconditional too: rows and columns
+// past the extents are clamped to the last one (finite values that meet the
+// zero padding of the matrix, or land in outputs that are not stored).  All
+// loads are raw buffer loads with the step offset in a scalar register.
+// One wave per 16-wide block (KB = ceil(n / 16) waves); NP planes (xy) or
+// column blocks (z) per workgroup share the matrices, which are loaded once
+// (double-buffered LDS block, one barrier per item).  FP64 with KB > 6 loads
+// the second matrix after the first product, into the first one's registers.
+// Contraction steps past the true length are skipped.
 constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
-constexpr int PRELOAD_KB = 6;
 
 template <int PREC>
 __device__ inline typename G<PREC>::Acc mma_step(typename G<PREC>::T a, typename G<PREC>::T b,
@@ -176,62 +180,89 @@ __device__ inline typename G<PREC>::Acc mma_step(typename G<PREC>::T a, typename
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <int PREC, int KB>
+template <int PREC, int KB, int NP>
 __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T* __restrict__ in,
                                                       typename G<PREC>::T* __restrict__ out,
                                                       const typename G<PREC>::T* __restrict__ T1t,
-                                                      const typename G<PREC>::T* __restrict__ T2t, int n1, int n2) {
+                                                      const typename G<PREC>::T* __restrict__ T2t, int n1, int n2,
+                                                      int n3) {
     using T = typename G<PREC>::T;
     using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
+    constexpr int LDP = 16 * KB;                         // padded matrix row
     constexpr int LDQ = 16 * KB + 1;                     // odd row length of the Q block
-    constexpr bool PRE = KB <= PRELOAD_KB;
-    __shared__ T sQ[16 * LDQ];
+    constexpr bool PRE = PREC != 1 || KB <= 6;           // both matrices in registers from the start
+    static_assert(NP == 1 || PRE, "several planes per block keep both matrices in registers");
+    __shared__ T sQ[NP > 1 ? 2 : 1][16 * LDQ];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
     const int r0 = blockIdx.x * 16;                      // first i2 of this block
-    const size_t pl = (size_t)blockIdx.y * n1 * n2;       // z-plane offset
+    const int z0 = blockIdx.y * NP;                      // first z-plane of this block
+    const unsigned psz = (unsigned)(n1 * n2);
     const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;  // contraction steps of the two products
     const int i2a = r0 + cl, jc = 16 * t + cl;           // A row (i2) and B column (j1, then i1)
-    T a[NKS], b[NKS], c[PRE ? NKS : 1];
+    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), r1 = buf_rsrc(T1t), r2 = buf_rsrc(T2t);
+    const int jcc = min(jc, n1 - 1);                     // clamped data column
+    const unsigned vo = (unsigned)((kb * n1 + jcc) * sizeof(T));
+    const unsigned va = (unsigned)((kb * LDP + i2a) * sizeof(T)), vc = (unsigned)((kb * LDP + jc) * sizeof(T));
+    constexpr unsigned kstep = 4 * LDP * sizeof(T);      // bytes between contraction steps of a matrix
+    T a[NKS], c[PRE ? NKS : 1], b[NP][NKS];
 #pragma unroll
     for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;
-        a[s] = (i2a < n2 && k < n2) ? T2t[(size_t)k * n2 + i2a] : T(0);
-        b[s] = (jc < n1 && k < n2) ? in[pl + (size_t)k * n1 + jc] : T(0);
-        if constexpr (PRE) c[s] = (jc < n1 && k < n1) ? T1t[(size_t)k * n1 + jc] : T(0);
-    }
-    Acc q = Acc{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < NKS; ++s)
-        if (s < ks2) q = mma_step<PREC>(a[s], b[s], q);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sQ[G<PREC>::drow(kb, v) * LDQ + jc] = q[v];   // columns >= n1 hold zeros
-    __syncthreads();
-    Acc r = Acc{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;
-        a[s] = sQ[cl * LDQ + k];
-        if constexpr (!PRE) b[s] = (jc < n1 && k < n1) ? T1t[(size_t)k * n1 + jc] : T(0);
+        a[s] = buf_load<T>(r2, va, s * kstep);
+        if constexpr (PRE) c[s] = buf_load<T>(r1, vc, s * kstep);
     }
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        if constexpr (PRE) {
-            if (s < ks1) r = mma_step<PREC>(a[s], c[s], r);
-        } else {
-            if (s < ks1) r = mma_step<PREC>(a[s], b[s], r);
+    for (int p = 0; p < NP; ++p) {
+        const int zp = min(z0 + p, n3 - 1);             // (a plane past the end is not used)
+#pragma unroll
+        for (int s = 0; s < NKS; ++s) {
+            if (4 * s + 3 < n2)                          // whole step inside the plane
+                b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
+            else if (s < ks2)                            // last step: rows clamped
+                b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
+                                      (unsigned)(zp * psz * sizeof(T)));
+            else
+                b[p][s] = T(0);                          // step skipped
         }
     }
-    if (jc >= n1) return;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int i2 = r0 + G<PREC>::drow(kb, v);
-        if (i2 < n2) out[pl + (size_t)i2 * n1 + jc] = r[v];
+    for (int p = 0; p < NP; ++p) {
+        if (z0 + p < n3) {                               // uniform over the block
+            T* Q = sQ[p & 1];
+            Acc q = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s)
+                if (s < ks2) q = mma_step<PREC>(a[s], b[p][s], q);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Q[G<PREC>::drow(kb, v) * LDQ + jc] = q[v];
+            __syncthreads();
+            T(&aq)[NKS] = b[p];                          // the plane's data is dead: its registers take Q
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                aq[s] = Q[cl * LDQ + 4 * s + kb];
+                if constexpr (!PRE) a[s] = buf_load<T>(r1, vc, s * kstep);   // (NP = 1: a is dead)
+            }
+            Acc r = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s < ks1) {
+                    if constexpr (PRE) r = mma_step<PREC>(aq[s], c[s], r);
+                    else r = mma_step<PREC>(aq[s], a[s], r);
+                }
+            }
+            if (jc < n1) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i2 = r0 + G<PREC>::drow(kb, v);
+                    if (i2 < n2) out[(size_t)(z0 + p) * psz + (size_t)i2 * n1 + jc] = r[v];
+                }
+            }
+        }
     }
 }
 
-template <int PREC, int KB>
+template <int PREC, int KB, int NP>
 __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* in, typename G<PREC>::T* out,
                                                      const typename G<PREC>::T* __restrict__ T3ft,
                                                      const typename G<PREC>::T* __restrict__ T3bt,
@@ -240,80 +271,134 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     using T = typename G<PREC>::T;
     using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
-    constexpr bool PRE = KB <= PRELOAD_KB;
-    __shared__ T sY[16 * KB * FLD];
+    constexpr int LDP = 16 * KB;
+    constexpr bool PRE = PREC != 1 || KB <= 6;
+    static_assert(NP == 1 || PRE, "several column blocks per block keep both matrices in registers");
+    __shared__ T sY[NP > 1 ? 2 : 1][16 * KB * FLD];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
     const int C = n1 * n2;
-    const int g = blockIdx.x * 16 + cl;
-    const bool gin = g < C;
     const int i3r = 16 * t + cl;                         // row of T3 (A operand)
     const int ks3 = (n3 + 3) >> 2;
-    T a[NKS], b[NKS], c[PRE ? NKS : 1];
+    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), rf = buf_rsrc(T3ft), rb = buf_rsrc(T3bt);
+    const unsigned va = (unsigned)((kb * LDP + i3r) * sizeof(T));
+    constexpr unsigned kstep = 4 * LDP * sizeof(T);
+    T a[NKS], c[PRE ? NKS : 1], b[NP][NKS];
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;                        // j3
-        a[s] = (i3r < n3 && k < n3) ? T3ft[(size_t)k * n3 + i3r] : T(0);
-        b[s] = (gin && k < n3) ? in[(size_t)k * C + g] : T(0);
-        if constexpr (PRE) c[s] = (i3r < n3 && k < n3) ? T3bt[(size_t)k * n3 + i3r] : T(0);
+    for (int s = 0; s < NKS; ++s) {                      // contraction index j3 = 4 s + kb
+        a[s] = buf_load<T>(rf, va, s * kstep);
+        if constexpr (PRE) c[s] = buf_load<T>(rb, va, s * kstep);
     }
-    Acc y = Acc{0, 0, 0, 0};
+    // every read of `in` by this block (all its column blocks) precedes its
+    // first write: in may be out
 #pragma unroll
-    for (int s = 0; s < NKS; ++s)
-        if (s < ks3) y = mma_step<PREC>(a[s], b[s], y);
-    double l12 = 0.0;
-    if (gin) {
-        const int i2 = g / n1, i1 = g - i2 * n1;
-        l12 = l1[i1] + l2[i2];
-    }
+    for (int p = 0; p < NP; ++p) {
+        const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
+        const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int i3 = 16 * t + G<PREC>::drow(kb, v);
-        sY[(16 * t + G<PREC>::drow(kb, v)) * FLD + cl] =
-            (gin && i3 < n3) ? (T)((double)y[v] / (l12 + l3[i3])) : T(0);
-    }
-    __syncthreads();                                     // every read of `in` by this block is done
-#pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        const int k = 4 * s + kb;
-        if constexpr (!PRE) a[s] = (i3r < n3 && k < n3) ? T3bt[(size_t)k * n3 + i3r] : T(0);
-        b[s] = sY[k * FLD + cl];
-    }
-    Acc z = Acc{0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        if constexpr (PRE) {
-            if (s < ks3) z = mma_step<PREC>(c[s], b[s], z);
-        } else {
-            if (s < ks3) z = mma_step<PREC>(a[s], b[s], z);
+        for (int s = 0; s < NKS; ++s) {
+            if (4 * s + 3 < n3)                          // whole step inside the array
+                b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
+            else if (s < ks3)                            // last step: rows clamped
+                b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
+            else
+                b[p][s] = T(0);                          // step skipped
         }
     }
-    if (!gin) return;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int i3 = 16 * t + G<PREC>::drow(kb, v);
-        if (i3 < n3) out[(size_t)i3 * C + g] = z[v];
+    for (int p = 0; p < NP; ++p) {
+        const int gb = (blockIdx.x * NP + p) * 16;
+        if (gb < C) {                                    // uniform over the block
+            const int g = gb + cl;
+            const bool gin = g < C;
+            T* Y = sY[p & 1];
+            Acc y = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s)
+                if (s < ks3) y = mma_step<PREC>(a[s], b[p][s], y);
+            double l12 = 0.0;
+            if (gin) {
+                const int i2 = g / n1, i1 = g - i2 * n1;
+                l12 = l1[i1] + l2[i2];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i3 = 16 * t + G<PREC>::drow(kb, v);
+                Y[i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)y[v] / (l12 + l3[i3])) : T(0);
+            }
+            __syncthreads();
+            T(&by)[NKS] = b[p];                          // the block's data is dead: its registers take Y
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                by[s] = Y[(4 * s + kb) * FLD + cl];
+                if constexpr (!PRE) a[s] = buf_load<T>(rb, va, s * kstep);   // (NP = 1: a is dead)
+            }
+            Acc z = Acc{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NKS; ++s) {
+                if (s < ks3) {
+                    if constexpr (PRE) z = mma_step<PREC>(c[s], by[s], z);
+                    else z = mma_step<PREC>(a[s], by[s], z);
+                }
+            }
+            if (gin) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i3 = 16 * t + G<PREC>::drow(kb, v);
+                    if (i3 < n3) out[(size_t)i3 * C + g] = z[v];
+                }
+            }
+        }
     }
+}
+
+template <int PREC, int KB, int NP>
+hipError_t fused_np(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
+    using T = typename G<PREC>::T;
+    hipError_t e;
+    // T = U^T forward, U backward; each passed transposed
+    dim3 gxy((f.n2 + 15) / 16, (f.n3 + NP - 1) / NP);
+    const int zb = (f.n1 * f.n2 + 15) / 16;
+    dim3 gz((zb + NP - 1) / NP);
+    // forward y and x
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB, NP>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.U[0], f.U[1], f.n1, f.n2,
+                       f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // forward z, scaling, backward z (in place on tmp)
+    hipLaunchKernelGGL((fd_z_pass<PREC, KB, NP>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.U[2], f.UT[2],
+                       f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // backward y and x
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB, NP>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.UT[0], f.UT[1],
+                       f.n1, f.n2, f.n3);
+    return hipGetLastError();
+}
+
+// compute units of the current device (queried once per process)
+int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                     hipSuccess && n > 0)
+            cus = n;
+        else
+            cus = 256;
+    }
+    return cus;
 }
 
 template <int PREC, int KB>
 hipError_t fused_kb(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
-    using T = typename G<PREC>::T;
-    hipError_t e;
-    // forward x and y
-    dim3 gxy((f.n2 + 15) / 16, f.n3);
-    // (T = U^T forward, U backward; each passed transposed)
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.U[0], f.U[1], f.n1, f.n2);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // forward z, scaling, backward z (in place on tmp)
-    dim3 gz((f.n1 * f.n2 + 15) / 16);
-    hipLaunchKernelGGL((fd_z_pass<PREC, KB>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.U[2], f.UT[2],
-                       f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // backward x and y
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.UT[0], f.UT[1], f.n1,
-                       f.n2);
-    return hipGetLastError();
+    if (f.ldp != 16 * KB) return hipErrorInvalidValue;   // matrices padded for this block count
+    // FP64 with n <= 80: when the one-item grid needs more than one workgroup
+    // per CU, two planes / column blocks per workgroup (the matrices loaded once
+    // for both) are faster; FP32 prefers the wider grid
+    if constexpr (PREC == 1 && KB <= 5) {
+        const long items = (long)((f.n2 + 15) / 16) * f.n3;
+        if (items > device_cus()) return fused_np<PREC, KB, 2>(f, s);
+    }
+    return fused_np<PREC, KB, 1>(f, s);
 }
 
 template <int PREC>

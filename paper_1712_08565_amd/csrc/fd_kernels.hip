@@ -358,15 +358,15 @@ hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], 
 
 hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s) {
     const bool small = P.n[0] <= 144 && P.n[1] <= 144 && P.n[2] <= 144;
-    if (small && (prec == 1 || prec == 2) && !std::getenv("WQFD_FD_MODES")) {
+    if (small && P.ldp && (prec == 1 || prec == 2) && !std::getenv("WQFD_FD_MODES")) {
         if (prec == 1) {
             FdFusedArgs<double> f;
             f.r = static_cast<const double*>(r);
             f.z = static_cast<double*>(z);
             f.tmp = reinterpret_cast<double*>(P.scratch);
             for (int l = 0; l < 3; ++l) {
-                f.U[l] = P.U64[l];
-                f.UT[l] = P.UT64[l];
+                f.U[l] = P.Up64[l];
+                f.UT[l] = P.UTp64[l];
             }
             f.l1 = P.lam[0];
             f.l2 = P.lam[1];
@@ -374,6 +374,7 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
             f.n1 = P.n[0];
             f.n2 = P.n[1];
             f.n3 = P.n[2];
+            f.ldp = P.ldp;
             return launch_fd_fused(f, s);
         }
         FdFusedArgs<float> f;
@@ -381,8 +382,8 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
         f.z = static_cast<float*>(z);
         f.tmp = reinterpret_cast<float*>(P.scratch);
         for (int l = 0; l < 3; ++l) {
-            f.U[l] = P.U32[l];
-            f.UT[l] = P.UT32[l];
+            f.U[l] = P.Up32[l];
+            f.UT[l] = P.UTp32[l];
         }
         f.l1 = P.lam[0];
         f.l2 = P.lam[1];
@@ -390,6 +391,7 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
         f.n1 = P.n[0];
         f.n2 = P.n[1];
         f.n3 = P.n[2];
+        f.ldp = P.ldp;
         return launch_fd_fused(f, s);
     }
     if (small) {

@@ -26,6 +26,7 @@
 
 #include <algorithm>
 
+#include "buffer.h"
 #include "device.h"
 #include "fused.h"
 
@@ -42,20 +43,6 @@ constexpr int kMaxZ = FUSED_MAX_Z;   // longest z range of one workgroup
 
 // s_waitcnt immediate for gfx9: vmcnt 0, expcnt and lgkmcnt left at their maxima
 constexpr int kVmcnt0 = 0x0F70;
-
-// Raw buffer access (base and plane offset in scalar registers, the lane's
-// offset in a vector register), so that streaming loads need no 64-bit vector
-// address arithmetic.  Offsets are in bytes and below 2^31 (checked on the host).
-__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
-}
-template <typename T>
-__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    if constexpr (sizeof(T) == 8)
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-    else
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
 
 template <typename T>
 struct MF;

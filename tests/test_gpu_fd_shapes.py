@@ -13,7 +13,7 @@ from oracle.wq import Space1D
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("els", [(5, 19, 40), (40, 19, 5), (70, 13, 30), (13, 97, 9)])
+@pytest.mark.parametrize("els", [(5, 19, 40), (40, 19, 5), (70, 13, 30), (13, 97, 9), (9, 130, 17)])
 def test_fd_parity_box(els):
     import torch
     from paper_1712_08565_amd import wqfd
