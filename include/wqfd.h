@@ -110,6 +110,11 @@ int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
  * factorisation of Section 3.2).  Same arguments as wq_apply.  Async. */
 int wq_apply_T(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
 
+/* w += K~ v (Algorithm 2, Section 3.2, added to the current contents of w).
+ * Same arguments as wq_apply; w is read and updated.  Available for operators
+ * that use the fused kernels (p <= 7); WQ_EINVAL otherwise.  Async on s. */
+int wq_apply_acc(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
+
 /* Load vector b = W^(0,0) (det J f): the weighted-quadrature mass rule of
  * Section 3.1 (eq. main) applied to f sampled at the quadrature points.
  * f_q device [N_q] FP64, b device [N] FP64.  Async on s. */

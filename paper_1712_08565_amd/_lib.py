@@ -31,6 +31,7 @@ SIGNATURES = [
     ("wq_set_coef", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("wq_apply", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_apply_T", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    ("wq_apply_acc", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_rhs", C.c_int, [_vp, _vp, _vp, _vp]),
     ("wq_grad_K", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("wq_grad_f", C.c_int, [_vp, _vp, _vp, _vp]),

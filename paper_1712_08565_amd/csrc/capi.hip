@@ -633,17 +633,27 @@ int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s) {
     return WQ_OK;
 }
 
-static int apply_common(wq_op A, int prec, const void* v, void* w, wq_stream_t s, bool tr) {
+static int apply_common(wq_op A, int prec, const void* v, void* w, wq_stream_t s, bool tr, bool acc) {
     if (!A || !v || !w) return fail(WQ_EINVAL, "null argument");
     if ((prec != WQ_F64 && prec != WQ_F32) || !(A->op.prec_mask & prec))
         return fail(WQ_EINVAL, "precision not prepared for this operator");
     if (v == w) return fail(WQ_EINVAL, "v and w must not alias");
-    HIP_TRY(wqfd::launch_apply(A->op, prec, v, w, tr, reinterpret_cast<hipStream_t>(s)), tr ? "wq_apply_T" : "wq_apply");
+    if (acc && !A->op.fused) return fail(WQ_EINVAL, "accumulating apply needs the fused kernels (p <= 7)");
+    // the fused kernels add into w; with acc they skip clearing it first
+    HIP_TRY(wqfd::launch_apply(A->op, prec, v, w, tr, reinterpret_cast<hipStream_t>(s), acc),
+            acc ? "wq_apply_acc" : tr ? "wq_apply_T" : "wq_apply");
     return WQ_OK;
 }
 
-int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s) { return apply_common(A, prec, v, w, s, false); }
-int wq_apply_T(wq_op A, int prec, const void* v, void* w, wq_stream_t s) { return apply_common(A, prec, v, w, s, true); }
+int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s) {
+    return apply_common(A, prec, v, w, s, false, false);
+}
+int wq_apply_T(wq_op A, int prec, const void* v, void* w, wq_stream_t s) {
+    return apply_common(A, prec, v, w, s, true, false);
+}
+int wq_apply_acc(wq_op A, int prec, const void* v, void* w, wq_stream_t s) {
+    return apply_common(A, prec, v, w, s, false, true);
+}
 
 int wq_rhs(wq_op A, const double* f_q, double* b, wq_stream_t s) {
     if (!A || !f_q || !b) return fail(WQ_EINVAL, "null argument");

@@ -141,6 +141,11 @@ def wq_apply_T(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec
     return _apply(lib().wq_apply_T, "wq_apply_T", op, v, w, prec, stream)
 
 
+def wq_apply_acc(op: WqOp, v: torch.Tensor, w: torch.Tensor, prec: Optional[int] = None, stream=None) -> torch.Tensor:
+    """w += K~ v in place (fused operators, p <= 7)."""
+    return _apply(lib().wq_apply_acc, "wq_apply_acc", op, v, w, prec, stream)
+
+
 def wq_rhs(op: WqOp, f_q: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     _need(f_q, torch.float64, op.Nq, "f_q")
     b = torch.empty(op.N, dtype=torch.float64, device=op.device) if b is None else b

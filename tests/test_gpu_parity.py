@@ -74,6 +74,35 @@ def test_apply_fp64_parity(name):
     assert e <= 1e-12, f"{e:.3e}"
 
 
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p6", "ring20_p6"])
+def test_apply_acc_parity(name):
+    """w += K~ v (Algorithm 2 added to w): w0 + K~ v after one call, w0 + 2 K~ v
+    after two, against the oracle's apply; FP64 to 1e-12 relative."""
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    v = synth.random_vector(pr.N, 51)
+    w0 = synth.random_vector(pr.N, 52)
+    Kv = pr.apply(v)
+    w = dev(w0)
+    wqfd.wq_apply_acc(dp.A, dev(v), w)
+    e1 = rel(host(w), w0 + Kv)
+    wqfd.wq_apply_acc(dp.A, dev(v), w)
+    e2 = rel(host(w), w0 + 2 * Kv)
+    print(f"[apply acc] {name}: {e1:.2e}, {e2:.2e}")
+    assert e1 <= 1e-12 and e2 <= 1e-12, (e1, e2)
+
+
+def test_apply_acc_refused_without_fused_kernels():
+    """p = 8 runs the staged kernels, which overwrite w: the accumulating call
+    is refused with an error instead of returning a wrong sum."""
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup("ring6_p8")
+    v = dev(synth.random_vector(pr.N, 53))
+    w = dev(synth.random_vector(pr.N, 54))
+    with pytest.raises(Exception, match="fused"):
+        wqfd.wq_apply_acc(dp.A, v, w)
+
+
 @pytest.mark.parametrize("name", APPLY_CASES)
 def test_apply_T_fp64_parity_and_adjoint_identity(name):
     from paper_1712_08565_amd import wqfd
