@@ -51,7 +51,7 @@ METRIC = "WQ apply GDOF/s & time-to-solve to rel.res 1e-10, FP64 vs mixed, p=2..
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wq_apply_fused_f64_ring64_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_08565_amd", "csrc", f) for f in ("wq_fused.hip", "fused.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1712_08565_amd", "csrc", f) for f in ("wq_fused.hip", "fused.h", "buffer.h")]
 EQ_TOL = 1e-10
 RTOL_LADDER = [1e-10, 3e-11, 1e-11, 3e-12, 1e-12, 3e-13, 1e-13]
 
