@@ -19,7 +19,7 @@ from oracle.operator import Problem
 pytestmark = pytest.mark.gpu
 
 APPLY_CASES = ["cube12_p3", "ring8_p2", "ring8_p3", "ring8_p4", "ring8_p5", "ring8_p6", "ring7_p4_kappa",
-               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6"]
+               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7"]
 
 _cache = {}
 
