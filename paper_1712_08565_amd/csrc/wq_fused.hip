@@ -715,9 +715,23 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     }
 }
 
+// Clears w: 16-byte stores when w is 16-byte aligned, element stores otherwise
+// and for the tail.
 template <typename T>
 __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) w[i] = T(0);
+    constexpr size_t V = 16 / sizeof(T);
+    const size_t nv = (reinterpret_cast<uintptr_t>(w) % 16 == 0) ? n / V : 0;
+    const size_t stride = (size_t)gridDim.x * 256, i0 = (size_t)blockIdx.x * 256 + threadIdx.x;
+    float4* wv = reinterpret_cast<float4*>(w);
+    for (size_t i = i0; i < nv; i += stride) wv[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (size_t i = nv * V + i0; i < n; i += stride) w[i] = T(0);
+}
+
+template <typename T>
+void launch_zero(T* w, size_t n, hipStream_t s) {
+    size_t g = (n * sizeof(T) / 16 + 255) / 256;
+    g = g < 1 ? 1 : g > 4096 ? 4096 : g;
+    hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, w, n);
 }
 
 template <typename T, int P>
@@ -752,9 +766,7 @@ hipError_t slots_p(int* slots) {
 template <typename T>
 hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
     const size_t N = (size_t)a.n1 * a.n2 * a.n3;
-    size_t g = (N + 255) / 256;
-    if (g > 4096) g = 4096;
-    if (!a.w_zeroed) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    if (!a.w_zeroed) launch_zero(a.w, N, s);
     switch (p) {
         case 2: return launch_p<T, 2>(a, s);
         case 3: return launch_p<T, 3>(a, s);
@@ -769,9 +781,7 @@ hipError_t launch_fused_apply(const FusedArgs<T>& a, int p, hipStream_t s) {
 template <typename T>
 hipError_t launch_fused_apply_T(const FusedArgs<T>& a, int p, hipStream_t s) {
     const size_t N = (size_t)a.n1 * a.n2 * a.n3;
-    size_t g = (N + 255) / 256;
-    if (g > 4096) g = 4096;
-    if (!a.w_zeroed) hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, a.w, N);
+    if (!a.w_zeroed) launch_zero(a.w, N, s);
     switch (p) {
         case 2: return launch_tp<T, 2>(a, s);
         case 3: return launch_tp<T, 3>(a, s);
