@@ -139,7 +139,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the multi-GPU (z-slab) decomposition is a design note, "
-              "not built (see DESIGN.md).", file=sys.stderr)
+              "not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
