@@ -14,12 +14,13 @@ Plain, slow and written to be checked against the paper by eye:
                (Section 2.2, eqs. exactness1d, weights-support, exactness_K).
 * ``geometry`` spline map, Jacobian and the coefficient tensor C (eq. C).
 * ``operator`` explicit sparse assembly of the WQ stiffness matrix
-               (sum over alpha, beta of W D B, Section 3.2) and a plain
-               matrix-free apply (Algorithm 2, eq. sum-factorization).
+               (sum over alpha, beta of W D B, Section 3.2), the WQ mass
+               matrix of the reaction term (eq. WDB) and plain matrix-free
+               applies (Algorithms 1 and 2, eq. sum-factorization).
 * ``fd``       Fast Diagonalization preconditioner (Section 4, by citation).
 * ``krylov``   right-preconditioned BiCGStab (Section 4).
-* ``adjoint``  gradients of J(u) = 1/2 |u - u_obs|^2 with respect to K at the
-               quadrature points and to f.
+* ``adjoint``  gradients of J(u) = 1/2 |u - u_obs|^2 with respect to K and
+               the reaction coefficient alpha at the quadrature points and to f.
 * ``errors``   H1 / L2 errors against a manufactured solution.
 
 Every function documents the passage it follows.  Readings of places where the

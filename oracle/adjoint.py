@@ -8,6 +8,7 @@ adjoint lambda = K~^{-T} (u - u_obs):
 
     dJ/dC_ab(q) = -(W^(ab)^T lambda)_q (B^(b) u)_q
     dJ/df_q     =  det J(q) (W^(00)^T lambda)_q            (b = W^(00)(det J f), reading R6)
+    dJ/dalpha_q = -det J(q) (W^(00)^T lambda)_q (B u)_q    (reaction term M~ = W^(00) diag(alpha det J) B)
 
 and, through C = det J J^{-1} K J^{-T} (reading R5),
     K = kappa I :  dJ/dkappa_q = sum_ab dJ/dC_ab(q) G_ab(q),  G = det J J^{-1} J^{-T}
@@ -56,3 +57,9 @@ def grad_f(prob, lam):
     Y = prob._shape(lam)
     Wt = mode(S[2].W[(0, 0)].T, mode(S[1].W[(0, 0)].T, mode(S[0].W[(0, 0)].T, Y, 2), 1), 0)
     return prob.detJ * Wt
+
+
+def grad_alpha(prob, lam, u):
+    """dJ/dalpha at the quadrature points: M~ is linear in alpha_q with
+    d M~ / d alpha_q = det J(q) W^(00)[:, q] B[q, :]."""
+    return -prob.detJ * prob.W00_T(prob._shape(lam)) * prob.values_at_quad(u)

@@ -11,6 +11,11 @@ inverted by fast diagonalization (Lynch, Rice and Thomas 1964): with the
 generalized eigenpairs K_l U_l = M_l U_l Lambda_l, U_l^T M_l U_l = I,
 
     P^{-1} = (U_3 (x) U_2 (x) U_1) diag(1 / (lam1_i + lam2_j + lam3_k)) (U_3 (x) U_2 (x) U_1)^T.
+
+For the model problem with a reaction term alpha u, a constant shift sigma (a
+representative value of alpha det J) adds sigma M_3 (x) M_2 (x) M_1 to P; in
+the same eigenbasis that term is sigma I, so the diagonal becomes
+lam1_i + lam2_j + lam3_k + sigma.
 """
 from __future__ import annotations
 
@@ -22,7 +27,8 @@ from .operator import mode
 
 
 class FD:
-    def __init__(self, spaces):
+    def __init__(self, spaces, shift: float = 0.0):
+        self.shift = float(shift)
         self.M = [s.M for s in spaces]
         self.K = [s.K for s in spaces]
         self.n = tuple(s.n for s in spaces)
@@ -32,7 +38,7 @@ class FD:
             self.lam.append(lam)
             self.U.append(U)
         l1, l2, l3 = self.lam
-        self.D = l3[:, None, None] + l2[None, :, None] + l1[None, None, :]
+        self.D = l3[:, None, None] + l2[None, :, None] + l1[None, None, :] + self.shift
 
     def apply(self, r):
         """z = P^{-1} r by the six mode products and the diagonal scaling."""
@@ -50,10 +56,15 @@ class FD:
         out = mode(K3, mode(M2, mode(M1, V, 2), 1), 0)
         out += mode(M3, mode(K2, mode(M1, V, 2), 1), 0)
         out += mode(M3, mode(M2, mode(K1, V, 2), 1), 0)
+        if self.shift:
+            out += self.shift * mode(M3, mode(M2, mode(M1, V, 2), 1), 0)
         return out.ravel()
 
     def P_matrix(self):
         M1, M2, M3 = (sp.csr_matrix(m) for m in self.M)
         K1, K2, K3 = (sp.csr_matrix(k) for k in self.K)
-        return (sp.kron(K3, sp.kron(M2, M1)) + sp.kron(M3, sp.kron(K2, M1))
-                + sp.kron(M3, sp.kron(M2, K1))).tocsr()
+        P = (sp.kron(K3, sp.kron(M2, M1)) + sp.kron(M3, sp.kron(K2, M1))
+             + sp.kron(M3, sp.kron(M2, K1)))
+        if self.shift:
+            P = P + self.shift * sp.kron(M3, sp.kron(M2, M1))
+        return P.tocsr()

@@ -1,5 +1,5 @@
-"""The MF-WQ stiffness operator (Sections 2.2-3.2).  CPU oracle, test
-infrastructure only.
+"""The MF-WQ operator of the model problem -div(K grad u) + alpha u = f
+(Sections 2.2-3.2).  CPU oracle, test infrastructure only.
 
 K~ = sum_{alpha,beta=1..3} W^(alpha,beta) D^(alpha,beta) B^(beta)          (Section 3.2)
 
@@ -10,7 +10,13 @@ with, for direction l (x = 1 fastest, Kronecker order of eq. ordering):
 where B_l^(0) = B_l, B_l^(1) = B-dot_l and W_l^{ab} are the 1D weights of the
 rule for int b_i^{(a)} b_j^{(b)} (eq. exactness_K).
 
-``assemble`` builds K~ explicitly as a scipy.sparse matrix (small sizes only);
+With a reaction coefficient alpha (``set_alpha``) the operator is K~ + M~, where
+M~ = W^(00) D B is the weighted-quadrature mass matrix of Section 3.1 (eq. WDB):
+B = B_3 (x) B_2 (x) B_1, W^(00) = W_3^{00} (x) W_2^{00} (x) W_1^{00} and
+D = diag(alpha(x_q) det J(x_q)) (the mass integrand pulled back to the
+parametric domain).
+
+``assemble`` builds the operator explicitly as a scipy.sparse matrix (small sizes only);
 ``apply`` / ``apply_T`` evaluate K~ v and K~^T v with one 1D product per mode
 (eq. sum-factorization) and no fusion.  ``rhs`` is the load vector of reading
 R6: b_i = sum_q W^(00)_{iq} det J(x_q) f(F(x_q)) (weighted-quadrature mass rule,
@@ -52,12 +58,23 @@ class Problem:
         self.N = S1.n * S2.n * S3.n
         self.Nq = S1.nq * S2.nq * S3.nq
         self.F, self.J = map_and_jacobian(self.spaces, ctrl)
+        self.Cm = None                          # reaction diagonal alpha det J (None: alpha = 0)
         self.set_K(K_fn(self.F) if K_fn is not None else None)
 
     def set_K(self, K):
         self.K = K
         C, self.detJ = coefficient_tensor(self.J, K)
         self.C = coefficient_planes(C)          # (6, nq3, nq2, nq1)
+
+    def set_alpha(self, alpha_q):
+        """Reaction coefficient alpha of the model problem at the quadrature
+        points ([nq3, nq2, nq1] or flat), or None for alpha = 0.  The diagonal of
+        Algorithm 1 is c_q = alpha(x_q) det J(x_q): the mass integrand
+        alpha b_i b_j over the physical domain, pulled back by F."""
+        if alpha_q is None:
+            self.Cm = None
+        else:
+            self.Cm = np.asarray(alpha_q, dtype=np.float64).reshape(self.detJ.shape) * self.detJ
 
     # -- factors -----------------------------------------------------------
     def Wk(self, alpha, beta):
@@ -85,7 +102,17 @@ class Problem:
                 D = sp.diags(C[_PLANE[(al, be)]].ravel())
                 term = (Wk @ D @ Bk).tocsr()
                 K = term if K is None else K + term
+        if self.Cm is not None:
+            K = K + self.assemble_mass()
         return K.tocsr()
+
+    def assemble_mass(self):
+        """M~ = W^(00) D B (eq. WDB) as a sparse matrix."""
+        S = self.spaces
+        Wk = sp.kron(sp.csr_matrix(S[2].W[(0, 0)]),
+                     sp.kron(sp.csr_matrix(S[1].W[(0, 0)]), sp.csr_matrix(S[0].W[(0, 0)])))
+        Bk = sp.kron(sp.csr_matrix(S[2].B[0]), sp.kron(sp.csr_matrix(S[1].B[0]), sp.csr_matrix(S[0].B[0])))
+        return (Wk @ sp.diags(self.Cm.ravel()) @ Bk).tocsr()
 
     # -- matrix-free products ---------------------------------------------
     def _shape(self, v, q=False):
@@ -110,13 +137,33 @@ class Problem:
         return mode(W3.T, mode(W2.T, mode(W1.T, Y, 2), 1), 0)
 
     def apply(self, v):
-        """w = K~ v following Algorithm 2 step by step."""
+        """w = K~ v following Algorithm 2 step by step (plus M~ v when alpha is set)."""
         g = self.grad_at_quad(v)
         w = np.zeros((self.n[2], self.n[1], self.n[0]))
         for be in range(3):
             for al in range(3):
                 w += self.test_contract(al, be, self.plane(al, be) * g[be])
+        if self.Cm is not None:
+            w += self.mass_apply(v).reshape(w.shape)
         return w.ravel()
+
+    def values_at_quad(self, v):
+        """v~ = (B_3 (x) B_2 (x) B_1) v, the values of v_h at the points (Algorithm 1, first step)."""
+        S = self.spaces
+        return mode(S[2].B[0], mode(S[1].B[0], mode(S[0].B[0], self._shape(v), 2), 1), 0)
+
+    def mass_apply(self, v):
+        """w = M~ v by the three steps of Algorithm 1: values at the points, the
+        diagonal D = diag(alpha det J), the W^(00) rules."""
+        vt = self.values_at_quad(v)
+        vtt = self.Cm * vt
+        return self.W00(vtt).ravel()
+
+    def mass_apply_T(self, v):
+        """w = M~^T v = B^T D W^(00)^T v."""
+        S = self.spaces
+        Y = self.Cm * self.W00_T(self._shape(v))
+        return mode(S[2].B[0].T, mode(S[1].B[0].T, mode(S[0].B[0].T, Y, 2), 1), 0).ravel()
 
     def apply_T(self, v):
         """w = K~^T v = sum_{alpha,beta} B^(beta)^T D^(alpha,beta) W^(alpha,beta)^T v."""
@@ -128,6 +175,8 @@ class Problem:
                 acc += self.plane(al, be) * self.test_contract_T(al, be, Y)
             B1, B2, B3 = self.Bk(be)
             w += mode(B3.T, mode(B2.T, mode(B1.T, acc, 2), 1), 0)
+        if self.Cm is not None:
+            w += self.mass_apply_T(v).reshape(w.shape)
         return w.ravel()
 
     def explicit_row(self, i):
@@ -142,6 +191,10 @@ class Problem:
                 Q = np.einsum("c,b,a->cba", W3[i3], W2[i2], W1[i1]) * self.plane(al, be)
                 B1, B2, B3 = self.Bk(be)
                 row += np.einsum("cba,ck,bj,ai->kji", Q, B3, B2, B1, optimize=True).ravel()
+        if self.Cm is not None:            # M~_ij = sum_q w^(00)_{iq} c_q b_j(x_q) (eq. Mwq)
+            S = self.spaces
+            Q = np.einsum("c,b,a->cba", S[2].W[(0, 0)][i3], S[1].W[(0, 0)][i2], S[0].W[(0, 0)][i1]) * self.Cm
+            row += np.einsum("cba,ck,bj,ai->kji", Q, S[2].B[0], S[1].B[0], S[0].B[0], optimize=True).ravel()
         return row
 
     # -- load vector and mass-type pieces ----------------------------------

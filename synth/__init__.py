@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "uniform_knots", "greville", "control_net", "Workload", "WORKLOADS",
-    "workload", "random_vector", "kappa_field", "sym6_field",
+    "workload", "random_vector", "kappa_field", "sym6_field", "alpha_field",
 ]
 
 
@@ -199,6 +199,17 @@ def sym6_field(seeds=(5, 6, 7), ell: float = 0.25, M: int = 64,
             return sum(Q[i][r] * d[r] * Q[j][r] for r in range(3))
         return _stack(xp, [k(0, 0), k(1, 1), k(2, 2), k(0, 1), k(0, 2), k(1, 2)])
     return K6
+
+
+def alpha_field(scale: float = 1.0) -> Callable:
+    """Smooth positive reaction coefficient of the model problem
+    -div(K grad u) + alpha u = f:
+    alpha(x) = scale (1 + 0.5 sin(pi x1) cos(pi x2) + 0.25 x3^2) >= scale / 2."""
+    def alpha(x):
+        xp = _ns(x)
+        return scale * (1.0 + 0.5 * xp.sin(math.pi * x[..., 0]) * xp.cos(math.pi * x[..., 1])
+                        + 0.25 * x[..., 2] * x[..., 2])
+    return alpha
 
 
 def u_sine(x):

@@ -10,7 +10,9 @@ their formulas:
   sum_q f_q dJ/df_q = <u - u_obs, u>;
 * u_obs = u gives a zero gradient;
 * a plausible mistake (the chain rule through eq. C taken with J^{-1} and
-  J^{-T} swapped) fails the finite-difference pin on a twisted geometry.
+  J^{-T} swapped) fails the finite-difference pin on a twisted geometry;
+* dJ/dalpha_q of the reaction term against central differences, and the same
+  gradient with det J dropped (a planted mistake) failing them.
 """
 import numpy as np
 import pytest
@@ -158,3 +160,36 @@ def test_swapped_chain_rule_fails_finite_differences():
     bad = _gK_dot(wrong, d, "sym6")
     assert abs(fd - right) <= 1e-6 * abs(right)
     assert abs(fd - bad) > 1e-3 * abs(fd)
+
+
+def test_gradient_alpha_matches_central_differences():
+    wl = synth.Workload("ring4_p3", 4, 3, "ring", 0.02, "identity", "paper")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), None)
+    f_q = np.asarray(wl.f()(pr.F))
+    alpha = np.asarray(synth.alpha_field(30.0)(pr.F))
+    pr.set_alpha(np.asarray(synth.alpha_field(60.0)(pr.F)))
+    _, u_obs = solve(pr, None, f_q)
+
+    def J_alpha(a):
+        pr.set_alpha(a)
+        _, u = solve(pr, None, f_q)
+        return 0.5 * float(np.sum((u - u_obs) ** 2))
+    pr.set_alpha(alpha)
+    A, u = solve(pr, None, f_q)
+    lam = spla.spsolve(A.T.tocsc(), u - u_obs)
+    g = adjoint.grad_alpha(pr, lam, u)
+    d = np.random.default_rng(4).uniform(-1, 1, alpha.shape)
+    eps = 1e-4 * np.abs(alpha).max()        # J ~ 1e3 |dJ|: a smaller step loses digits to cancellation
+    fd = (J_alpha(alpha + eps * d) - J_alpha(alpha - eps * d)) / (2 * eps)
+    an = float(np.sum(g * d))
+    assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+    # single quadrature point
+    q = (pr.nq[2] // 2, pr.nq[1] // 3, pr.nq[0] // 2)
+    e = np.zeros_like(alpha)
+    e[q] = 1.0
+    eps1 = 1e-2 * alpha[q]
+    fd1 = (J_alpha(alpha + eps1 * e) - J_alpha(alpha - eps1 * e)) / (2 * eps1)
+    assert abs(fd1 - g[q]) <= 1e-4 * abs(g[q]), (fd1, g[q])
+    # planted mistake: the gradient without det J
+    wrong = float(np.sum(g / pr.detJ * d))
+    assert abs(fd - wrong) > 1e-2 * abs(fd)

@@ -16,7 +16,13 @@ which re-types the oracle's own formulas:
   with the transposed convention planted in the oracle to show it fails;
 * FD: generalized eigen-identities, exact inverse of its Kronecker form, and
   one-iteration convergence on the identity cube;
-* load vector: exact for sources in the spline space (reading R3, R6).
+* load vector: exact for sources in the spline space (reading R3, R6);
+* reaction term (Algorithm 1): on the identity cube with constant alpha the WQ
+  mass matrix equals the exact Galerkin mass, K~ + alpha M~ equals the shifted
+  FD Kronecker sum, and the shifted FD is its exact inverse (one iteration); on
+  an affine map M~ carries the constant det J; with a variable alpha the
+  manufactured solution converges at the spline rate, and a planted mistake
+  (alpha without det J) breaks that.
 """
 import math
 
@@ -307,3 +313,108 @@ def test_load_vector_exact_for_spline_sources():
     G = bspline.galerkin_1d(k, p, 0, 0)[1:m - 1, :]
     ref = mode(G, mode(G, mode(G, c, 2), 1), 0).ravel()
     assert np.linalg.norm(b - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- reaction term (Algorithm 1)
+def _interior_galerkin(k, p, a, b):
+    m = len(k) - p - 1
+    return bspline.galerkin_1d(k, p, a, b)[1:m - 1, 1:m - 1]
+
+
+@pytest.mark.parametrize("p", [2, 3, 4])
+def test_identity_geometry_mass_is_exact_galerkin(p):
+    k = nonuniform_knots(5, p, seed=11)
+    kn = (k, k, k)
+    pr = Problem(kn, p, synth.control_net("identity", kn, p))
+    alpha = 2.5
+    pr.set_alpha(np.full(pr.Nq, alpha))
+    G00 = _interior_galerkin(k, p, 0, 0)
+    M = alpha * np.kron(G00, np.kron(G00, G00))
+    Mt = pr.assemble_mass().toarray()
+    assert np.abs(Mt - M).max() <= 1e-13 * np.abs(M).max()
+    # the full operator is the Kronecker sum of the shifted FD preconditioner
+    A = pr.assemble().toarray()
+    P = FD(pr.spaces, shift=alpha).P_matrix().toarray()
+    assert np.abs(A - P).max() <= 1e-13 * np.abs(P).max()
+    # Algorithm 1 matrix-free equals the assembled mass, also transposed
+    v = synth.random_vector(pr.N, 5)
+    assert np.linalg.norm(pr.mass_apply(v) - Mt @ v) <= 1e-13 * np.linalg.norm(Mt @ v)
+    assert np.linalg.norm(pr.mass_apply_T(v) - Mt.T @ v) <= 1e-13 * np.linalg.norm(Mt @ v)
+
+
+def test_mass_carries_det_J_on_affine_map():
+    p = 3
+    k = synth.uniform_knots(5, p)
+    kn = (k, k, k)
+    pr = Problem(kn, p, synth.control_net("shear", kn, p))
+    detA = float(np.linalg.det(synth._shear_matrix()))
+    assert np.abs(pr.detJ - detA).max() < 1e-13
+    pr.set_alpha(np.full(pr.Nq, 1.5))
+    G00 = _interior_galerkin(k, p, 0, 0)
+    M = 1.5 * detA * np.kron(G00, np.kron(G00, G00))
+    assert np.abs(pr.assemble_mass().toarray() - M).max() <= 1e-13 * np.abs(M).max()
+
+
+def test_shifted_fd_is_exact_inverse_and_one_iteration():
+    p = 3
+    k = nonuniform_knots(6, p, seed=4)
+    kn = (k, k, k)
+    pr = Problem(kn, p, synth.control_net("identity", kn, p))
+    fd = FD(pr.spaces, shift=40.0)
+    r = synth.random_vector(pr.N, 4)
+    z = spla.spsolve(fd.P_matrix().tocsc(), r)
+    assert np.linalg.norm(fd.apply(r) - z) < 1e-12 * np.linalg.norm(z)
+    assert np.linalg.norm(fd.apply(fd.P_apply(r)) - r) < 1e-12 * np.linalg.norm(r)
+    pr.set_alpha(np.full(pr.Nq, 40.0))
+    x, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(synth.f_sine), fd.apply, tol=1e-12)
+    assert it == 1 and rel < 1e-12
+
+
+def _reaction_h1_errors(p):
+    """H1 errors of -Lap u + alpha u = f on the cube, u = u_sine, alpha variable."""
+    alpha_fn = synth.alpha_field(20.0)
+    out = []
+    for ne in (4, 8, 16):
+        k = synth.uniform_knots(ne, p)
+        kn = (k, k, k)
+        ctrl = synth.control_net("identity", kn, p)
+        pr = Problem(kn, p, ctrl)
+        pr.set_alpha(alpha_fn(pr.F))
+        b = pr.rhs_from(lambda x: synth.f_sine(x) + alpha_fn(x) * synth.u_sine(x))
+        u, it, rel, _ = bicgstab(pr.apply, b, FD(pr.spaces, shift=20.0).apply, tol=1e-12)
+        assert rel <= 1e-12
+        out.append(errors(kn, p, ctrl, u, synth.u_sine)[1])
+    return out
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_reaction_solution_converges_at_spline_rate(p):
+    h1 = _reaction_h1_errors(p)
+    assert abs(_rates(h1)[-1] - p) < 0.3
+
+
+def test_reaction_without_det_J_fails_on_a_scaled_cube():
+    # on the unit cube det J = 1, so the planted mistake only shows once det J != 1:
+    # a cube scaled by 2 (det J = 8) with the source rescaled to its coordinates
+    p = 2
+    k = synth.uniform_knots(8, p)
+    kn = (k, k, k)
+    ctrl = 2.0 * synth.control_net("identity", kn, p)
+    alpha_fn = synth.alpha_field(20.0)
+
+    def u(x):
+        return synth.u_sine(x / 2.0)
+
+    def f(x):
+        return 0.25 * synth.f_sine(x / 2.0) + alpha_fn(x) * u(x)
+
+    def err(planted):
+        pr = Problem(kn, p, ctrl)
+        a_q = alpha_fn(pr.F)
+        pr.set_alpha(a_q)
+        if planted:                             # the mistake: alpha without det J on the diagonal
+            pr.Cm = np.asarray(a_q).reshape(pr.detJ.shape) * 1.0
+        x, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(f), FD(pr.spaces, shift=80.0).apply, tol=1e-12)
+        return errors(kn, p, ctrl, x, u)[1]
+    good, bad = err(False), err(True)
+    assert bad > 5 * good
