@@ -101,9 +101,27 @@ int wq_detj(wq_op A, double* detj, wq_stream_t s);
  * (eq. C) without touching the geometry.  Async on s. */
 int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s);
 
+/* Reaction coefficient of the model problem -div(K grad u) + alpha u = f
+ * (Section 2.1): alpha_q device [N_q] FP64, alpha at the quadrature points in
+ * the layout of K_q, or NULL to remove the term.  Stores the diagonal
+ * c_q = alpha_q det J(x_q) of the weighted-quadrature mass matrix
+ * M~ = W^(0,0) diag(c) B (Section 3.1, eq. WDB; B = B3 x B2 x B1) in the
+ * operator's workspace (FP64, and FP32 when prepared); alpha_q is not kept.
+ * From then on wq_apply, wq_apply_T, wq_apply_acc, krylov_solve and ir_solve
+ * use K~ + M~.  The paper takes alpha >= 0; other values are used as given.
+ * Async on s.  Errors: WQ_EINVAL, WQ_EHIP. */
+int wq_set_alpha(wq_op A, const double* alpha_q, wq_stream_t s);
+
+/* w = M~ v alone: the mass product of Algorithm 1 (values of v at the points,
+ * times c_q, the W^(0,0) rules), with the c_q of the last wq_set_alpha.  Runs as
+ * six banded 1D passes through the operator's scratch (not the fused kernels).
+ * Same arguments as wq_apply.  Async on s.  Errors: WQ_EINVAL (also when no
+ * alpha is set), WQ_EHIP. */
+int wq_apply_mass(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
+
 /* w = K~ v, Algorithm 2: w = sum_{a,b} W^(a,b) D^(a,b) B^(b) v (Section 3.2).
  * prec: WQ_F64 or WQ_F32 (must have been prepared).  v, w device, N entries,
- * must not alias.  Async on s. */
+ * must not alias.  With a reaction coefficient set, w = (K~ + M~) v.  Async on s. */
 int wq_apply(wq_op A, int prec, const void* v, void* w, wq_stream_t s);
 
 /* w = K~^T v = sum_{a,b} B^(b)T D^(a,b) W^(a,b)T v (transpose of the
@@ -130,6 +148,11 @@ int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream
 /* dJ/df_q = det J(q) (W^(0,0)T lam)_q into device [N_q].  Async on s. */
 int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s);
 
+/* dJ/dalpha_q = -det J(q) (W^(0,0)T lam)_q (B u)_q (M~ is linear in alpha_q,
+ * eq. WDB) into device [N_q] FP64; lam, u device [N] FP64.  Async on s.
+ * Errors: WQ_EINVAL, WQ_EHIP. */
+int wq_grad_alpha(wq_op A, const double* lam, const double* u, double* g, wq_stream_t s);
+
 void wq_destroy(wq_op A);
 
 /* ------------------------------------------------------------------------ *
@@ -150,8 +173,15 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
  * accumulation.  r, z device (may alias).  Async on s. */
 int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s);
 
-/* Eigenvalues lam_l (host out, n_l doubles each, may be NULL) and
- * eigenvectors U_l (host out, row-major n_l x n_l, may be NULL). */
+/* Shift for the reaction term: P becomes P + sigma M3 x M2 x M1, whose inverse
+ * has the diagonal 1/(l1_i + l2_j + l3_k + sigma) in the same eigenbasis.
+ * sigma is a representative value of alpha det J (e.g. its mean); 0 restores
+ * the plain P.  Synchronises s.  Errors: WQ_EINVAL (non-finite sigma, or a
+ * non-positive diagonal), WQ_EHIP. */
+int fd_set_shift(fd_pc P, double sigma, wq_stream_t s);
+
+/* Eigenvalues lam_l (host out, n_l doubles each, may be NULL; without the
+ * shift) and eigenvectors U_l (host out, row-major n_l x n_l, may be NULL). */
 int fd_factors(fd_pc P, int l, double* lam, double* U);
 
 void fd_destroy(fd_pc P);

@@ -32,13 +32,17 @@ SIGNATURES = [
     ("wq_apply", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_apply_T", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_apply_acc", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    ("wq_set_alpha", C.c_int, [_vp, _vp, _vp]),
+    ("wq_apply_mass", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_rhs", C.c_int, [_vp, _vp, _vp, _vp]),
     ("wq_grad_K", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("wq_grad_f", C.c_int, [_vp, _vp, _vp, _vp]),
+    ("wq_grad_alpha", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("wq_destroy", None, [_vp]),
     ("fd_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), C.c_int, _vp, C.c_size_t, _szp, _vp,
                            C.POINTER(C.c_void_p)]),
     ("fd_apply", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    ("fd_set_shift", C.c_int, [_vp, C.c_double, _vp]),
     ("fd_factors", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fd_destroy", None, [_vp]),
     ("krylov_ws_bytes", C.c_size_t, [_vp]),

@@ -510,6 +510,14 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
         o_c32 = off;
         off += al256(6 * o.Nq * 4);
     }
+    // reaction plane alpha det J (written by wq_set_alpha)
+    const size_t o_cm64 = off;
+    off += al256(o.Nq * 8);
+    size_t o_cm32 = 0;
+    if (prec_mask & WQ_F32) {
+        o_cm32 = off;
+        off += al256(o.Nq * 4);
+    }
     const size_t o_scr = off;
     o.scratch_bytes = wqfd::wq_scratch_bytes(o, prec_mask);
     off += al256(o.scratch_bytes);
@@ -530,6 +538,8 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     o.F = reinterpret_cast<double*>(base + o_F);
     o.C64 = reinterpret_cast<double*>(base + o_c64);
     o.C32 = (prec_mask & WQ_F32) ? reinterpret_cast<float*>(base + o_c32) : nullptr;
+    o.Cm64 = reinterpret_cast<double*>(base + o_cm64);
+    o.Cm32 = (prec_mask & WQ_F32) ? reinterpret_cast<float*>(base + o_cm32) : nullptr;
     o.scratch = base + o_scr;
     HIP_TRY(hipMemcpyAsync(o.detJ, hdet.data(), o.Nq * 8, hipMemcpyHostToDevice, s), "upload detJ");
     HIP_TRY(hipMemcpyAsync(o.Jinv, hjinv.data(), 9 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload Jinv");
@@ -633,6 +643,17 @@ int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s) {
     return WQ_OK;
 }
 
+int wq_set_alpha(wq_op A, const double* alpha_q, wq_stream_t s) {
+    if (!A) return fail(WQ_EINVAL, "null handle");
+    if (!alpha_q) {
+        A->op.mass = false;
+        return WQ_OK;
+    }
+    HIP_TRY(wqfd::launch_set_alpha(A->op, alpha_q, reinterpret_cast<hipStream_t>(s)), "set_alpha");
+    A->op.mass = true;
+    return WQ_OK;
+}
+
 static int apply_common(wq_op A, int prec, const void* v, void* w, wq_stream_t s, bool tr, bool acc) {
     if (!A || !v || !w) return fail(WQ_EINVAL, "null argument");
     if ((prec != WQ_F64 && prec != WQ_F32) || !(A->op.prec_mask & prec))
@@ -655,6 +676,16 @@ int wq_apply_acc(wq_op A, int prec, const void* v, void* w, wq_stream_t s) {
     return apply_common(A, prec, v, w, s, false, true);
 }
 
+int wq_apply_mass(wq_op A, int prec, const void* v, void* w, wq_stream_t s) {
+    if (!A || !v || !w) return fail(WQ_EINVAL, "null argument");
+    if ((prec != WQ_F64 && prec != WQ_F32) || !(A->op.prec_mask & prec))
+        return fail(WQ_EINVAL, "precision not prepared for this operator");
+    if (v == w) return fail(WQ_EINVAL, "v and w must not alias");
+    if (!A->op.mass) return fail(WQ_EINVAL, "no reaction coefficient set (wq_set_alpha)");
+    HIP_TRY(wqfd::launch_apply_mass(A->op, prec, v, w, reinterpret_cast<hipStream_t>(s)), "wq_apply_mass");
+    return WQ_OK;
+}
+
 int wq_rhs(wq_op A, const double* f_q, double* b, wq_stream_t s) {
     if (!A || !f_q || !b) return fail(WQ_EINVAL, "null argument");
     HIP_TRY(wqfd::launch_rhs(A->op, f_q, b, reinterpret_cast<hipStream_t>(s)), "wq_rhs");
@@ -670,6 +701,13 @@ int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream
 int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s) {
     if (!A || !lam || !gf) return fail(WQ_EINVAL, "null argument");
     HIP_TRY(wqfd::launch_grad_f(A->op, lam, gf, reinterpret_cast<hipStream_t>(s)), "wq_grad_f");
+    return WQ_OK;
+}
+
+int wq_grad_alpha(wq_op A, const double* lam, const double* u, double* g, wq_stream_t s) {
+    if (!A || !lam || !u || !g) return fail(WQ_EINVAL, "null argument");
+    if (!(A->op.prec_mask & WQ_F64)) return fail(WQ_EINVAL, "FP64 not prepared");
+    HIP_TRY(wqfd::launch_grad_alpha(A->op, lam, u, g, reinterpret_cast<hipStream_t>(s)), "wq_grad_alpha");
     return WQ_OK;
 }
 
@@ -795,6 +833,22 @@ int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s) {
     if ((prec != WQ_F64 && prec != WQ_F32 && prec != WQ_BF16) || !(P->pc.prec_mask & prec))
         return fail(WQ_EINVAL, "precision not prepared for this preconditioner");
     HIP_TRY(wqfd::launch_fd_apply(P->pc, prec, r, z, reinterpret_cast<hipStream_t>(s)), "fd_apply");
+    return WQ_OK;
+}
+
+int fd_set_shift(fd_pc P, double sigma, wq_stream_t s) {
+    if (!P) return fail(WQ_EINVAL, "null handle");
+    auto& f = P->pc;
+    if (!std::isfinite(sigma)) return fail(WQ_EINVAL, "shift must be finite");
+    double lmin = sigma;
+    for (int l = 0; l < 3; ++l) lmin += *std::min_element(f.hlam[l].begin(), f.hlam[l].end());
+    if (!(lmin > 0.0)) return fail(WQ_EINVAL, "shift makes the FD diagonal non-positive");
+    std::vector<double> l3(f.hlam[2]);
+    for (double& x : l3) x += sigma;
+    hipStream_t st = reinterpret_cast<hipStream_t>(s);
+    HIP_TRY(hipMemcpyAsync(f.lam[2], l3.data(), l3.size() * 8, hipMemcpyHostToDevice, st), "upload shifted lam3");
+    HIP_TRY(hipStreamSynchronize(st), "fd_set_shift sync");
+    f.shift = sigma;
     return WQ_OK;
 }
 

@@ -50,6 +50,9 @@ struct WqOp {
     double* F = nullptr;        // [3][Nq]
     double* C64 = nullptr;      // [6][Nq] (C11, C22, C33, C12, C13, C23)
     float* C32 = nullptr;       // [6][Nq]
+    double* Cm64 = nullptr;     // [Nq] reaction plane alpha det J (mass term of Algorithm 1)
+    float* Cm32 = nullptr;      // [Nq]
+    bool mass = false;          // reaction term set (wq_set_alpha)
     void* scratch = nullptr;    // apply intermediates (bytes: scratch_bytes)
     size_t scratch_bytes = 0;
     OpTables<double> t64;
@@ -77,7 +80,8 @@ struct FdPc {
     double* UTp64[3] = {nullptr, nullptr, nullptr};
     float* Up32[3] = {nullptr, nullptr, nullptr};
     float* UTp32[3] = {nullptr, nullptr, nullptr};
-    double* lam[3] = {nullptr, nullptr, nullptr};    // eigenvalues (device)
+    double* lam[3] = {nullptr, nullptr, nullptr};    // eigenvalues (device); lam[2] carries the shift
+    double shift = 0.0;                              // constant added to the diagonal (reaction term)
     std::vector<double> hlam[3], hU[3];
     void* scratch = nullptr;    // one N-sized buffer of the widest precision
 };
@@ -92,6 +96,10 @@ hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool t
 hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s);
 hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s);
 hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s);
+// reaction term: Cm = alpha det J (both prepared precisions), w = M~ v, dJ/dalpha
+hipError_t launch_set_alpha(const WqOp& op, const double* alpha_q, hipStream_t s);
+hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, hipStream_t s);
+hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s);
 
 // FD preconditioner (fd_kernels.hip)
 hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s);

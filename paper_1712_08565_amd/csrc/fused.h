@@ -21,6 +21,7 @@ struct FusedArgs {
     const T* v = nullptr;
     T* w = nullptr;
     const T* C = nullptr;
+    const T* Cm = nullptr;          // reaction plane alpha det J [N_q], or nullptr (no reaction term)
     int n1 = 0, n2 = 0, n3 = 0, nq1 = 0, nq2 = 0, nq3 = 0;
     size_t Nq = 0;
     const T* tilesX = nullptr;

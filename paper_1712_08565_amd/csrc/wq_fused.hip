@@ -18,6 +18,12 @@
 //       cores and the 16 x 16 DOF block is added to w with atomics (tiles and
 //       z ranges overlap in the DOFs they touch).
 //
+// Reaction term (the mass apply of Algorithm 1, M~ = W^(00) D B): its values
+// at the points are B3 applied to U_0, the window the z-derivative waves already
+// hold, and its x and y test rules W1^{00}, W2^{00} are those of the field zz.
+// So the z-derivative waves add c_q (B3 . window) times the W3^{00} column into
+// the zz ring, and nothing else changes; the transposed kernel mirrors this.
+//
 // The banded 1D factors restricted to a tile are stored as dense 16 x 16
 // blocks (DOF footprints of 16 quadrature points fit in 16 for p <= 7), held in
 // LDS for the whole kernel.  FP64 uses v_mfma_f64_16x16x4f64, FP32
@@ -146,7 +152,7 @@ __device__ inline void setup_store(const SetupRegs<T, CZ>& su, T (*sCoef)[BLK], 
 // Every buffer a role writes in an interval is read by the other role only
 // after the closing barrier, and is not rewritten before the reader's interval
 // has ended; the schedule is computed identically by every wave.
-template <typename T, int P>
+template <typename T, int P, bool MASS>
 __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a) {
     constexpr int RT = P + 1;              // trial window (DOF planes)
     constexpr int RO = P + 2;              // test window (output planes)
@@ -233,16 +239,24 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     // only for its own slot, not for the loads issued after it.
     const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
     const unsigned pbytes = (unsigned)(plane * sizeof(T));
-    const __amdgpu_buffer_rsrc_t rC[3] = {buf_rsrc(a.C + poff[0]), buf_rsrc(a.C + poff[1]), buf_rsrc(a.C + poff[2])};
-    auto cload3 = [&](T (&dst)[3], int kq) {              // kq: a plane of this range
+    // With the reaction term a fourth slot holds c_q = alpha det J for the z group;
+    // the x and y groups load their third plane into it again (a cache hit, value
+    // unused), so every column wave keeps the same load sequence.
+    constexpr int NC = MASS ? 4 : 3;
+    __amdgpu_buffer_rsrc_t rC[NC];
+    rC[0] = buf_rsrc(a.C + poff[0]);
+    rC[1] = buf_rsrc(a.C + poff[1]);
+    rC[2] = buf_rsrc(a.C + poff[2]);
+    if constexpr (MASS) rC[3] = buf_rsrc(beta == 2 ? a.Cm : a.C + poff[2]);
+    auto cload3 = [&](T (&dst)[NC], int kq) {             // kq: a plane of this range
 #pragma unroll
-        for (int al = 0; al < 3; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
+        for (int al = 0; al < NC; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
     };
 
     // one quadrature plane of column work: g = (z trial row) . window,
     // psi_alpha = C_(alpha beta) g, ring += (z test rows) psi; czo = offset of
     // the plane's z coefficients
-    auto valu_plane = [&](int czo, const T (&C)[3]) {
+    auto valu_plane = [&](int czo, const T (&C)[NC]) {
         const T* cz = sZ + czo;
         const T* ct3 = cz + (beta == 2 ? RT : 0);               // B3 row, or B-dot3 for beta = z
         T g = T(0);
@@ -258,12 +272,23 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
             acc[1][s] += w01[s] * p1;
             acc[2][s] += w2[s] * p2;
         }
+        if constexpr (MASS) {
+            if (beta == 2) {                                    // reaction: value (B3 row) x c_q x W3^{00}
+                T gm = T(0);
+#pragma unroll
+                for (int s = 0; s < RT; ++s) gm += cz[s] * Uw[s];
+                const T pm = C[3] * gm;
+                const T* w00 = cz + 2 * RT;
+#pragma unroll
+                for (int s = 0; s < RO; ++s) acc[2][s] += w00[s] * pm;
+            }
+        }
     };
 
     // band starts (MFMA waves: of point q1 = tid % 16; column waves: of q2) and
     // the column waves' first coefficient slots, loaded with the set-up
     const int bX = a.bandX[t1 * 16 + (tid & 15)], bY = a.bandY[t2 * 16 + q2l];
-    T Cs[2][3];
+    T Cs[2][NC];
     if (!mrole) {
         cload3(Cs[0], k0);
         cload3(Cs[1], min(k0 + 1, k1 - 1));
@@ -468,7 +493,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
 //     factors (fields x and z share B2 and are summed before it) and atomics.
 // Operands with transposed LDS reads use the accumulator row mapping as K
 // index, as in the forward kernel.
-template <typename T, int P>
+template <typename T, int P, bool MASS>
 __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> a) {
     constexpr int RT = P + 1;              // output ring (DOF planes, B band)
     constexpr int RO = P + 2;              // input window (DOF planes, W band)
@@ -659,13 +684,18 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
         // coefficient slots loaded one interval ahead, as in the forward kernel
         const unsigned cbyte = (unsigned)(min(q2, a.nq2 - 1) * a.nq1 + min(q1, a.nq1 - 1)) * (unsigned)sizeof(T);
         const unsigned pbytes = (unsigned)(plane * sizeof(T));
-        const __amdgpu_buffer_rsrc_t rC[3] = {buf_rsrc(a.C + poff[0]), buf_rsrc(a.C + poff[1]),
-                                              buf_rsrc(a.C + poff[2])};
-        auto cload3 = [&](T (&dst)[3], int kq) {
+        // reaction plane in a fourth slot, loaded as in the forward kernel
+        constexpr int NC = MASS ? 4 : 3;
+        __amdgpu_buffer_rsrc_t rC[NC];
+        rC[0] = buf_rsrc(a.C + poff[0]);
+        rC[1] = buf_rsrc(a.C + poff[1]);
+        rC[2] = buf_rsrc(a.C + poff[2]);
+        if constexpr (MASS) rC[3] = buf_rsrc(beta == 2 ? a.Cm : a.C + poff[2]);
+        auto cload3 = [&](T (&dst)[NC], int kq) {
 #pragma unroll
-            for (int al = 0; al < 3; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
+            for (int al = 0; al < NC; ++al) dst[al] = buf_load<T>(rC[al], cbyte, (unsigned)kq * pbytes);
         };
-        auto valu_plane = [&](int czo, const T (&C)[3]) {
+        auto valu_plane = [&](int czo, const T (&C)[NC]) {
             const T* cz = sZ + czo;
             // z weight variant of field (alpha, beta): 2 [alpha = z] + [beta = z]
             const T* w01 = cz + 2 * RT + (beta == 2 ? 1 : 0) * RO;
@@ -681,8 +711,19 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
             const T* bz = cz + (beta == 2 ? RT : 0);                // B3 row, or B-dot3 for beta = z
 #pragma unroll
             for (int s = 0; s < RT; ++s) orng[s] += bz[s] * phi;
+            if constexpr (MASS) {
+                if (beta == 2) {                                // reaction: W3^{00} x c_q x value (B3 row)
+                    const T* w00 = cz + 2 * RT;
+                    T ym = T(0);
+#pragma unroll
+                    for (int s = 0; s < RO; ++s) ym += w00[s] * Yw[2][s];
+                    const T pm = C[3] * ym;
+#pragma unroll
+                    for (int s = 0; s < RT; ++s) orng[s] += cz[s] * pm;
+                }
+            }
         };
-        T Cs[2][3];
+        T Cs[2][NC];
         cload3(Cs[0], k0);
         cload3(Cs[1], min(k0 + 1, k1 - 1));
         __builtin_amdgcn_s_waitcnt(kVmcnt0);
@@ -738,7 +779,10 @@ template <typename T, int P>
 hipError_t launch_p(const FusedArgs<T>& a, hipStream_t s) {
     if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.sched || !a.sched_off) return hipErrorInvalidValue;
     const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
-    hipLaunchKernelGGL((wq_apply_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    if (a.Cm)
+        hipLaunchKernelGGL((wq_apply_fused_kernel<T, P, true>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL((wq_apply_fused_kernel<T, P, false>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
@@ -746,14 +790,17 @@ template <typename T, int P>
 hipError_t launch_tp(const FusedArgs<T>& a, hipStream_t s) {
     if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.schedT || !a.schedT_off) return hipErrorInvalidValue;
     const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
-    hipLaunchKernelGGL((wq_apply_T_fused_kernel<T, P>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    if (a.Cm)
+        hipLaunchKernelGGL((wq_apply_T_fused_kernel<T, P, true>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
+    else
+        hipLaunchKernelGGL((wq_apply_T_fused_kernel<T, P, false>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 
 template <int P>
 hipError_t slots_p(int* slots) {
     int occ = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wq_apply_fused_kernel<double, P>, 1024, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, wq_apply_fused_kernel<double, P, false>, 1024, 0);
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;

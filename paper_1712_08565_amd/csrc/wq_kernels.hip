@@ -5,7 +5,9 @@
 // pointwise product with the coefficient planes C_ab(x_q), then banded
 // contractions with the weight matrices W_l^{ab}.  Also the transpose, the
 // coefficient set-up C = det J J^{-1} K J^{-T} (eq. C), the load vector and the
-// adjoint gradients with respect to K and f.
+// adjoint gradients with respect to K and f.  With a reaction coefficient
+// alpha the operator also carries the mass term of Algorithm 1 (Section 3.1),
+// M~ v = W^(00) diag(alpha det J) B v (eq. WDB), plus dJ/dalpha.
 //
 // This file holds the staged form: one launch per 1D contraction, with
 // intermediates in device memory.  Each launch streams its input once with
@@ -162,11 +164,18 @@ hipError_t trial_gradient(const WqOp& op, const OpTables<T>& tb, const T* v, Sta
 }
 
 template <typename T>
-hipError_t apply_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* v, T* w, hipStream_t s) {
+hipError_t apply_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* Cm, const T* v, T* w,
+                        hipStream_t s) {
     Staged<T> st(op, op.scratch);
     const int n1 = op.n[0], n2 = op.n[1];
     const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
     WQ_TRY(trial_gradient(op, tb, v, st, s));
+    // reaction term: values at the points, X = B3 B2 B1 v, from B3 v (in Z[0])
+    // before the test passes reuse Z[0]
+    if (Cm) {
+        WQ_TRY(band<T>(1, tb.dir[1].B[0], st.Z[0], nullptr, st.A, n1, op.n[1], nq3, false, s));
+        WQ_TRY(band<T>(0, tb.dir[0].B[0], st.A, nullptr, st.X, n1, nq2, nq3, false, s));
+    }
     bool zset[4] = {false, false, false, false};
     for (int be = 0; be < 3; ++be)
         for (int al = 0; al < 3; ++al) {
@@ -180,19 +189,32 @@ hipError_t apply_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const
             WQ_TRY(band<T>(1, tb.dir[1].W[var[1]], st.A, nullptr, st.Z[grp], n1, nq2, nq3, zset[grp], s));
             zset[grp] = true;
         }
+    if (Cm) {   // W1^{00} (c .* X), then W2^{00} into the W3^{00} group
+        WQ_TRY(band<T, kMulIn>(0, tb.dir[0].W[0], st.X, Cm, st.A, nq1, nq2, nq3, false, s));
+        WQ_TRY(band<T>(1, tb.dir[1].W[0], st.A, nullptr, st.Z[0], n1, nq2, nq3, zset[0], s));
+    }
     for (int grp = 0; grp < 4; ++grp)
         WQ_TRY(band<T>(2, tb.dir[2].W[grp], st.Z[grp], nullptr, w, n1, n2, nq3, grp > 0, s));
     return hipSuccess;
 }
 
 template <typename T>
-hipError_t apply_T_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* v, T* w, hipStream_t s) {
+hipError_t apply_T_staged(const WqOp& op, const OpTables<T>& tb, const T* C, const T* Cm, const T* v, T* w,
+                          hipStream_t s) {
     Staged<T> st(op, op.scratch);
     const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
     const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
     const Dir1D<T>&dx = tb.dir[0], &dy = tb.dir[1], &dz = tb.dir[2];
     // z: W3^T v for the four variants -> [nq3][n2][n1]
     for (int grp = 0; grp < 4; ++grp) WQ_TRY(band<T>(2, dz.WT[grp], v, nullptr, st.Z[grp], n1, n2, n3, false, s));
+    // reaction term first: w = B^T (c .* W^(00)T v)
+    if (Cm) {
+        WQ_TRY(band<T>(1, dy.WT[0], st.Z[0], nullptr, st.A, n1, n2, nq3, false, s));
+        WQ_TRY(band<T, kMulOut>(0, dx.WT[0], st.A, Cm, st.X, n1, nq2, nq3, false, s));
+        WQ_TRY(band<T>(0, dx.BT[0], st.X, nullptr, st.A, nq1, nq2, nq3, false, s));
+        WQ_TRY(band<T>(1, dy.BT[0], st.A, nullptr, st.Bq, n1, nq2, nq3, false, s));
+        WQ_TRY(band<T>(2, dz.BT[0], st.Bq, nullptr, w, n1, n2, nq3, false, s));
+    }
     // psi_beta = sum_alpha C_ab (W^(ab)^T v)
     for (int be = 0; be < 3; ++be)
         for (int al = 0; al < 3; ++al) {
@@ -207,7 +229,7 @@ hipError_t apply_T_staged(const WqOp& op, const OpTables<T>& tb, const T* C, con
         const int d1 = be == 0, d2 = be == 1, d3 = be == 2;
         WQ_TRY(band<T>(0, dx.BT[d1], st.g[be], nullptr, st.A, nq1, nq2, nq3, false, s));     // [nq3][nq2][n1]
         WQ_TRY(band<T>(1, dy.BT[d2], st.A, nullptr, st.X, n1, nq2, nq3, false, s));          // [nq3][n2][n1]
-        WQ_TRY(band<T>(2, dz.BT[d3], st.X, nullptr, w, n1, n2, nq3, be > 0, s));              // [n3][n2][n1]
+        WQ_TRY(band<T>(2, dz.BT[d3], st.X, nullptr, w, n1, n2, nq3, be > 0 || Cm, s));        // [n3][n2][n1]
     }
     return hipSuccess;
 }
@@ -309,6 +331,42 @@ __global__ __launch_bounds__(kThreads) void mul_kernel(const double* __restrict_
         b[i] *= a[i];
 }
 
+// Reaction plane c_q = alpha_q det J_q (FP64, and an FP32 copy when prepared).
+__global__ __launch_bounds__(kThreads) void set_alpha_kernel(const double* __restrict__ alpha,
+                                                             const double* __restrict__ detJ,
+                                                             double* __restrict__ c64, float* __restrict__ c32,
+                                                             size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const double c = alpha[i] * detJ[i];
+        c64[i] = c;
+        if (c32) c32[i] = (float)c;
+    }
+}
+
+// g = -g .* b
+__global__ __launch_bounds__(kThreads) void neg_mul_kernel(const double* __restrict__ b, double* __restrict__ g,
+                                                           size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        g[i] = -(g[i] * b[i]);
+}
+
+// w = M~ v = W^(00) (c .* B v), Algorithm 1: values at the points by z, y, x
+// passes, the diagonal folded into the first test pass, then the W^(00) rules.
+template <typename T>
+hipError_t apply_mass_staged(const WqOp& op, const OpTables<T>& tb, const T* Cm, const T* v, T* w, hipStream_t s) {
+    Staged<T> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
+    const Dir1D<T>&dx = tb.dir[0], &dy = tb.dir[1], &dz = tb.dir[2];
+    WQ_TRY(band<T>(2, dz.B[0], v, nullptr, st.Z[0], n1, n2, n3, false, s));
+    WQ_TRY(band<T>(1, dy.B[0], st.Z[0], nullptr, st.A, n1, n2, nq3, false, s));
+    WQ_TRY(band<T>(0, dx.B[0], st.A, nullptr, st.X, n1, nq2, nq3, false, s));
+    WQ_TRY(band<T, kMulIn>(0, dx.W[0], st.X, Cm, st.A, nq1, nq2, nq3, false, s));
+    WQ_TRY(band<T>(1, dy.W[0], st.A, nullptr, st.Z[0], n1, nq2, nq3, false, s));
+    WQ_TRY(band<T>(2, dz.W[0], st.Z[0], nullptr, w, n1, n2, nq3, false, s));
+    return hipSuccess;
+}
+
 }  // namespace
 
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask) {
@@ -333,25 +391,56 @@ hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool t
             FusedArgs<double> a = op.fz64;
             a.v = static_cast<const double*>(v);
             a.w = static_cast<double*>(w);
+            a.Cm = op.mass ? op.Cm64 : nullptr;
             a.w_zeroed = w_zeroed;
             return transpose ? launch_fused_apply_T<double>(a, op.p, s) : launch_fused_apply<double>(a, op.p, s);
         }
         FusedArgs<float> a = op.fz32;
         a.v = static_cast<const float*>(v);
         a.w = static_cast<float*>(w);
+        a.Cm = op.mass ? op.Cm32 : nullptr;
         a.w_zeroed = w_zeroed;
         return transpose ? launch_fused_apply_T<float>(a, op.p, s) : launch_fused_apply<float>(a, op.p, s);
     }
     if (prec == 1) {
         const double* vv = static_cast<const double*>(v);
         double* ww = static_cast<double*>(w);
-        return transpose ? apply_T_staged<double>(op, op.t64, op.C64, vv, ww, s)
-                         : apply_staged<double>(op, op.t64, op.C64, vv, ww, s);
+        const double* cm = op.mass ? op.Cm64 : nullptr;
+        return transpose ? apply_T_staged<double>(op, op.t64, op.C64, cm, vv, ww, s)
+                         : apply_staged<double>(op, op.t64, op.C64, cm, vv, ww, s);
     }
     const float* vv = static_cast<const float*>(v);
     float* ww = static_cast<float*>(w);
-    return transpose ? apply_T_staged<float>(op, op.t32, op.C32, vv, ww, s)
-                     : apply_staged<float>(op, op.t32, op.C32, vv, ww, s);
+    const float* cm = op.mass ? op.Cm32 : nullptr;
+    return transpose ? apply_T_staged<float>(op, op.t32, op.C32, cm, vv, ww, s)
+                     : apply_staged<float>(op, op.t32, op.C32, cm, vv, ww, s);
+}
+
+hipError_t launch_set_alpha(const WqOp& op, const double* alpha_q, hipStream_t s) {
+    hipLaunchKernelGGL(set_alpha_kernel, dim3(grid_for(op.Nq)), dim3(kThreads), 0, s, alpha_q, op.detJ, op.Cm64,
+                       (op.prec_mask & 2) ? op.Cm32 : nullptr, op.Nq);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, hipStream_t s) {
+    if (prec == 1)
+        return apply_mass_staged<double>(op, op.t64, op.Cm64, static_cast<const double*>(v), static_cast<double*>(w),
+                                         s);
+    return apply_mass_staged<float>(op, op.t32, op.Cm32, static_cast<const float*>(v), static_cast<float*>(w), s);
+}
+
+hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s) {
+    // g = det J W^(00)T lam (the chain of dJ/df), then g = -g .* (B u)
+    WQ_TRY(launch_grad_f(op, lam, g, s));
+    Staged<double> st(op, op.scratch);
+    const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+    const int nq2 = op.nq[1], nq3 = op.nq[2];
+    const OpTables<double>& tb = op.t64;
+    WQ_TRY(band<double>(2, tb.dir[2].B[0], u, nullptr, st.Z[0], n1, n2, n3, false, s));
+    WQ_TRY(band<double>(1, tb.dir[1].B[0], st.Z[0], nullptr, st.A, n1, n2, nq3, false, s));
+    WQ_TRY(band<double>(0, tb.dir[0].B[0], st.A, nullptr, st.X, n1, nq2, nq3, false, s));
+    hipLaunchKernelGGL(neg_mul_kernel, dim3(grid_for(op.Nq)), dim3(kThreads), 0, s, st.X, g, op.Nq);
+    return hipGetLastError();
 }
 
 hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s) {

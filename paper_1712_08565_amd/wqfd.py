@@ -14,7 +14,8 @@ import torch
 from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_K_IDENTITY, WQ_K_SCALAR, WQ_K_SYM6, WQError, check, lib)
 
 __all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
-           "wq_apply_T", "wq_rhs", "wq_grad_K", "wq_grad_f", "fd_setup", "fd_apply", "fd_factors",
+           "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f",
+           "wq_grad_alpha", "fd_setup", "fd_apply", "fd_set_shift", "fd_factors",
            "krylov_solve", "ir_solve", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
            "WQ_K_SYM6", "WQError"]
 
@@ -43,7 +44,7 @@ def _need(t: torch.Tensor, dtype, numel: int, name: str):
 
 
 class WqOp:
-    """MF-WQ stiffness operator handle; owns its device workspace tensor."""
+    """MF-WQ operator handle (stiffness, plus the reaction term once set); owns its device workspace tensor."""
 
     def __init__(self, handle, ws, p, prec_mask, k_kind, device):
         self.handle, self.ws, self.p, self.prec_mask, self.k_kind, self.device = \
@@ -121,6 +122,14 @@ def wq_set_coef(op: WqOp, k_kind: int, K_q: Optional[torch.Tensor] = None, strea
     op.k_kind = k_kind
 
 
+def wq_set_alpha(op: WqOp, alpha_q: Optional[torch.Tensor], stream=None):
+    """Reaction coefficient alpha at the quadrature points ([N_q] FP64), or None to remove it."""
+    if alpha_q is not None:
+        alpha_q = alpha_q.contiguous()
+        _need(alpha_q, torch.float64, op.Nq, "alpha_q")
+    check(lib().wq_set_alpha(op.handle, _p(alpha_q), _stream(stream)), "wq_set_alpha")
+
+
 def _apply(fn, name, op, v, w, prec, stream):
     prec = prec or (WQ_F64 if v.dtype == torch.float64 else WQ_F32)
     _need(v, _DT[prec], op.N, "v")
@@ -144,6 +153,12 @@ def wq_apply_T(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec
 def wq_apply_acc(op: WqOp, v: torch.Tensor, w: torch.Tensor, prec: Optional[int] = None, stream=None) -> torch.Tensor:
     """w += K~ v in place (fused operators, p <= 7)."""
     return _apply(lib().wq_apply_acc, "wq_apply_acc", op, v, w, prec, stream)
+
+
+def wq_apply_mass(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec: Optional[int] = None,
+                  stream=None) -> torch.Tensor:
+    """w = M~ v (Algorithm 1) for the reaction coefficient set by wq_set_alpha."""
+    return _apply(lib().wq_apply_mass, "wq_apply_mass", op, v, w, prec, stream)
 
 
 def wq_rhs(op: WqOp, f_q: torch.Tensor, b: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -173,6 +188,16 @@ def wq_grad_f(op: WqOp, lam: torch.Tensor, gf: Optional[torch.Tensor] = None, st
     return gf
 
 
+def wq_grad_alpha(op: WqOp, lam: torch.Tensor, u: torch.Tensor, g: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    _need(lam, torch.float64, op.N, "lam")
+    _need(u, torch.float64, op.N, "u")
+    g = torch.empty(op.Nq, dtype=torch.float64, device=op.device) if g is None else g
+    _need(g, torch.float64, op.Nq, "g")
+    check(lib().wq_grad_alpha(op.handle, _p(lam), _p(u), _p(g), _stream(stream)), "wq_grad_alpha")
+    return g
+
+
 def fd_setup(p: int, knots: Sequence[np.ndarray], prec_mask: int = WQ_F64, device="cuda", stream=None) -> FdPc:
     ks, nk, kp = _knots(knots)
     need = C.c_size_t(0)
@@ -193,6 +218,11 @@ def fd_apply(P: FdPc, r: torch.Tensor, z: Optional[torch.Tensor] = None, prec: O
     _need(z, _DT[prec], P.N, "z")
     check(lib().fd_apply(P.handle, prec, _p(r), _p(z), _stream(stream)), "fd_apply")
     return z
+
+
+def fd_set_shift(P: FdPc, sigma: float, stream=None):
+    """Add sigma M3 x M2 x M1 to the FD operator (reaction term); 0 removes it."""
+    check(lib().fd_set_shift(P.handle, float(sigma), _stream(stream)), "fd_set_shift")
 
 
 def fd_factors(P: FdPc, l: int):

@@ -55,6 +55,23 @@ def test_space_1d_matches_oracle(p, kind):
             assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (a, b)
 
 
+@pytest.mark.parametrize("p", [7, 8])
+def test_space_1d_high_degree_weights_agree(p):
+    """p = 7, 8: the local exactness systems are ill-conditioned, and the two
+    independent minimum-norm solves agree to about 1e-11 of max |W| (measured
+    1.1e-11 for W^(00) at p = 8); the points and values stay exact."""
+    k = synth.uniform_knots(6, p)
+    xq, B, W = space_1d(p, k)
+    S = owq.Space1D(k, p)
+    assert np.abs(xq - S.xq).max() < 1e-15
+    for d in (0, 1):
+        assert np.abs(B[d] - S.B[d]).max() <= 1e-13 * max(1.0, np.abs(S.B[d]).max())
+    for a in (0, 1):
+        for b in (0, 1):
+            ref = S.W[(a, b)]
+            assert np.abs(W[2 * a + b] - ref).max() <= 5e-11 * np.abs(ref).max(), (a, b)
+
+
 @pytest.mark.parametrize("p", [2, 4, 6])
 def test_fd_eigenpairs_match_oracle(p):
     k = nonuniform(10, p, 7)
