@@ -64,10 +64,10 @@ def kernel_hash() -> str:
     return h.hexdigest()
 
 
-def committed_traffic(degrees):
+def committed_traffic(degrees, reaction=False):
     """Mean DRAM-side bytes per FP64 apply over ``degrees`` from the counter
-    summary, or None if it is missing, stale (kernel source changed) or lacks a
-    degree."""
+    summary (the kernels with the reaction term when ``reaction``), or None if
+    it is missing, stale (kernel source changed) or lacks a degree."""
     try:
         lines = open(TRAFFIC_FILE).read().splitlines()
     except OSError:
@@ -76,8 +76,8 @@ def committed_traffic(degrees):
     for ln in lines:
         if ln.startswith("# kernel sha256:"):
             sha = ln.split(":", 1)[1].strip()
-        elif ln.startswith("p=") and "traffic_bytes=" in ln:
-            kv = dict(t.split("=", 1) for t in ln.split())
+        elif ln.startswith("reaction p=" if reaction else "p=") and "traffic_bytes=" in ln:
+            kv = dict(t.split("=", 1) for t in ln.split() if "=" in t)
             per_p[int(kv["p"])] = float(kv["traffic_bytes"])
     if sha != kernel_hash() or any(p not in per_p for p in degrees):
         return None
@@ -134,6 +134,8 @@ def main():
                     help="comma-separated named workloads instead of the default ring (e.g. ring96_p5,twist128_p6)")
     ap.add_argument("--mixed-fd", choices=("f32", "bf16"), default="f32", help="FD precision of the inner solves")
     ap.add_argument("--mixed-tau", type=float, default=1e-4, help="inner relative tolerance of the refinement")
+    ap.add_argument("--reaction-degree", type=int, default=3,
+                    help="degree of the reaction-term measurement on the same ring (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB per step (counter calibration)")
     args = ap.parse_args()
@@ -299,6 +301,57 @@ def main():
                         r[f"{kind}_eq_err"].append(torch.linalg.norm(xq - P["xref"]).item() / nref)
                         r[f"{kind}_eq_it"].append(last[0] if kind == "fp64" else last[1])
 
+    # reaction term alpha u (mass apply of Algorithm 1 inside the fused kernels):
+    # its own operator on the ring, alpha = 10 n_el^2 (1 + ...) so that M~ and K~
+    # are of the same size, FD shifted by mean(alpha det J)
+    react = None
+    if args.reaction_degree and not args.workloads:
+        rp = args.reaction_degree
+        wl = synth.Workload(f"ring{args.n_el}_p{rp}", args.n_el, rp, "ring", 0.02, "identity", "paper")
+        dpr = problem.build(wl, wqfd.WQ_F64 | wqfd.WQ_F32, wqfd.WQ_F64 | wqfd.WQ_F32 | wqfd.WQ_BF16)
+        _, sigma = problem.set_reaction(dpr, synth.alpha_field(10.0 * args.n_el ** 2))
+        vr = torch.as_tensor(synth.random_vector(dpr.A.N, 42), device="cuda")
+        react = dict(dp=dpr, v=vr, w=torch.empty_like(vr), wacc=torch.zeros_like(vr), x=torch.zeros_like(vr),
+                     kws=torch.empty(wqfd.lib().krylov_ws_bytes(dpr.A.handle), dtype=torch.uint8, device="cuda"),
+                     iws=torch.empty(wqfd.lib().ir_ws_bytes(dpr.A.handle), dtype=torch.uint8, device="cuda"),
+                     sigma=sigma, apply_ms=[], kernel_ms=[], fp64_ms=[], fp64_it=[], mix_ms=[], mix_inner=[])
+        torch.cuda.synchronize()
+
+    def reaction_step(record: bool):
+        R = react
+        dpr = R["dp"]
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            wqfd.wq_apply(dpr.A, R["v"], R["w"])
+            e1.record(stream)
+        k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k0.record(stream)
+        for _ in range(args.reps):
+            wqfd.wq_apply_acc(dpr.A, R["v"], R["wacc"])
+        k1.record(stream)
+        if not args.no_solve:
+            R["x"].zero_()
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record(stream)
+            _, it, _ = wqfd.krylov_solve(dpr.A, dpr.P, dpr.b, x=R["x"], rtol=1e-10, maxit=2000, ws=R["kws"])
+            s1.record(stream)
+            xm = torch.zeros_like(R["x"])
+            m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            m0.record(stream)
+            _, _, inner, _ = wqfd.ir_solve(dpr.A, dpr.P, dpr.b, x=xm, fd_prec=MIX_FD, rtol=1e-10, tau_inner=MIX_TAU,
+                                           ws=R["iws"])
+            m1.record(stream)
+        torch.cuda.synchronize()
+        if record:
+            R["apply_ms"] += [e0.elapsed_time(e1) for e0, e1 in evs]
+            R["kernel_ms"].append(k0.elapsed_time(k1) / args.reps)
+            if not args.no_solve:
+                R["fp64_ms"].append(s0.elapsed_time(s1))
+                R["fp64_it"].append(it)
+                R["mix_ms"].append(m0.elapsed_time(m1))
+                R["mix_inner"].append(inner)
+
     for i in range(args.warmup):
         one_step(False)
         log(f"warmup step {i + 1}/{args.warmup} done")
@@ -309,6 +362,10 @@ def main():
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if react is not None:                    # after the timed steps, not part of them
+        for i in range(args.warmup + args.steps):
+            reaction_step(i >= args.warmup)
+        log("reaction-term measurement done")
 
     tot_dof = sum(probs[p]["N"] * len(rec[p]["apply_ms"]) for p in keys)
     tot_s = sum(sum(rec[p]["apply_ms"]) for p in keys) / 1e3
@@ -367,11 +424,33 @@ def main():
                    "mixed": {"inner_fd": args.mixed_fd, "inner_apply": "f32", "tau_inner": args.mixed_tau}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "wq_apply_fused_kernel<double, p> (timed alone via wq_apply_acc)",
+                     "kernel": "wq_apply_fused_kernel<double, p, false> (timed alone via wq_apply_acc)",
                      "launches": n_apply,
                      "bytes_per_launch": "48 N_q + 16 N"},
         "per_degree": per_p,
     }
+    if react is not None:
+        R = react
+        Nr, Nqr = R["dp"].A.N, R["dp"].A.Nq
+        t_ap, t_k = float(np.mean(R["apply_ms"])), float(np.mean(R["kernel_ms"]))
+        base = per_p.get(f"p{args.reaction_degree}")
+        rr = {"N": Nr, "Nq": Nqr,
+              "workload": f"thick quarter ring, {args.n_el}^3 elements, p = {args.reaction_degree}, "
+                          f"alpha = {10 * args.n_el ** 2} (1 + 0.5 sin(pi x1) cos(pi x2) + 0.25 x3^2), "
+                          f"FD shift mean(alpha det J) = {R['sigma']:.4g}",
+              "apply_ms": round(t_ap, 4), "kernel_ms": round(t_k, 4), "apply_GDOFs": round(Nr / t_ap / 1e6, 3),
+              "bytes_per_launch": "56 N_q + 16 N",
+              "kernel_GBs": round((56 * Nqr + 16 * Nr) / t_k / 1e6, 1),
+              "kernel_frac_of_hbm_peak": round((56 * Nqr + 16 * Nr) / t_k / 1e6 / HBM_PEAK_GBS, 4),
+              "kernel_traffic_bytes": committed_traffic([args.reaction_degree], reaction=True)}
+        if base is not None:
+            rr["kernel_time_vs_stiffness_only"] = round(t_k / base["kernel_ms"], 3)
+        if not args.no_solve:
+            rr.update({"fp64_solve_ms": round(float(np.median(R["fp64_ms"])), 2),
+                       "fp64_iters": int(np.median(R["fp64_it"])),
+                       "mixed_solve_ms": round(float(np.median(R["mix_ms"])), 2),
+                       "mixed_inner": int(np.median(R["mix_inner"]))})
+        out["reaction"] = rr
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
