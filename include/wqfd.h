@@ -87,6 +87,21 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3],
              const double* ctrl, int k_kind, const double* K_q, int prec_mask,
              void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, wq_op* out);
 
+/* The same operator with standard Gauss quadrature instead of weighted
+ * quadrature (the remark after rem:memory, eq. WDBgaussian): p + 1
+ * Gauss-Legendre points per element and direction, test factors
+ * W^{ab}_{iq} = w_q b_i^{(a)}(x_q) (independent of the trial order b), so
+ * K^GQ = sum_{a,b} W^GQ D B is the Gauss-quadrature Galerkin matrix.  It needs
+ * (p+1) n_el points per direction instead of about 2 n_el, hence O(N p^3)
+ * coefficient memory and O(N p^4) apply work instead of O(N) and O(N p): a
+ * baseline for the weighted-quadrature operator, with the same kernels and
+ * every call of this header (apply, transpose, reaction term, solves,
+ * gradients; wq_quad_points reports the Gauss points).  Arguments and errors as
+ * wq_setup. */
+int wq_setup_gauss(int p, const int32_t nknots[3], const double* const knots[3],
+                   const double* ctrl, int k_kind, const double* K_q, int prec_mask,
+                   void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, wq_op* out);
+
 /* Sizes: n[l] interior functions and nq[l] quadrature points per direction. */
 int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]);
 

@@ -16,6 +16,10 @@ B = B_3 (x) B_2 (x) B_1, W^(00) = W_3^{00} (x) W_2^{00} (x) W_1^{00} and
 D = diag(alpha(x_q) det J(x_q)) (the mass integrand pulled back to the
 parametric domain).
 
+With ``rule="gauss"`` the same factorisation holds for standard Gauss
+quadrature (p + 1 points per element, test factors w_q b_i^{(a)}(x_q); the
+remark after rem:memory, eq. WDBgaussian): the Gauss-quadrature Galerkin matrix.
+
 ``assemble`` builds the operator explicitly as a scipy.sparse matrix (small sizes only);
 ``apply`` / ``apply_T`` evaluate K~ v and K~^T v with one 1D product per mode
 (eq. sum-factorization) and no fusion.  ``rhs`` is the load vector of reading
@@ -49,9 +53,9 @@ def mode(A, X, axis):
 class Problem:
     """Spaces, geometry and coefficient planes of one single-patch problem."""
 
-    def __init__(self, knots3, p, ctrl, K_fn=None):
+    def __init__(self, knots3, p, ctrl, K_fn=None, rule="wq"):
         self.p = p
-        self.spaces = [Space1D(k, p) for k in knots3]
+        self.spaces = [Space1D(k, p, rule) for k in knots3]
         S1, S2, S3 = self.spaces
         self.n = (S1.n, S2.n, S3.n)
         self.nq = (S1.nq, S2.nq, S3.nq)

@@ -29,7 +29,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .bspline import basis_matrix, breakpoints, galerkin_1d, n_basis
+from .bspline import basis_matrix, breakpoints, galerkin_1d, gauss_points, n_basis
 
 RANK_RTOL = 1e-12
 
@@ -95,19 +95,40 @@ def weights(knots, p: int, xq=None):
     return out
 
 
-class Space1D:
-    """Everything one direction contributes: knots, points, B, B-dot, W^{ab}."""
+def gauss_weights(knots, p: int, xq, wq):
+    """Standard Gauss quadrature written as test factors (the remark after
+    rem:memory, eq. WDBgaussian): W^{ab}_{iq} = w_q b_i^{(a)}(x_q) for the
+    interior i, the same for both trial orders b."""
+    out = {}
+    for a in (0, 1):
+        Wa = (interior_B(knots, p, xq, a) * np.asarray(wq)[:, None]).T
+        out[(a, 0)] = Wa
+        out[(a, 1)] = Wa.copy()
+    return out
 
-    def __init__(self, knots, p: int):
+
+class Space1D:
+    """Everything one direction contributes: knots, points, B, B-dot, W^{ab}.
+    rule "wq": weighted quadrature (Section 2.2); "gauss": p + 1 Gauss points per
+    element with the weights as test factors (the remark after rem:memory)."""
+
+    def __init__(self, knots, p: int, rule: str = "wq"):
         self.knots = np.asarray(knots, dtype=np.float64)
         self.p = p
+        self.rule = rule
         self.m = n_basis(self.knots, p)
         self.n = self.m - 2
-        self.xq = quad_points(self.knots, p)
+        if rule == "gauss":
+            self.xq, self.wq = gauss_points(self.knots, p + 1)
+        else:
+            self.xq = quad_points(self.knots, p)
         self.nq = len(self.xq)
         self.B = {b: interior_B(self.knots, p, self.xq, b) for b in (0, 1)}
         self.Bfull = {b: basis_matrix(self.knots, p, self.xq, b) for b in (0, 1)}
-        self.W = weights(self.knots, p, self.xq)
+        if rule == "gauss":
+            self.W = gauss_weights(self.knots, p, self.xq, self.wq)
+        else:
+            self.W = weights(self.knots, p, self.xq)
         # interior 1D Galerkin mass and stiffness (used by FD and by pins)
         self.M = galerkin_1d(self.knots, p, 0, 0)[1:-1, 1:-1]
         self.K = galerkin_1d(self.knots, p, 1, 1)[1:-1, 1:-1]

@@ -25,6 +25,8 @@ _vp, _i32p, _dp, _szp, _ip = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_dou
 SIGNATURES = [
     ("wq_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, C.c_int, _vp, C.c_int, _vp, C.c_size_t,
                            _szp, _vp, C.POINTER(C.c_void_p)]),
+    ("wq_setup_gauss", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, C.c_int, _vp, C.c_int, _vp,
+                                 C.c_size_t, _szp, _vp, C.POINTER(C.c_void_p)]),
     ("wq_dims", C.c_int, [_vp, _i32p, _i32p]),
     ("wq_quad_points", C.c_int, [_vp, _vp, _vp, _vp]),
     ("wq_detj", C.c_int, [_vp, _vp, _vp]),

@@ -410,9 +410,10 @@ extern "C" {
 const char* wq_last_error(void) { return g_err.c_str(); }
 const char* wq_version(void) { return "wqfd 0.1 (gfx950)"; }
 
-int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
-             const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s_,
-             wq_op* out) {
+// wq_setup and wq_setup_gauss: the same operator set-up for the two quadrature rules
+static int setup_impl(int rule, int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                      int k_kind, const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed,
+                      wq_stream_t s_, wq_op* out) {
     g_err.clear();
     hipStream_t s = reinterpret_cast<hipStream_t>(s_);
     int rc = check_knots_args(p, nknots, knots);
@@ -428,7 +429,7 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     wqfd::Space1D sp[3];
     std::string err;
     for (int l = 0; l < 3; ++l) {
-        rc = wqfd::build_space(p, nknots[l], knots[l], true, sp[l], err);
+        rc = wqfd::build_space(p, nknots[l], knots[l], true, sp[l], err, rule);
         if (rc) return fail(rc, "direction " + std::to_string(l + 1) + ": " + err);
     }
     auto op = std::make_unique<wq_op_s>();
@@ -599,6 +600,19 @@ int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const
     HIP_TRY(hipStreamSynchronize(s), "wq_setup sync");
     *out = op.release();
     return WQ_OK;
+}
+
+int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
+             const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s,
+             wq_op* out) {
+    return setup_impl(wqfd::kRuleWQ, p, nknots, knots, ctrl, k_kind, K_q, prec_mask, ws, ws_bytes, ws_needed, s, out);
+}
+
+int wq_setup_gauss(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
+                   const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s,
+                   wq_op* out) {
+    return setup_impl(wqfd::kRuleGauss, p, nknots, knots, ctrl, k_kind, K_q, prec_mask, ws, ws_bytes, ws_needed, s,
+                      out);
 }
 
 int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]) {

@@ -165,7 +165,7 @@ int eval_nonzero(const std::vector<double>& U, int p, int m, double x, double* N
 }
 
 int build_space(int p, int nknots, const double* knots, bool with_weights, Space1D& S,
-                std::string& err) {
+                std::string& err, int rule) {
     char buf[256];
     if (p < 2 || p > kMaxDegree) {
         snprintf(buf, sizeof buf, "degree p = %d outside [2, %d]", p, kMaxDegree);
@@ -204,13 +204,29 @@ int build_space(int p, int nknots, const double* knots, bool with_weights, Space
     }
     // quadrature points
     const auto& br = S.breaks;
-    std::vector<double> xq(br.begin(), br.end());
-    for (int e = 1; e < S.n_el - 1; ++e) xq.push_back(0.5 * (br[e] + br[e + 1]));
-    for (int e : {0, S.n_el - 1}) {
-        const double h = br[e + 1] - br[e];
-        for (int k = 1; k <= p + 1; ++k) xq.push_back(br[e] + k * h / (p + 2));
+    std::vector<double> gx, gw;                   // Gauss-Legendre rule on [-1, 1], p + 1 points
+    gauss_legendre(p + 1, gx, gw);
+    std::vector<double> xq, wq;                   // wq: Gauss weights of the points (Gauss rule)
+    if (rule == kRuleGauss) {
+        std::vector<int> ord(p + 1);                  // nodes in ascending order
+        for (int g = 0; g <= p; ++g) ord[g] = g;
+        std::sort(ord.begin(), ord.end(), [&](int u, int v) { return gx[u] < gx[v]; });
+        for (int e = 0; e < S.n_el; ++e) {
+            const double lo = br[e], h = br[e + 1] - br[e];
+            for (int g : ord) {
+                xq.push_back(lo + 0.5 * h * (gx[g] + 1.0));
+                wq.push_back(0.5 * h * gw[g]);
+            }
+        }
+    } else {
+        xq.assign(br.begin(), br.end());
+        for (int e = 1; e < S.n_el - 1; ++e) xq.push_back(0.5 * (br[e] + br[e + 1]));
+        for (int e : {0, S.n_el - 1}) {
+            const double h = br[e + 1] - br[e];
+            for (int k = 1; k <= p + 1; ++k) xq.push_back(br[e] + k * h / (p + 2));
+        }
+        std::sort(xq.begin(), xq.end());
     }
-    std::sort(xq.begin(), xq.end());
     S.xq = xq;
     S.nq = (int)xq.size();
     const int m = S.m, n = S.n, nq = S.nq;
@@ -233,8 +249,6 @@ int build_space(int p, int nknots, const double* knots, bool with_weights, Space
         }
     }
     // 1D Galerkin integrals G^{ab} (m x m) with p+1 Gauss points per element
-    std::vector<double> gx, gw;
-    gauss_legendre(p + 1, gx, gw);
     std::vector<double> G[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) G[a][b].assign((size_t)m * m, 0.0);
@@ -259,6 +273,15 @@ int build_space(int p, int nknots, const double* knots, bool with_weights, Space
             S.Ki[(size_t)i * n + j] = G[1][1][(size_t)(i + 1) * m + j + 1];
         }
     if (!with_weights) return WQ_OK;
+    if (rule == kRuleGauss) {                     // W^{ab}_iq = w_q b_i^{(a)}(x_q), any b
+        for (int a = 0; a < 2; ++a) {
+            S.W[a][0].assign((size_t)n * nq, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int q = 0; q < nq; ++q) S.W[a][0][(size_t)i * nq + q] = wq[q] * S.B[a][(size_t)q * n + i];
+            S.W[a][1] = S.W[a][0];
+        }
+        return WQ_OK;
+    }
     // weights
     double worst = 0.0;
     for (int a = 0; a < 2; ++a)

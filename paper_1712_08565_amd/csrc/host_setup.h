@@ -12,6 +12,12 @@ namespace wqfd {
 
 constexpr int kMaxDegree = 10;
 
+// Quadrature rule of the operator: weighted quadrature (Section 2.2), or the
+// standard Gauss rule with p + 1 points per element, whose test factor is
+// W_iq = w_q b_i^{(a)}(x_q) for every trial derivative order (the remark after
+// rem:memory, eq. WDBgaussian).
+enum Rule { kRuleWQ = 0, kRuleGauss = 1 };
+
 // One direction of the tensor-product space (Section 2.1): open knot vector
 // with simple interior knots, m B-splines of degree p, n = m - 2 interior ones,
 // nq quadrature points (Section 2.2).
@@ -28,10 +34,10 @@ struct Space1D {
     double max_exactness_residual = 0.0;
 };
 
-// Validates the knot vector and builds everything above.  Returns 0 or a
-// negative wqfd error code with a message in `err`.
+// Validates the knot vector and builds everything above for the given rule.
+// Returns 0 or a negative wqfd error code with a message in `err`.
 int build_space(int p, int nknots, const double* knots, bool with_weights, Space1D& out,
-                std::string& err);
+                std::string& err, int rule = kRuleWQ);
 
 // Values and first derivatives of the p+1 B-splines that are non-zero on the
 // knot span containing x (span index returned; x == 1 uses the last span).

@@ -37,9 +37,9 @@ def K_at(wl, Fq: torch.Tensor):
     return WQ_K_SYM6, K.t().contiguous().reshape(-1)
 
 
-def build(wl, prec_mask: int = WQ_F64, fd_prec_mask: int = WQ_F64, device="cuda") -> DeviceProblem:
+def build(wl, prec_mask: int = WQ_F64, fd_prec_mask: int = WQ_F64, device="cuda", rule: str = "wq") -> DeviceProblem:
     knots = wl.knots()
-    A = wqfd.wq_setup(wl.p, knots, wl.ctrl(), WQ_K_IDENTITY, None, prec_mask, device)
+    A = wqfd.wq_setup(wl.p, knots, wl.ctrl(), WQ_K_IDENTITY, None, prec_mask, device, rule=rule)
     _, Fq = wqfd.wq_quad_points(A)
     kind, K_q = K_at(wl, Fq)
     if kind != WQ_K_IDENTITY:

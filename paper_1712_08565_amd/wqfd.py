@@ -80,19 +80,22 @@ class FdPc:
 
 
 def wq_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, k_kind: int = WQ_K_IDENTITY,
-             K_q: Optional[torch.Tensor] = None, prec_mask: int = WQ_F64, device="cuda", stream=None) -> WqOp:
+             K_q: Optional[torch.Tensor] = None, prec_mask: int = WQ_F64, device="cuda", stream=None,
+             rule: str = "wq") -> WqOp:
+    """rule "wq": weighted quadrature (wq_setup); "gauss": p + 1 Gauss points per element (wq_setup_gauss)."""
     ks, nk, kp = _knots(knots)
     ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
     need = C.c_size_t(0)
     h = C.c_void_p(0)
     L = lib()
-    check(L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, C.c_void_p(0), prec_mask, None, 0,
-                     C.byref(need), _stream(stream), C.byref(h)), "wq_setup(size)")
+    fn, name = {"wq": (L.wq_setup, "wq_setup"), "gauss": (L.wq_setup_gauss, "wq_setup_gauss")}[rule]
+    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, C.c_void_p(0), prec_mask, None, 0,
+             C.byref(need), _stream(stream), C.byref(h)), name + "(size)")
     ws = torch.empty(need.value, dtype=torch.uint8, device=device)
     if K_q is not None:
         K_q = K_q.contiguous()
-    check(L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, _p(K_q), prec_mask, _p(ws), need.value,
-                     None, _stream(stream), C.byref(h)), "wq_setup")
+    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, _p(K_q), prec_mask, _p(ws), need.value,
+             None, _stream(stream), C.byref(h)), name)
     return WqOp(h, ws, p, prec_mask, k_kind, device)
 
 

@@ -1,0 +1,115 @@
+"""GPU parity of the Gauss-quadrature variant (the remark after rem:memory:
+standard Gauss quadrature, p + 1 points per element, test factors
+w_q b_i^{(a)}(x_q), run through the same fused kernels) against the CPU FP64
+oracle with the same rule.  Gates as for weighted quadrature: FP64 apply and
+transposed apply <= 1e-12 relative; FP32 <= 1e-5; solves: error vs the oracle's
+direct solve <= 1e-10 (or the residual gate of reading R10)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle.operator import Problem
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["cube12_p3", "ring8_p2", "ring8_p6", "twist6_p6", "ring20_p6", "ring18_p7", "ring6_p8"]
+_cache = {}
+
+
+def setup(name):
+    if name in _cache:
+        return _cache[name]
+    import torch
+    from paper_1712_08565_amd import problem
+    from paper_1712_08565_amd.wqfd import WQ_F32, WQ_F64
+    wl = synth.workload(name)
+    print(f"[gauss] setup {name} (p={wl.p}, n_el={wl.n_el})", flush=True)
+    dp = problem.build(wl, WQ_F64 | WQ_F32, WQ_F64, rule="gauss")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field(), rule="gauss")
+    torch.cuda.synchronize()
+    _cache[name] = (wl, dp, pr)
+    return _cache[name]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+def dev(x, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), device="cuda", dtype=dtype or torch.float64)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_gauss_points_and_apply_parity(name):
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    n, nq = wqfd.wq_dims(dp.A)
+    assert n == pr.n and nq == pr.nq and nq[0] == (wl.p + 1) * wl.n_el
+    xq, _ = wqfd.wq_quad_points(dp.A)
+    e_x = max(float(np.abs(xq[l] - pr.spaces[l].xq).max()) for l in range(3))
+    v = synth.random_vector(pr.N, 81)
+    u = synth.random_vector(pr.N, 82)
+    w = host(wqfd.wq_apply(dp.A, dev(v)))
+    wT = host(wqfd.wq_apply_T(dp.A, dev(v)))
+    e, eT = rel(w, pr.apply(v)), rel(wT, pr.apply_T(v))
+    gu = host(wqfd.wq_apply(dp.A, dev(u)))
+    d = abs(gu @ v - u @ wT) / (np.linalg.norm(gu) * np.linalg.norm(v))
+    print(f"[gauss] {name}: n_q {nq}, points {e_x:.1e}, apply {e:.2e}, apply_T {eT:.2e}, adjoint identity {d:.2e}")
+    assert e_x < 1e-15 and e <= 1e-12 and eT <= 1e-12 and d <= 1e-13, (e_x, e, eT, d)
+
+
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p6", "ring18_p7"])
+def test_gauss_runs_the_fused_kernels(name):
+    """p <= 7: the Gauss tables pass the fused kernels' footprint and band
+    checks, so the accumulating apply (fused only) is accepted and adds K v."""
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    v = synth.random_vector(pr.N, 83)
+    w0 = synth.random_vector(pr.N, 84)
+    w = dev(w0)
+    wqfd.wq_apply_acc(dp.A, dev(v), w)
+    e = rel(host(w), w0 + pr.apply(v))
+    assert e <= 1e-12, f"{e:.3e}"
+
+
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p6", "twist6_p6"])
+def test_gauss_apply_fp32_error(name):
+    import torch
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    v = synth.random_vector(pr.N, 85)
+    e = rel(host(wqfd.wq_apply(dp.A, dev(v, torch.float32))), pr.apply(v))
+    print(f"[gauss fp32] {name}: {e:.2e}")
+    assert e <= 1e-5, f"{e:.3e}"
+
+
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p2", "twist6_p6"])
+def test_gauss_solve_parity(name):
+    """Gauss Galerkin with K = I on the identity cube is the FD operator itself:
+    one iteration there.  Gates: the oracle's matrix-free residual of the GPU
+    solution <= 1e-12; for p <= 3 also the error vs the oracle's direct solve
+    (assembling the Gauss operator is dense and slow at higher p)."""
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    b = pr.rhs_from(wl.f())
+    e_b = rel(host(dp.b), b)
+    x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-14, maxit=400, raise_on_noconv=False)
+    xh = host(x)
+    r_or = float(np.linalg.norm(b - pr.apply(xh)) / np.linalg.norm(b))
+    print(f"[gauss solve] {name}: rhs {e_b:.2e}, {it} it, relres {res:.2e}, oracle residual {r_or:.2e}")
+    assert e_b <= 1e-12 and res <= 1e-13 and r_or <= 1e-12, (e_b, res, r_or)
+    if name == "cube12_p3":
+        assert it == 1
+    if wl.p <= 3:
+        K = pr.assemble()
+        e = rel(xh, spla.spsolve(K.tocsc(), b))
+        print(f"[gauss solve] {name}: error vs direct {e:.2e}")
+        if e > 1e-10:
+            cond = np.linalg.cond(K.toarray())
+            assert e <= 10 * cond * r_or, (e, cond, r_or)

@@ -22,7 +22,12 @@ which re-types the oracle's own formulas:
   FD Kronecker sum, and the shifted FD is its exact inverse (one iteration); on
   an affine map M~ carries the constant det J; with a variable alpha the
   manufactured solution converges at the spline rate, and a planted mistake
-  (alpha without det J) breaks that.
+  (alpha without det J) breaks that;
+* Gauss-quadrature variant (the remark after rem:memory): exact Galerkin
+  stiffness on the identity cube with a constant SPD K, a symmetric operator on
+  curved maps (where weighted quadrature is not), and equality with a brute-force
+  element-by-element Gauss assembly whose bases and geometry come from
+  scipy.interpolate.BSpline.
 """
 import math
 
@@ -418,3 +423,68 @@ def test_reaction_without_det_J_fails_on_a_scaled_cube():
         return errors(kn, p, ctrl, x, u)[1]
     good, bad = err(False), err(True)
     assert bad > 5 * good
+
+
+# ---------------------------------------------------------------- Gauss-quadrature variant
+def test_gauss_identity_geometry_full_constant_K():
+    p = 3
+    k = nonuniform_knots(5, p, seed=2)
+    kn = (k, k, k)
+    Kc = np.array([[2.0, 0.5, 0.3], [0.5, 1.5, 0.2], [0.3, 0.2, 1.0]])
+    K6 = np.array([Kc[a, b] for a, b in geometry.SYM_PAIRS])
+    pr = Problem(kn, p, synth.control_net("identity", kn, p),
+                 lambda X: np.broadcast_to(K6, X.shape[:-1] + (6,)).copy(), rule="gauss")
+    assert pr.nq == ((p + 1) * 5,) * 3
+    Kt = pr.assemble().toarray()
+    G = {(a, b): _interior_galerkin(k, p, a, b) for a in (0, 1) for b in (0, 1)}
+    ref = 0
+    for al in range(3):
+        for be in range(3):
+            ab = [(int(l == al), int(l == be)) for l in range(3)]
+            ref = ref + Kc[al, be] * np.kron(G[ab[2]], np.kron(G[ab[1]], G[ab[0]]))
+    assert np.abs(Kt - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("name", ["ring8_p3", "twist5_p4"])
+def test_gauss_operator_symmetric_on_curved_maps(name):
+    wl = synth.workload(name)
+    g = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field(), rule="gauss").assemble()
+    w = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field()).assemble()
+    asym = lambda A: abs(A - A.T).max() / abs(A).max()
+    assert asym(g) < 1e-14
+    assert asym(w) > 1e-6              # weighted quadrature is not symmetric there: the pin discriminates
+
+
+def test_gauss_matches_elementwise_brute_force():
+    """K_ij = sum over elements and Gauss points of w grad b_i . C grad b_j with
+    C = det J J^{-1} J^{-T}, bases and geometry from scipy BSpline, on a tiny ring."""
+    p, ne = 2, 3
+    k = synth.uniform_knots(ne, p)
+    kn = (k, k, k)
+    ctrl = synth.control_net("ring", kn, p, 0.02, 0)
+    m = len(k) - p - 1
+    g, gw = np.polynomial.legendre.leggauss(p + 1)
+    br = np.unique(k)
+    x = np.concatenate([0.5 * (b - a) * g + 0.5 * (a + b) for a, b in zip(br[:-1], br[1:])])
+    wx = np.concatenate([0.5 * (b - a) * gw for a, b in zip(br[:-1], br[1:])])
+    Bv = BSpline.design_matrix(x, k, p).toarray()                                   # [q, j]
+    Bd = np.stack([BSpline(k, np.eye(m)[j], p).derivative()(x) for j in range(m)], 1)
+    # geometry F = sum ctrl[c, b, a] N_a(x1) N_b(x2) N_c(x3) and J_rs = dF_r / dxi_s
+    d1 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bd, Bv, Bv)
+    d2 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bv, Bd, Bv)
+    d3 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bv, Bv, Bd)
+    J = np.stack([d1, d2, d3], -1)                                                  # [k, j, i, r, s]
+    Ji = np.linalg.inv(J)
+    C = np.linalg.det(J)[..., None, None] * (Ji @ np.swapaxes(Ji, -1, -2))
+    w3 = np.einsum("k,j,i->kji", wx, wx, wx)
+    # gradients of the interior tensor-product functions (x fastest) in the parametric frame
+    Vi, Di = Bv[:, 1:m - 1], Bd[:, 1:m - 1]
+    G = np.stack([np.einsum("kc,jb,ia->kjicba", Vi, Vi, Di),
+                  np.einsum("kc,jb,ia->kjicba", Vi, Di, Vi),
+                  np.einsum("kc,jb,ia->kjicba", Di, Vi, Vi)], -1)                   # [k, j, i, c, b, a, s]
+    n = m - 2
+    G = G.reshape(len(x), len(x), len(x), n ** 3, 3)
+    Kref = np.einsum("kjiu,kjiAs,kjist,kjiBt->AB", w3[..., None], G, C, G, optimize=True)
+    pr = Problem(kn, p, ctrl, rule="gauss")
+    Kt = pr.assemble().toarray()
+    assert np.abs(Kt - Kref).max() <= 1e-13 * np.abs(Kref).max()
