@@ -136,6 +136,9 @@ def main():
     ap.add_argument("--mixed-tau", type=float, default=1e-4, help="inner relative tolerance of the refinement")
     ap.add_argument("--reaction-degree", type=int, default=3,
                     help="degree of the reaction-term measurement on the same ring (0: skip)")
+    ap.add_argument("--gauss-degrees", default="",
+                    help="degrees of a Gauss-quadrature comparison on the same ring (e.g. 2,3,4; off by default: "
+                         "it launches the same kernel instances as the timed applies)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB per step (counter calibration)")
     args = ap.parse_args()
@@ -366,6 +369,39 @@ def main():
         for i in range(args.warmup + args.steps):
             reaction_step(i >= args.warmup)
         log("reaction-term measurement done")
+    # Gauss-quadrature variant of the same operator (p + 1 Gauss points per element,
+    # the same fused kernels): applies only, one operator at a time
+    gauss = {}
+    if args.gauss_degrees and not args.workloads:
+        for gp in [int(x) for x in args.gauss_degrees.split(",")]:
+            wl = synth.Workload(f"ring{args.n_el}_p{gp}", args.n_el, gp, "ring", 0.02, "identity", "paper")
+            t0g = time.perf_counter()
+            A = wqfd.wq_setup(gp, wl.knots(), wl.ctrl(), wqfd.WQ_K_IDENTITY, None, wqfd.WQ_F64, rule="gauss")
+            setup_g = time.perf_counter() - t0g
+            vg = torch.as_tensor(synth.random_vector(A.N, 42), device="cuda")
+            wg, wgacc = torch.empty_like(vg), torch.zeros_like(vg)
+            ap_ms, k_ms = [], []
+            for i in range(args.warmup + args.steps):
+                evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                       for _ in range(args.reps)]
+                for e0, e1 in evs:
+                    e0.record(stream)
+                    wqfd.wq_apply(A, vg, wg)
+                    e1.record(stream)
+                k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                k0.record(stream)
+                for _ in range(args.reps):
+                    wqfd.wq_apply_acc(A, vg, wgacc)
+                k1.record(stream)
+                torch.cuda.synchronize()
+                if i >= args.warmup:
+                    ap_ms += [e0.elapsed_time(e1) for e0, e1 in evs]
+                    k_ms.append(k0.elapsed_time(k1) / args.reps)
+            gauss[gp] = dict(N=A.N, Nq=A.Nq, apply_ms=float(np.mean(ap_ms)), kernel_ms=float(np.mean(k_ms)),
+                             setup_s=setup_g)
+            del A, vg, wg, wgacc
+            torch.cuda.empty_cache()
+            log(f"gauss p={gp} done")
 
     tot_dof = sum(probs[p]["N"] * len(rec[p]["apply_ms"]) for p in keys)
     tot_s = sum(sum(rec[p]["apply_ms"]) for p in keys) / 1e3
@@ -451,6 +487,24 @@ def main():
                        "mixed_solve_ms": round(float(np.median(R["mix_ms"])), 2),
                        "mixed_inner": int(np.median(R["mix_inner"]))})
         out["reaction"] = rr
+    if gauss:
+        gd = {}
+        for gp, g in gauss.items():
+            alg = 48 * g["Nq"] + 16 * g["N"]
+            e = {"Nq": g["Nq"], "apply_ms": round(g["apply_ms"], 4), "kernel_ms": round(g["kernel_ms"], 4),
+                 "apply_GDOFs": round(g["N"] / g["apply_ms"] / 1e6, 3),
+                 "kernel_GBs": round(alg / g["kernel_ms"] / 1e6, 1),
+                 "kernel_frac_of_hbm_peak": round(alg / g["kernel_ms"] / 1e6 / HBM_PEAK_GBS, 4),
+                 "setup_s": round(g["setup_s"], 2)}
+            wq_p = per_p.get(f"p{gp}")
+            if wq_p is not None:
+                e["Nq_vs_wq"] = round(g["Nq"] / wq_p["Nq"], 2)
+                e["apply_time_vs_wq"] = round(g["apply_ms"] / wq_p["apply_ms"], 2)
+            gd[f"p{gp}"] = e
+        out["gauss_quadrature"] = {
+            "workload": f"thick quarter ring, {args.n_el}^3 elements, K = I, the same operator with p + 1 "
+                        f"Gauss points per element (wq_setup_gauss), FP64 apply through the same fused kernels",
+            "bytes_per_launch": "48 N_q + 16 N", "per_degree": gd}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
