@@ -1,11 +1,14 @@
 /*
  * wqfd.h -- C ABI of the MI355X (gfx950) matrix-free weighted-quadrature
  * (MF-WQ) isogeometric solver: the WQ stiffness operator of Section 3.2
- * (Algorithm 2), its transpose, the Fast Diagonalization (FD) preconditioner
- * used in Section 4, and a right-preconditioned BiCGStab driver (Section 4).
+ * (Algorithm 2), its transpose, the WQ mass operator of the reaction term
+ * (Section 3.1, Algorithm 1), the Fast Diagonalization (FD) preconditioner
+ * used in Section 4, a right-preconditioned BiCGStab driver (Section 4), mixed-
+ * precision refinement, adjoint gradients, and the same operator with standard
+ * Gauss quadrature as a baseline (wq_setup_gauss).
  *
- * Model problem (Section 2.1, eq. poisson, with alpha = 0):
- *     -div(K grad u) = f on Omega = F([0,1]^3),  u = 0 on the boundary,
+ * Model problem (Section 2.1, eq. poisson; alpha = 0 until wq_set_alpha):
+ *     -div(K grad u) + alpha u = f on Omega = F([0,1]^3),  u = 0 on the boundary,
  * discretised with degree-p splines of maximum regularity on open knot
  * vectors, homogeneous Dirichlet space of eq. (space): n = m - 2 interior
  * B-splines per direction, N = n1 n2 n3 unknowns, x index fastest (eq. ordering).

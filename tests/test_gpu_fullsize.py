@@ -6,7 +6,9 @@ benchmark times.  The oracle cannot assemble K~ at this size, so:
     rounding scale sum_j |K_ij v_j| (<= 1e-12);
   * transposed apply: <K~ v, u> = <v, K~^T u> (<= 1e-13 relative);
   * FD and load vector: the oracle's full vectors (<= 1e-12 relative);
-  * FP64 solve: the oracle's matrix-free residual of the GPU solution <= 1e-10.
+  * FP64 solve: the oracle's matrix-free residual of the GPU solution <= 1e-10;
+  * reaction term (p = 3, the bench's alpha): sampled rows of K~ + M~ the same
+    way, and the transpose identity.
 """
 import numpy as np
 import pytest
@@ -104,3 +106,31 @@ def test_fullsize_solve_residual(name):
     res = float(np.linalg.norm(b - pr.apply(xh)) / np.linalg.norm(b))
     print(f"[fullsize] {name}: {it} iterations, reported {rel:.2e}, oracle residual {res:.2e}", flush=True)
     assert res <= 1e-10, f"{res:.3e}"
+
+
+def test_fullsize_reaction_sampled_rows():
+    import torch
+    from paper_1712_08565_amd import problem, wqfd
+    from paper_1712_08565_amd.wqfd import WQ_F64
+    wl, _, pr = setup("ring64_p3")
+    alpha_fn = synth.alpha_field(10.0 * wl.n_el ** 2)
+    dp = problem.build(wl, WQ_F64, WQ_F64)
+    problem.set_reaction(dp, alpha_fn)
+    pr.set_alpha(alpha_fn(pr.F))
+    try:
+        v = synth.random_vector(pr.N, 42)
+        u = synth.random_vector(pr.N, 44)
+        w = wqfd.wq_apply(dp.A, dev(v)).cpu().numpy()
+        KTu = wqfd.wq_apply_T(dp.A, dev(u)).cpu().numpy()
+        worst = 0.0
+        for i in sample_rows(pr.n, wl.p):
+            row = pr.explicit_row(i)
+            worst = max(worst, abs(w[i] - float(row @ v)) / float(np.abs(row) @ np.abs(v)))
+        d = abs(w @ u - v @ KTu) / (np.linalg.norm(w) * np.linalg.norm(u))
+        print(f"[fullsize] ring64_p3 + alpha: worst sampled row / rounding scale {worst:.2e}, "
+              f"transpose identity {d:.2e}", flush=True)
+        assert worst <= 1e-12 and d <= 1e-13, (worst, d)
+    finally:
+        pr.set_alpha(None)
+        del dp
+        torch.cuda.empty_cache()
