@@ -770,8 +770,10 @@ __global__ __launch_bounds__(256) void zero_kernel(T* __restrict__ w, size_t n) 
 
 template <typename T>
 void launch_zero(T* w, size_t n, hipStream_t s) {
-    size_t g = (n * sizeof(T) / 16 + 255) / 256;
-    g = g < 1 ? 1 : g > 4096 ? 4096 : g;
+    // about eight 16-byte stores per thread: a clear of a few MB is launch-bound,
+    // and fewer workgroups start and retire sooner
+    size_t g = (n * sizeof(T) / 16 + 2047) / 2048;
+    g = g < 1 ? 1 : g > 1024 ? 1024 : g;
     hipLaunchKernelGGL(zero_kernel<T>, dim3((unsigned)g), dim3(256), 0, s, w, n);
 }
 
