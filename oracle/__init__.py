@@ -25,6 +25,8 @@ Plain, slow and written to be checked against the paper by eye:
 
 Every function documents the passage it follows.  Readings of places where the
 paper is silent or ambiguous are named R1..R10 in the docstrings; the same
-readings are implemented (independently) by the library.  "parity unpinned"
-marks results with no pin other than the shared reading.
+readings are implemented (independently) by the library.  Every function is
+pinned by tests/test_oracle_pins.py and tests/test_oracle_adjoint.py against
+facts the paper or the mathematics fixes, or against a rebuild from the
+definitions with independent library routines; none is "parity unpinned".
 """

@@ -23,6 +23,11 @@ which re-types the oracle's own formulas:
   an affine map M~ carries the constant det J; with a variable alpha the
   manufactured solution converges at the spline rate, and a planted mistake
   (alpha without det J) breaks that;
+* weighted quadrature on a curved map: the oracle's K~ on a tiny ring equals K~
+  rebuilt from its definition (eq. Kwq) by independent routines: scipy BSpline
+  values and derivatives, Gauss-Legendre Galerkin integrals, scipy.linalg.lstsq
+  minimum-norm weights (readings R1-R3), a scipy-evaluated map and dense
+  Kronecker products;
 * Gauss-quadrature variant (the remark after rem:memory): exact Galerkin
   stiffness on the identity cube with a constant SPD K, a symmetric operator on
   curved maps (where weighted quadrature is not), and equality with a brute-force
@@ -488,3 +493,77 @@ def test_gauss_matches_elementwise_brute_force():
     pr = Problem(kn, p, ctrl, rule="gauss")
     Kt = pr.assemble().toarray()
     assert np.abs(Kt - Kref).max() <= 1e-13 * np.abs(Kref).max()
+
+
+def _scipy_map(ctrl, k, p, x):
+    """F and J (last two axes r, s: dF_r / dxi_s) at the tensor grid x^3 from scipy BSpline."""
+    m = len(k) - p - 1
+    Bv = BSpline.design_matrix(x, k, p).toarray()
+    Bd = np.stack([BSpline(k, np.eye(m)[j], p).derivative()(x) for j in range(m)], 1)
+    d1 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bd, Bv, Bv)
+    d2 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bv, Bd, Bv)
+    d3 = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bv, Bv, Bd)
+    return np.stack([d1, d2, d3], -1)
+
+
+@pytest.mark.parametrize("p,ne", [(2, 3), (3, 3)])
+def test_wq_operator_on_curved_map_from_its_definition(p, ne):
+    k = synth.uniform_knots(ne, p)
+    m = len(k) - p - 1
+    n = m - 2
+    br = np.unique(k)
+    # points (reading R1): breakpoints, interior midpoints, p + 1 equispaced points in each end element
+    x = list(br) + [0.5 * (a + b) for a, b in zip(br[1:-2], br[2:-1])]
+    for e in (0, len(br) - 2):
+        h = br[e + 1] - br[e]
+        x += [br[e] + j * h / (p + 2) for j in range(1, p + 2)]
+    x = np.sort(np.array(x))
+    assert len(x) == 2 * ne + 2 * p + 1
+    # basis values / derivatives at the points and 1D Galerkin integrals (Gauss-Legendre, exact here)
+    sp = [BSpline(k, np.eye(m)[j], p) for j in range(m)]
+    Bf = {0: np.stack([s(x) for s in sp], 1), 1: np.stack([s.derivative()(x) for s in sp], 1)}
+    g, gw = np.polynomial.legendre.leggauss(p + 1)
+    G = {(a, b): np.zeros((m, m)) for a in (0, 1) for b in (0, 1)}
+    for lo, hi in zip(br[:-1], br[1:]):
+        xe, we = 0.5 * (hi - lo) * g + 0.5 * (hi + lo), 0.5 * (hi - lo) * gw
+        V = {0: np.stack([s(xe) for s in sp], 1), 1: np.stack([s.derivative()(xe) for s in sp], 1)}
+        for a in (0, 1):
+            for b in (0, 1):
+                G[(a, b)] += (V[a] * we[:, None]).T @ V[b]
+    # weights (readings R2, R3): minimum-norm solution of the exactness conditions over supp(b_i)
+    W = {}
+    for a in (0, 1):
+        for b in (0, 1):
+            Wab = np.zeros((n, len(x)))
+            for i in range(1, m - 1):
+                S = np.nonzero((x >= k[i]) & (x <= k[i + p + 1]))[0]
+                T = [j for j in range(m) if abs(j - i) <= p]
+                sol = sla.lstsq(Bf[b][np.ix_(S, T)].T, G[(a, b)][i, T])[0]
+                Wab[i - 1, S] = sol
+            W[(a, b)] = Wab
+    B = {d: Bf[d][:, 1:m - 1] for d in (0, 1)}
+    # geometry and C = det J J^{-1} J^{-T} (reading R5, K = I)
+    ctrl = synth.control_net("ring", (k, k, k), p, 0.02, 0)
+    J = _scipy_map(ctrl, k, p, x)
+    Ji = np.linalg.inv(J)
+    C = np.linalg.det(J)[..., None, None] * (Ji @ np.swapaxes(Ji, -1, -2))
+    # K~ = sum_{alpha, beta} W^(alpha beta) diag(C_{alpha beta}) B^(beta), dense Kronecker products
+    K = 0
+    for al in range(3):
+        for be in range(3):
+            ab = [(int(l == al), int(l == be)) for l in range(3)]
+            Wk = np.kron(W[ab[2]], np.kron(W[ab[1]], W[ab[0]]))
+            Bk = np.kron(B[ab[2][1]], np.kron(B[ab[1][1]], B[ab[0][1]]))
+            K = K + Wk @ (C[..., al, be].ravel()[:, None] * Bk)
+    pr = Problem((k, k, k), p, ctrl)
+    Kt = pr.assemble().toarray()
+    assert np.abs(Kt - K).max() <= 1e-12 * np.abs(K).max()
+    # the comparison separates a plausible slip: test and trial derivative orders swapped in the weights
+    Kbad = 0
+    for al in range(3):
+        for be in range(3):
+            ab = [(int(l == al), int(l == be)) for l in range(3)]
+            Wk = np.kron(W[ab[2][::-1]], np.kron(W[ab[1][::-1]], W[ab[0][::-1]]))
+            Bk = np.kron(B[ab[2][1]], np.kron(B[ab[1][1]], B[ab[0][1]]))
+            Kbad = Kbad + Wk @ (C[..., al, be].ravel()[:, None] * Bk)
+    assert np.abs(Kt - Kbad).max() > 1e-2 * np.abs(K).max()
