@@ -27,7 +27,7 @@ which re-types the oracle's own formulas:
   rebuilt from its definition (eq. Kwq) by independent routines: scipy BSpline
   values and derivatives, Gauss-Legendre Galerkin integrals, scipy.linalg.lstsq
   minimum-norm weights (readings R1-R3), a scipy-evaluated map and dense
-  Kronecker products;
+  Kronecker products; the same with the reaction term W^(00) diag(alpha det J) B;
 * Gauss-quadrature variant (the remark after rem:memory): exact Galerkin
   stiffness on the identity cube with a constant SPD K, a symmetric operator on
   curved maps (where weighted quadrature is not), and equality with a brute-force
@@ -558,6 +558,16 @@ def test_wq_operator_on_curved_map_from_its_definition(p, ne):
     pr = Problem((k, k, k), p, ctrl)
     Kt = pr.assemble().toarray()
     assert np.abs(Kt - K).max() <= 1e-12 * np.abs(K).max()
+    # reaction term: + W^(00) diag(alpha det J) B (eq. WDB), alpha at the scipy-evaluated points
+    Bv = BSpline.design_matrix(x, k, p).toarray()
+    Xp = np.einsum("cbar,ia,jb,kc->kjir", ctrl, Bv, Bv, Bv)
+    alpha = synth.alpha_field(50.0)
+    cm = alpha(Xp) * np.linalg.det(J)
+    M = np.kron(W[(0, 0)], np.kron(W[(0, 0)], W[(0, 0)])) @ (cm.ravel()[:, None] * np.kron(B[0], np.kron(B[0], B[0])))
+    pr.set_alpha(alpha(pr.F))
+    KMt = pr.assemble().toarray()
+    assert np.abs(KMt - (K + M)).max() <= 1e-12 * np.abs(K + M).max()
+    assert np.abs(M).max() > 1e-2 * np.abs(K).max()        # the reaction part is not negligible here
     # the comparison separates a plausible slip: test and trial derivative orders swapped in the weights
     Kbad = 0
     for al in range(3):
