@@ -39,6 +39,7 @@ import argparse
 import hashlib
 import json
 import math
+import re
 import os
 import sys
 import time
@@ -56,11 +57,21 @@ EQ_TOL = 1e-10
 RTOL_LADDER = [1e-10, 3e-11, 1e-11, 3e-12, 1e-12, 3e-13, 1e-13]
 
 
+def _code_only(text: str) -> str:
+    """The source without comments, trailing blanks and empty lines (the kernel
+    sources hold no string literals with comment markers)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+
+
 def kernel_hash() -> str:
+    """sha256 of the code of the fused-apply sources (comments excluded, so that
+    a counter summary stays valid across comment edits)."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()
 
 

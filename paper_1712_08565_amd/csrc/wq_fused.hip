@@ -4,10 +4,12 @@
 // contiguous range of quadrature planes k, and streams through k:
 //
 //   trial (v~^b = B^(b) v):  each DOF plane j3 entering the z window is
-//       contracted in x and y on the matrix cores (two 16x16x16 products for
-//       x, three for y), giving U_x = (B2 x B-dot1) v, U_y = (B-dot2 x B1) v,
-//       U_0 = (B2 x B1) v at the tile's columns; every thread keeps the last
-//       p+1 planes of its column in registers and forms
+//       contracted in x (B1 and B-dot1, by the MFMA waves on the vector units
+//       with the exact band of p+1 functions per point) and then in y (by the
+//       column waves as the plane enters their window, exact band again),
+//       giving U_x = (B2 x B-dot1) v, U_y = (B-dot2 x B1) v, U_0 = (B2 x B1) v
+//       at the tile's columns; every thread keeps the last p+1 planes of its
+//       column in registers and forms
 //         v~^x = sum_j3 B3 U_x,  v~^y = sum_j3 B3 U_y,  v~^z = sum_j3 B-dot3 U_0.
 //   pointwise: psi_ab = C_ab(x_q) v~^b, the six coefficient planes streamed
 //       from HBM once, coalesced along x.
