@@ -151,6 +151,8 @@ struct FusedHost {
     std::vector<int> band[2];       // [tile][16]: first nonzero (local) j of the B / B-dot rows of the tile's points
     std::vector<int> bs3, wts3;
     std::vector<double> cz;         // [nq3][2(p+1) + 4(p+2)]
+    std::vector<double> czT;        // the same rows for the transposed kernel (ring slot order for p >= FUSED_RING_MIN_P)
+    std::vector<int> rotT;          // [nq3][2]: transposed rings' offsets (input, output) when plane k is processed
     int zchunk = 0;
     std::vector<int> sched;         // interval records (wqfd::FusedSched), all z ranges
     std::vector<int> sched_off;     // first record of each z range, plus the total
@@ -192,7 +194,7 @@ int choose_zchunk(int nq3, int tiles, int slots, int p) {
 // plane (forward: B3 band, p + 1; transposed: W3 band, p + 2); outs/OUT: the
 // same for the output ring (forward: W3, p + 2; transposed: B3, p + 1).
 bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>& outs, int OUT, int n3, int k0,
-                    int k1, int CZ, std::vector<int>& out) {
+                    int k1, int CZ, std::vector<int>& out, std::vector<int>* rot) {
     const int RT = IN, RO = OUT, NU = 3;
     const std::vector<int>& bs3 = ins;
     const std::vector<int>& wts3 = outs;
@@ -233,10 +235,19 @@ bool fused_schedule(const std::vector<int>& ins, int IN, const std::vector<int>&
                       int(m_stage) << 8 | int(fl_prev) << 9 | int(red_prev) << 10 | (tnext % NU) << 11 |
                       (nfw & 1) << 13 | fl_slot << 14 | red_slot << 15 | (nred & 1) << 16 | (tprod & 1) << 17 |
                       (tprod % NU) << 18 | (tstage & 1) << 20;
-        // column-role events per step j = 0, 1: entry, retirement, plane processed
-        int ev = 0;
-        for (int j = 0; j < 2; ++j)
+        // column-role events per step j = 0, 1: entry, retirement, plane processed;
+        // ring slots of the entry and the retirement; and, per processed plane, the
+        // ring offsets: after e entries and r retirements window position s sits in
+        // slots (e + s) mod IN and (r + s) mod OUT
+        const int e_before = tnext - bs3[k0], r_before = obase - wts3[k0];
+        int ev = (e_before % IN) << 8 | (r_before % OUT) << 12;
+        for (int j = 0; j < 2; ++j) {
             ev |= (int(in_at == j) | int(out_at == j) << 1 | int(nv > j) << 2) << (3 * j);
+            if (rot && nv > j) {
+                (*rot)[2 * (k + j)] = (e_before + int(c_in && in_at <= j)) % IN;
+                (*rot)[2 * (k + j) + 1] = (r_before + int(c_out && out_at <= j)) % OUT;
+            }
+        }
         const int cn0 = std::min(k + nv, k1 - 1), cn1 = std::min(k + nv + 1, k1 - 1);
         out.insert(out.end(), {f, k, red_i3, tstage, ev, (std::min(k, k1 - 1) - k0) * CZ, cn0, cn1});
         // advance
@@ -376,6 +387,7 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
         fh.zchunk = choose_zchunk(nq3, fh.ntile[0] * fh.ntile[1], slots, p);
     }
     fh.sched.clear();
+    fh.rotT.assign(2 * (size_t)nq3, -1);
     fh.sched_off.clear();
     fh.schedT.clear();
     fh.schedT_off.clear();
@@ -383,8 +395,23 @@ bool build_fused_tables(const wqfd::Space1D* sp, int p, FusedHost& fh) {
         const int k1 = std::min(nq3, k0 + fh.zchunk);
         fh.sched_off.push_back((int)(fh.sched.size() / wqfd::FUSED_REC));
         fh.schedT_off.push_back((int)(fh.schedT.size() / wqfd::FUSED_REC));
-        if (!fused_schedule(fh.bs3, RT, fh.wts3, RO, n3, k0, k1, CZ, fh.sched)) return false;
-        if (!fused_schedule(fh.wts3, RO, fh.bs3, RT, n3, k0, k1, CZ, fh.schedT)) return false;
+        if (!fused_schedule(fh.bs3, RT, fh.wts3, RO, n3, k0, k1, CZ, fh.sched, nullptr)) return false;
+        if (!fused_schedule(fh.wts3, RO, fh.bs3, RT, n3, k0, k1, CZ, fh.schedT, &fh.rotT)) return false;
+    }
+    // transposed kernel's rows: the W rows multiply its input ring, the B rows its output ring
+    fh.czT = fh.cz;
+    if (p >= wqfd::FUSED_RING_MIN_P) {
+        for (int x : fh.rotT)
+            if (x < 0) return false;                  // a plane no range processed
+        for (int k = 0; k < nq3; ++k) {
+            const double* c = &fh.cz[(size_t)k * CZ];
+            double* cT = &fh.czT[(size_t)k * CZ];
+            const int wT = fh.rotT[2 * k], bT = fh.rotT[2 * k + 1];
+            for (int d = 0; d < 2; ++d)
+                for (int s = 0; s < RT; ++s) cT[d * RT + (bT + s) % RT] = c[d * RT + s];
+            for (int v = 0; v < 4; ++v)
+                for (int s = 0; s < RO; ++s) cT[2 * RT + v * RO + (wT + s) % RO] = c[2 * RT + v * RO + s];
+        }
     }
     fh.sched_off.push_back((int)(fh.sched.size() / wqfd::FUSED_REC));
     fh.schedT_off.push_back((int)(fh.schedT.size() / wqfd::FUSED_REC));
@@ -474,7 +501,8 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
     FusedHost fh;
     const bool fused_ok = build_fused_tables(sp, p, fh) && !std::getenv("WQFD_STAGED");
     size_t f_tiles64[2] = {0, 0}, f_tiles32[2] = {0, 0}, f_J[2] = {0, 0}, f_I[2] = {0, 0}, f_band[2] = {0, 0};
-    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_sched = 0, f_soff = 0, f_schedT = 0, f_soffT = 0;
+    size_t f_bs3 = 0, f_wts3 = 0, f_cz64 = 0, f_cz32 = 0, f_czT64 = 0, f_czT32 = 0, f_sched = 0, f_soff = 0,
+           f_schedT = 0, f_soffT = 0;
     if (fused_ok) {
         for (int l = 0; l < 2; ++l) {
             f_tiles64[l] = pk.add(fh.tiles[l].data(), fh.tiles[l].size() * 8);
@@ -489,6 +517,9 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
         f_cz64 = pk.add(fh.cz.data(), fh.cz.size() * 8);
         std::vector<float> c32(fh.cz.begin(), fh.cz.end());
         f_cz32 = pk.add(c32.data(), c32.size() * 4);
+        f_czT64 = pk.add(fh.czT.data(), fh.czT.size() * 8);
+        std::vector<float> cT32(fh.czT.begin(), fh.czT.end());
+        f_czT32 = pk.add(cT32.data(), cT32.size() * 4);
         f_sched = pk.add(fh.sched.data(), fh.sched.size() * sizeof(int));
         f_soff = pk.add(fh.sched_off.data(), fh.sched_off.size() * sizeof(int));
         f_schedT = pk.add(fh.schedT.data(), fh.schedT.size() * sizeof(int));
@@ -563,7 +594,7 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
         }
     }
     if (fused_ok) {
-        auto fill = [&](auto& fz, size_t ot0, size_t ot1, size_t ocz, auto* Cp) {
+        auto fill = [&](auto& fz, size_t ot0, size_t ot1, size_t ocz, size_t oczT, auto* Cp) {
             using T = std::remove_pointer_t<decltype(Cp)>;
             fz.C = Cp;
             fz.n1 = o.n[0];
@@ -584,6 +615,7 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
             fz.bs3 = reinterpret_cast<const int*>(tb + f_bs3);
             fz.wts3 = reinterpret_cast<const int*>(tb + f_wts3);
             fz.cz = reinterpret_cast<const T*>(tb + ocz);
+            fz.czT = reinterpret_cast<const T*>(tb + oczT);
             fz.ntx = fh.ntile[0];
             fz.nty = fh.ntile[1];
             fz.zchunk = fh.zchunk;
@@ -592,8 +624,8 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
             fz.schedT = reinterpret_cast<const int*>(tb + f_schedT);
             fz.schedT_off = reinterpret_cast<const int*>(tb + f_soffT);
         };
-        fill(o.fz64, f_tiles64[0], f_tiles64[1], f_cz64, o.C64);
-        fill(o.fz32, f_tiles32[0], f_tiles32[1], f_cz32, o.C32);
+        fill(o.fz64, f_tiles64[0], f_tiles64[1], f_cz64, f_czT64, o.C64);
+        fill(o.fz32, f_tiles32[0], f_tiles32[1], f_cz32, f_czT32, o.C32);
         o.fused = true;
     }
     HIP_TRY(wqfd::launch_set_coef(o, k_kind, K_q, s), "set_coef");

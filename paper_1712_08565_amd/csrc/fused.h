@@ -8,6 +8,11 @@
 namespace wqfd {
 
 constexpr int FUSED_MAX_Z = 64;   // longest z range of one workgroup of the fused apply
+// From this degree the transposed kernel keeps its z windows as fixed register
+// rings (czT then holds every plane's rows in ring slot order; below it the
+// windows shift and czT equals cz).  The shifts cost about as much as the ring
+// bookkeeping, but from p = 6 on the shifted form spills registers.
+constexpr int FUSED_RING_MIN_P = 6;
 
 // Arguments of the fused apply.  Dense 16 x 16 blocks per 16-point tile:
 // tilesX[t][6][16][16] (x direction) and tilesY (y direction), in the order
@@ -15,7 +20,8 @@ constexpr int FUSED_MAX_Z = 64;   // longest z range of one workgroup of the fus
 // j = DOF offset from JX[t]) and W_v[i][q] for v = 0..3 (i = DOF offset from
 // IX[t]).  In z the banded factors per quadrature plane k: trial window start
 // bs3[k], test window start wts3[k] and cz[k][2(p+1) + 4(p+2)] = B3 row,
-// B-dot3 row (p+1 each) and the four W3^v columns (p+2 each).
+// B-dot3 row (p+1 each) and the four W3^v columns (p+2 each); czT the same rows
+// for the transposed kernel (in ring slot order from FUSED_RING_MIN_P on).
 template <typename T>
 struct FusedArgs {
     const T* v = nullptr;
@@ -35,6 +41,7 @@ struct FusedArgs {
     const int* bs3 = nullptr;
     const int* wts3 = nullptr;
     const T* cz = nullptr;
+    const T* czT = nullptr;
     int ntx = 0, nty = 0, zchunk = 0;
     // interval schedule: records of FUSED_REC ints per interval (see FusedSched),
     // z range r uses records sched_off[r] .. sched_off[r + 1] - 1
@@ -55,7 +62,9 @@ struct FusedArgs {
 // 15 partial slot reduced; 16 partial slot written; 17 V slot read; 18-19 U
 // slot written; 20 V slot written.  The column role reads its events already
 // split by step: ev bits 3j, 3j + 1, 3j + 2 = window entry, retirement, plane
-// k + j processed, at step j = 0, 1; czo = (k - k0) CZ, the offset of plane k's
+// k + j processed, at step j = 0, 1; bits 8-11 and 12-15 = the ring slot the
+// interval's entry fills and the slot its retirement empties (entry e fills slot
+// e mod IN, retirement r empties slot r mod OUT); czo = (k - k0) CZ, the offset of plane k's
 // z coefficients in the range's table; cnext0/1 = the planes (clamped to the
 // range) whose coefficients are loaded for the next interval.
 struct FusedSched {

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "buffer.h"
 #include "device.h"
@@ -66,6 +67,25 @@ struct MF<float> {
     __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int drow(int kb, int v) { return 4 * kb + v; }
 };
+
+// Calls f(std::integral_constant<int, i>) for a wave-uniform i in [LO, HI) by a
+// binary tree of scalar branches, so that f touches one fixed element of a
+// register array.  (A run-time index into such an array makes the compiler
+// place it in scratch memory or select over every element; the empty volatile
+// asm keeps each leaf a branch target instead of a select.)
+template <int LO, int HI, typename F>
+__device__ __forceinline__ void slot_dispatch(int i, F&& f) {
+    if constexpr (HI - LO == 1) {
+        f(std::integral_constant<int, LO>{});
+        asm volatile("");
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (i < MID)
+            slot_dispatch<LO, MID>(i, f);
+        else
+            slot_dispatch<MID, HI>(i, f);
+    }
+}
 
 // 16x16x16 product accumulated into c.  A[m][k] = At[m][k]; B[k][n] = Bt[k][n]
 // (BT = false) or Bt[n][k] (BT = true).
@@ -113,7 +133,7 @@ __device__ inline const T* setup_src(const FusedArgs<T>& a, int tl, int t1, int 
 
 template <typename T, int CZ>
 __device__ inline void setup_load(SetupRegs<T, CZ>& su, const FusedArgs<T>& a, int tid, int t1, int t2, int k0,
-                                  int k1) {
+                                  int k1, const T* cz) {
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int idx = tid + 1024 * i;
@@ -123,7 +143,7 @@ __device__ inline void setup_load(SetupRegs<T, CZ>& su, const FusedArgs<T>& a, i
 #pragma unroll
     for (int i = 0; i < SetupRegs<T, CZ>::ZL; ++i) {
         const int idx = tid + 1024 * i;
-        su.zv[i] = idx < nz ? a.cz[(size_t)k0 * CZ + idx] : T(0);
+        su.zv[i] = idx < nz ? cz[(size_t)k0 * CZ + idx] : T(0);
     }
 }
 
@@ -197,7 +217,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
     // coefficient blocks of this tile and z coefficients: loads issued here, LDS
     // written just before the first barrier
     SetupRegs<T, CZ> su;
-    setup_load(su, a, tid, t1, t2, k0, k1);
+    setup_load(su, a, tid, t1, t2, k0, k1, a.cz);
     const int r0 = a.sched_off[zc], nrec = a.sched_off[zc + 1] - r0;
     // the range's interval records, one per lane (at most 64, checked on the
     // host); interval r's fields are read with readlane into scalar registers
@@ -493,6 +513,10 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_fused_kernel(FusedArgs<T> a)
 //     B3^(b3)T phi_beta into a ring of the p+1 output planes it touches;
 //   retired output planes (3 fields): x and y products with the transposed B
 //     factors (fields x and z share B2 and are summed before it) and atomics.
+// From p = FUSED_RING_MIN_P the column waves' windows are fixed register rings
+// (an entering plane is written into its slot, a retired slot is emptied in
+// place, slots from the interval records and z rows stored in slot order):
+// shifting them costs about the same issue time, but spills registers there.
 // Operands with transposed LDS reads use the accumulator row mapping as K
 // index, as in the forward kernel.
 template <typename T, int P, bool MASS>
@@ -501,6 +525,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     constexpr int RO = P + 2;              // input window (DOF planes, W band)
     constexpr int CZ = 2 * RT + 4 * RO;    // z coefficients per quadrature plane
     constexpr int NU = 3;                  // input planes in flight
+    constexpr bool RING = P >= FUSED_RING_MIN_P;   // windows as fixed register rings
     __shared__ T sCoef[12][BLK];           // 0,1 B1t_d  2,3 B2t_d  4..7 W1t_v  8..11 W2t_v
     __shared__ T sV[2][BLK];               // staged planes of v (input block IX, IY)
     __shared__ T sU[NU][9][BLK];           // Y_f of produced planes
@@ -533,7 +558,7 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
     const int J2 = __builtin_amdgcn_readfirstlane(a.JY[t2]), I2 = __builtin_amdgcn_readfirstlane(a.IY[t2]);
 
     SetupRegs<T, CZ> su;
-    setup_load(su, a, tid, t1, t2, k0, k1);
+    setup_load(su, a, tid, t1, t2, k0, k1, a.czT);
     const int r0 = a.schedT_off[zc], nrec = a.schedT_off[zc + 1] - r0;
     // the range's interval records, one per lane (at most 64, checked on the
     // host); interval r's fields are read with readlane into scalar registers
@@ -733,22 +758,41 @@ __global__ __launch_bounds__(1024, 1) void wq_apply_T_fused_kernel(FusedArgs<T> 
             const int fl = __builtin_amdgcn_readlane(Rf, r), ev = __builtin_amdgcn_readlane(Rev, r);
             const int czo = __builtin_amdgcn_readlane(Rczo, r), cn0 = __builtin_amdgcn_readlane(Rc0, r),
                       cn1 = __builtin_amdgcn_readlane(Rc1, r);
+            const int es = (ev >> 8) & 15, rs = (ev >> 12) & 15;    // ring slots of the entry / retirement
+            const int el = q2l * LD + q1l;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 if ((ev >> (3 * j)) & 1) {                       // window entry
                     const int us = (fl >> 11) & 3;
+                    if constexpr (RING) {
+                        const T y0 = sU[us][beta][el], y1 = sU[us][3 + beta][el], y2 = sU[us][6 + beta][el];
+                        slot_dispatch<0, RO>(es, [&](auto c) {
+                            Yw[0][c] = y0;
+                            Yw[1][c] = y1;
+                            Yw[2][c] = y2;
+                        });
+                    } else {
 #pragma unroll
-                    for (int al = 0; al < 3; ++al) {
+                        for (int al = 0; al < 3; ++al) {
 #pragma unroll
-                        for (int s = 0; s < RO - 1; ++s) Yw[al][s] = Yw[al][s + 1];
-                        Yw[al][RO - 1] = sU[us][3 * al + beta][q2l * LD + q1l];
+                            for (int s = 0; s < RO - 1; ++s) Yw[al][s] = Yw[al][s + 1];
+                            Yw[al][RO - 1] = sU[us][3 * al + beta][el];
+                        }
                     }
                 }
                 if ((ev >> (3 * j + 1)) & 1) {                   // retirement
-                    if ((fl >> 6) & 1) sP[(fl >> 13) & 1][beta][q2l * LD + q1l] = orng[0];
+                    if constexpr (RING) {
+                        if ((fl >> 6) & 1) {
+                            const int ps = (fl >> 13) & 1;
+                            slot_dispatch<0, RT>(rs, [&](auto c) { sP[ps][beta][el] = orng[c]; });
+                        }
+                        slot_dispatch<0, RT>(rs, [&](auto c) { orng[c] = T(0); });
+                    } else {
+                        if ((fl >> 6) & 1) sP[(fl >> 13) & 1][beta][el] = orng[0];
 #pragma unroll
-                    for (int s = 0; s < RT - 1; ++s) orng[s] = orng[s + 1];
-                    orng[RT - 1] = T(0);
+                        for (int s = 0; s < RT - 1; ++s) orng[s] = orng[s + 1];
+                        orng[RT - 1] = T(0);
+                    }
                 }
                 if ((ev >> (3 * j + 2)) & 1) valu_plane(czo + j * CZ, Cs[j]);
                 cload3(Cs[j], j ? cn1 : cn0);
@@ -792,7 +836,7 @@ hipError_t launch_p(const FusedArgs<T>& a, hipStream_t s) {
 
 template <typename T, int P>
 hipError_t launch_tp(const FusedArgs<T>& a, hipStream_t s) {
-    if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.schedT || !a.schedT_off) return hipErrorInvalidValue;
+    if (a.zchunk <= 0 || a.zchunk > kMaxZ || !a.schedT || !a.schedT_off || !a.czT) return hipErrorInvalidValue;
     const int nzc = (a.nq3 + a.zchunk - 1) / a.zchunk;
     if (a.Cm)
         hipLaunchKernelGGL((wq_apply_T_fused_kernel<T, P, true>), dim3(a.ntx * a.nty * nzc), dim3(1024), 0, s, a);
