@@ -90,6 +90,33 @@ def test_autograd_gradient_matches_oracle(name):
     assert eu <= 1e-10 and eK <= 1e-10 and ef <= 1e-10, (f"{eu:.3e}", f"{eK:.3e}", f"{ef:.3e}")
 
 
+def test_autograd_alpha_gradient_matches_oracle():
+    """dJ/dalpha through the autograd wrapper (reaction term set from alpha_q)
+    against the oracle's adjoint gradient with direct solves: <= 1e-10."""
+    import torch
+    from paper_1712_08565_amd import autograd, problem
+    wl, dp, pr = setup("ring7_p4_kappa")
+    alpha_fn = synth.alpha_field(10.0 * wl.n_el ** 2)
+    alpha_q = alpha_fn(dp.Fq.t()).contiguous().requires_grad_(True)
+    problem.set_reaction(dp, alpha_fn)                   # shifted FD for the solves
+    try:
+        u_obs = 0.01 * synth.random_vector(pr.N, 48)
+        u = autograd.solve(dp.A, dp.P, dp.K_q, dp.f_q, rtol=1e-13, alpha_q=alpha_q)
+        J = 0.5 * torch.sum((u - dev(u_obs)) ** 2)
+        J.backward()
+        pr.set_alpha(alpha_fn(pr.F))
+        A = pr.assemble().tocsc()
+        uo = spla.spsolve(A, pr.rhs_from(wl.f()))
+        lam = spla.spsolve(A.T.tocsc(), uo - u_obs)
+        eu = rel(host(u), uo)
+        ea = rel(host(alpha_q.grad), adjoint.grad_alpha(pr, lam, uo))
+        print(f"[adjoint alpha] u {eu:.2e}  dJ/dalpha {ea:.2e}", flush=True)
+        assert eu <= 1e-10 and ea <= 1e-10, (f"{eu:.3e}", f"{ea:.3e}")
+    finally:
+        pr.set_alpha(None)
+        problem.set_reaction(dp, None)
+
+
 def _J(autograd, dp, K_q, f_q, u_obs, rtol):
     import torch
     with torch.no_grad():
