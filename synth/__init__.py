@@ -319,6 +319,8 @@ def _mk() -> Dict[str, Workload]:
     w["twist6_p6"] = Workload("twist6_p6", 6, 6, "twist", 0.0, "sym6", "smooth")
     w["twist5_p4"] = Workload("twist5_p4", 5, 4, "twist", 0.0, "sym6", "smooth")
     w["ring6_p8"] = Workload("ring6_p8", 6, 8, "ring", 0.02, "identity", "paper")
+    # the highest degree of the paper's study (staged kernels)
+    w["ring5_p10"] = Workload("ring5_p10", 5, 10, "ring", 0.02, "identity", "paper")
     # highest degree of the fused kernels: one tile, and several tiles with a ragged last one (n_q = 51)
     w["ring6_p7"] = Workload("ring6_p7", 6, 7, "ring", 0.02, "identity", "paper")
     w["ring18_p7"] = Workload("ring18_p7", 18, 7, "ring", 0.02, "identity", "paper")

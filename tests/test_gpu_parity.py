@@ -19,7 +19,7 @@ from oracle.operator import Problem
 pytestmark = pytest.mark.gpu
 
 APPLY_CASES = ["cube12_p3", "ring8_p2", "ring8_p3", "ring8_p4", "ring8_p5", "ring8_p6", "ring7_p4_kappa",
-               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7"]
+               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7", "ring5_p10"]
 
 _cache = {}
 
@@ -90,6 +90,25 @@ def test_apply_acc_parity(name):
     e2 = rel(host(w), w0 + 2 * Kv)
     print(f"[apply acc] {name}: {e1:.2e}, {e2:.2e}")
     assert e1 <= 1e-12 and e2 <= 1e-12, (e1, e2)
+
+
+def test_repeated_applies_and_solves_agree():
+    """Run-to-run agreement: the fused apply adds overlapping tiles into w with
+    FP64 atomics, so repeated applies may differ only in the last bits
+    (<= 1e-14 of max |w|); repeated solves take the same number of iterations
+    and agree to the solver tolerance."""
+    import torch
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup("ring20_p6")
+    v = dev(synth.random_vector(pr.N, 55))
+    ws = [wqfd.wq_apply(dp.A, v).clone() for _ in range(5)]
+    torch.cuda.synchronize()
+    d = max(float((w - ws[0]).abs().max()) for w in ws[1:]) / float(ws[0].abs().max())
+    xs = [wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-12) for _ in range(3)]
+    its = {it for _, it, _ in xs}
+    dx = max(float((x - xs[0][0]).norm() / xs[0][0].norm()) for x, _, _ in xs[1:])
+    print(f"[repeat] applies {d:.1e}, solves: iterations {sorted(its)}, spread {dx:.1e}")
+    assert d <= 1e-14 and len(its) == 1 and dx <= 1e-11, (d, its, dx)
 
 
 def test_apply_acc_refused_without_fused_kernels():

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import bspline as obs
 from oracle import wq as owq
 from oracle.geometry import map_and_jacobian
 from oracle.operator import Problem
@@ -70,6 +71,25 @@ def test_space_1d_high_degree_weights_agree(p):
         for b in (0, 1):
             ref = S.W[(a, b)]
             assert np.abs(W[2 * a + b] - ref).max() <= 5e-11 * np.abs(ref).max(), (a, b)
+
+
+@pytest.mark.parametrize("p", [9, 10])
+def test_space_1d_stable_to_degree_10(p):
+    """No instability up to p = 10 (the paper's remark on degrees to 10): the
+    library's weights meet the exactness conditions against the oracle's 1D
+    Galerkin integrals (pinned by adaptive quadrature) for every trial function,
+    and stay close to the oracle's own minimum-norm weights."""
+    k = synth.uniform_knots(8, p)
+    xq, B, W = space_1d(p, k)
+    S = owq.Space1D(k, p)
+    m = len(k) - p - 1
+    for a in (0, 1):
+        for b in (0, 1):
+            G = obs.galerkin_1d(k, p, a, b)[1:m - 1]                    # interior test rows, all trial columns
+            Bf = obs.basis_matrix(k, p, xq, b)                         # [nq][m]
+            res = np.abs(W[2 * a + b] @ Bf - G).max()
+            assert res <= 1e-9 * np.abs(G).max(), (a, b, res)
+            assert np.abs(W[2 * a + b] - S.W[(a, b)]).max() <= 1e-8 * np.abs(S.W[(a, b)]).max(), (a, b)
 
 
 @pytest.mark.parametrize("p", [2, 4, 6])

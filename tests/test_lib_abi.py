@@ -93,3 +93,50 @@ def test_size_query_needs_no_device():
                       None) == _lib.WQ_EINVAL
     assert L.wq_setup(3, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 8, None, 0, C.byref(need), None,
                       None) == _lib.WQ_EINVAL
+
+
+def test_small_or_misaligned_workspace_is_refused():
+    """WQ_ENOMEM for a workspace below the size query, WQ_EINVAL for one that is
+    not 256-byte aligned; both are decided before the workspace is touched (the
+    stand-in address below is never dereferenced)."""
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    wl = synth.workload("cube5_p2")
+    ks, nk, kp = _setup_args(wl.p, wl.knots())
+    ctrl = wl.ctrl()
+    need = C.c_size_t(0)
+    h = C.c_void_p(0)
+    assert L.wq_setup(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 1, None, 0, C.byref(need), None,
+                      None) == 0
+    fake = 1 << 30
+    assert L.wq_setup(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 1, C.c_void_p(fake), need.value - 1,
+                      None, None, C.byref(h)) == _lib.WQ_ENOMEM
+    assert L.wq_setup(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 1, C.c_void_p(fake + 8), need.value,
+                      None, None, C.byref(h)) == _lib.WQ_EINVAL
+    assert L.fd_setup(wl.p, nk, kp, 1, None, 0, C.byref(need), None, None) == 0
+    assert L.fd_setup(wl.p, nk, kp, 1, C.c_void_p(fake), need.value - 1, None, None, C.byref(h)) == _lib.WQ_ENOMEM
+    assert L.fd_setup(wl.p, nk, kp, 1, C.c_void_p(fake + 8), need.value, None, None, C.byref(h)) == _lib.WQ_EINVAL
+    assert not h.value
+
+
+def test_memory_is_order_N_independent_of_p():
+    """The operator's memory is a fixed number of bytes per quadrature point and
+    does not grow with p per degree of freedom (the memory claims of Sections
+    3.1-3.2), while an assembled matrix would need about 12 (2p+1)^3 bytes per
+    degree of freedom."""
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    per_point, per_dof = [], []
+    for p in range(2, 11):
+        k = synth.uniform_knots(16, p)
+        ks, nk, kp = _setup_args(p, (k, k, k))
+        ctrl = synth.control_net("identity", (k, k, k), p)
+        need = C.c_size_t(0)
+        assert L.wq_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), 0, None, 1, None, 0, C.byref(need), None,
+                          None) == 0
+        n, nq = 16 + p - 2, 2 * 16 + 2 * p + 1
+        per_point.append(need.value / nq ** 3)
+        per_dof.append(need.value / n ** 3)
+    assert max(per_point) / min(per_point) < 1.02, per_point
+    assert max(per_dof[1:]) <= per_dof[0], per_dof          # no growth with p
+    assert per_dof[-1] < 0.05 * 12 * 21 ** 3                 # 2.6% of an assembled matrix at p = 10
