@@ -84,6 +84,11 @@ enum {
  * weights: minimum-norm solutions of the exactness conditions for all m trial
  * B-splines (eqs. exactness1d, weights-support, exactness_K).
  * C = det(J) J^{-1} K J^{-T} with J = dF/dxi (eq. C).  Synchronises `s`.
+ * Deterministic mode: with the environment variable WQFD_STAGED set at set-up
+ * the operator uses the staged kernels only (one writer per output, no
+ * atomics), so its applies repeat bit for bit; they are slower, and
+ * wq_apply_acc is not available.  Otherwise applies for p <= 7 run the fused
+ * kernels, whose atomic adds make repeated results differ in the last bits.
  * Errors: WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR, WQ_ENOMEM, WQ_EHIP.
  * ------------------------------------------------------------------------ */
 int wq_setup(int p, const int32_t nknots[3], const double* const knots[3],

@@ -1038,6 +1038,7 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     if (rc) return fail(rc, err);
     *outer = 0;
     *inner_total = 0;
+    if (!std::isfinite(nb)) return fail(WQ_ENONFINITE, "non-finite value in the right-hand side");
     if (nb == 0.0) {
         HIP_TRY(hipMemsetAsync(x, 0, N * 8, s), "zero x");
         *relres = 0;
@@ -1054,8 +1055,10 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     rc = residual();
     if (rc) return rc;
     *relres = nr / nb;
-    while (nr / nb > rtol && *outer < max_outer) {
+    // (a NaN residual compares false with everything: test it before the stopping test)
+    while (true) {
         if (!std::isfinite(nr)) return fail(WQ_ENONFINITE, "non-finite residual in iterative refinement");
+        if (nr / nb <= rtol || *outer >= max_outer) break;
         HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
         int it = 0;
         double rel = 0;

@@ -1,0 +1,97 @@
+"""Failure handling and the deterministic mode, forced from the host (no kernel
+is made to fault): the iteration limit (WQ_ENOCONV, last iterate returned), a
+non-finite right-hand side (WQ_ENONFINITE, in BiCGStab and in the refinement
+loop), a zero right-hand side (x = 0 at once), and operators built with
+WQFD_STAGED=1, whose staged kernels give one writer per output and so
+bit-for-bit repeatable applies."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.operator import Problem
+
+pytestmark = pytest.mark.gpu
+
+_cache = {}
+
+
+def setup(name="ring8_p3"):
+    if name in _cache:
+        return _cache[name]
+    import torch
+    from paper_1712_08565_amd import problem
+    from paper_1712_08565_amd.wqfd import WQ_F32, WQ_F64
+    wl = synth.workload(name)
+    print(f"[failure] setup {name}", flush=True)
+    dp = problem.build(wl, WQ_F64 | WQ_F32, WQ_F64 | WQ_F32)
+    torch.cuda.synchronize()
+    _cache[name] = (wl, dp)
+    return _cache[name]
+
+
+def test_iteration_limit_returns_last_iterate():
+    import torch
+    from paper_1712_08565_amd import wqfd
+    from paper_1712_08565_amd._lib import WQ_ENOCONV
+    wl, dp = setup()
+    x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-12, maxit=2, raise_on_noconv=False)
+    assert it == 2 and 1e-12 < res < 1.0 and bool(torch.isfinite(x).all()), (it, res)
+    with pytest.raises(wqfd.WQError) as e:
+        wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-12, maxit=2)
+    assert e.value.code == WQ_ENOCONV and "iteration limit" in str(e.value)
+
+
+def test_non_finite_right_hand_side_is_reported():
+    from paper_1712_08565_amd import wqfd
+    from paper_1712_08565_amd._lib import WQ_ENONFINITE
+    from paper_1712_08565_amd.wqfd import WQ_F32
+    wl, dp = setup()
+    b = dp.b.clone()
+    b[7] = float("nan")
+    with pytest.raises(wqfd.WQError) as e:
+        wqfd.krylov_solve(dp.A, dp.P, b)
+    assert e.value.code == WQ_ENONFINITE
+    b[7] = float("inf")
+    with pytest.raises(wqfd.WQError) as e:
+        wqfd.ir_solve(dp.A, dp.P, b, fd_prec=WQ_F32)
+    assert e.value.code == WQ_ENONFINITE
+
+
+def test_zero_right_hand_side_gives_zero():
+    import torch
+    from paper_1712_08565_amd import wqfd
+    wl, dp = setup()
+    x0 = torch.ones_like(dp.b)
+    x, it, res = wqfd.krylov_solve(dp.A, dp.P, torch.zeros_like(dp.b), x=x0)
+    torch.cuda.synchronize()
+    assert it == 0 and float(x.abs().max()) == 0.0, (it, res)
+
+
+def test_staged_mode_is_bitwise_repeatable():
+    """WQFD_STAGED=1 at set-up selects the staged kernels for that operator:
+    repeated applies agree bit for bit and match the fused operator to rounding."""
+    import torch
+    from paper_1712_08565_amd import problem, wqfd
+    from paper_1712_08565_amd.wqfd import WQ_F64
+    wl = synth.workload("ring8_p6")
+    os.environ["WQFD_STAGED"] = "1"
+    try:
+        staged = problem.build(wl, WQ_F64, WQ_F64)
+    finally:
+        del os.environ["WQFD_STAGED"]
+    fused = problem.build(wl, WQ_F64, WQ_F64)
+    with pytest.raises(wqfd.WQError):                    # the accumulating call needs the fused kernels
+        wqfd.wq_apply_acc(staged.A, staged.b, torch.zeros_like(staged.b))
+    v = torch.as_tensor(synth.random_vector(staged.A.N, 57), device="cuda")
+    ws = [wqfd.wq_apply(staged.A, v).clone() for _ in range(3)]
+    wts = [wqfd.wq_apply_T(staged.A, v).clone() for _ in range(3)]
+    wf = wqfd.wq_apply(fused.A, v)
+    torch.cuda.synchronize()
+    assert all(torch.equal(ws[0], w) for w in ws[1:]) and all(torch.equal(wts[0], w) for w in wts[1:])
+    d = float((ws[0] - wf).norm() / wf.norm())
+    pr = Problem(wl.knots(), wl.p, wl.ctrl())
+    e = float(np.linalg.norm(ws[0].cpu().numpy() - pr.apply(v.cpu().numpy())) / np.linalg.norm(pr.apply(v.cpu().numpy())))
+    print(f"[staged] fused vs staged {d:.1e}, staged vs oracle {e:.1e}")
+    assert d <= 1e-14 and e <= 1e-12, (d, e)
