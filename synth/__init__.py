@@ -103,7 +103,11 @@ def control_net(kind: str, knots3, p: int, noise: float = 0.0, seed: int = 0,
 
     kind: 'identity' (unit cube), 'ring' (thick quarter ring extruded in z),
     'shear' (affine, non-symmetric Jacobian), 'twist' (cube twisted about the
-    vertical axis, up to 30 degrees at the top).
+    vertical axis, up to 30 degrees at the top); these place the control points
+    at the images of the Greville abscissae (second order in h).  'ring_interp'
+    is the ring map interpolated at the Greville abscissae by the spline of the
+    same knots (scipy.interpolate.make_interp_spline along each axis), accurate
+    to order p + 1 in h.
     ``noise`` adds 0.02-style smooth perturbations that vanish on the boundary:
     eta_c(g) = sum_{a,b,c in {1,2}} r sin(a pi g1) sin(b pi g2) sin(c pi g3) / 8,
     r ~ U(-1, 1) from ``seed``.
@@ -114,6 +118,13 @@ def control_net(kind: str, knots3, p: int, noise: float = 0.0, seed: int = 0,
         X = _map_identity(G1, G2, G3)
     elif kind == "ring":
         X = _map_ring(G1, G2, G3)
+    elif kind == "ring_interp":
+        from scipy.interpolate import make_interp_spline
+        V = np.stack(_map_ring(G1, G2, G3), -1)           # values at the Greville grid [k3, k2, k1, 3]
+        for axis, (k, gl) in zip((2, 1, 0), zip(knots3, g)):
+            c = make_interp_spline(gl, V, k=p, t=np.asarray(k, dtype=np.float64), axis=axis).c
+            V = np.moveaxis(c, 0, axis)                    # (the coefficients come with that axis first)
+        X = (V[..., 0], V[..., 1], V[..., 2])
     elif kind == "shear":
         X = _map_shear(G1, G2, G3)
     elif kind == "twist":

@@ -577,3 +577,21 @@ def test_wq_operator_on_curved_map_from_its_definition(p, ne):
             Bk = np.kron(B[ab[2][1]], np.kron(B[ab[1][1]], B[ab[0][1]]))
             Kbad = Kbad + Wk @ (C[..., al, be].ravel()[:, None] * Bk)
     assert np.abs(Kt - Kbad).max() > 1e-2 * np.abs(K).max()
+
+
+def test_interpolated_ring_geometry_converges_at_order_p_plus_1():
+    """synth's 'ring_interp' control net reproduces the ring map to order p + 1
+    (evaluated with scipy BSpline), the Greville-image net 'ring' only to order 2."""
+    x = np.random.default_rng(0).uniform(0, 1, 300)
+    ex = np.stack(synth._map_ring(x, x, x), -1)
+    p = 3
+    err = {}
+    for kind in ("ring_interp", "ring"):
+        for ne in (8, 16):
+            k = synth.uniform_knots(ne, p)
+            B = BSpline.design_matrix(x, k, p).toarray()
+            F = np.einsum("cbar,ia,ib,ic->ir", synth.control_net(kind, (k, k, k), p), B, B, B)
+            err[(kind, ne)] = np.abs(F - ex).max()
+    assert err[("ring_interp", 8)] / err[("ring_interp", 16)] > 12          # about 2^(p+1) = 16
+    assert err[("ring", 8)] / err[("ring", 16)] < 5                          # about 2^2
+    assert err[("ring_interp", 16)] < 1e-3 * err[("ring", 16)]
