@@ -37,7 +37,10 @@ which re-types the oracle's own formulas:
   stiffness on the identity cube with a constant SPD K, a symmetric operator on
   curved maps (where weighted quadrature is not), and equality with a brute-force
   element-by-element Gauss assembly whose bases and geometry come from
-  scipy.interpolate.BSpline.
+  scipy.interpolate.BSpline;
+* the H1 / L2 error integrator (Table 1's measure): zero error for a solution in
+  the spline space on a non-symmetric affine map, and the closed-form error of a
+  single perturbed coefficient.
 """
 import math
 
@@ -46,7 +49,7 @@ import pytest
 import scipy.integrate as si
 import scipy.linalg as sla
 import scipy.sparse.linalg as spla
-from scipy.interpolate import BSpline
+from scipy.interpolate import BSpline, make_interp_spline
 
 import synth
 from oracle import bspline, geometry, wq
@@ -613,3 +616,97 @@ def test_table1_coarse_levels_reproduced(ne, p):
     u, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(synth.f_paper), FD(pr.spaces).apply, tol=1e-12)
     h1 = errors(kn, p, ctrl, u, synth.u_paper)[1]
     assert rel <= 1e-12 and abs(h1 / ref - 1) < 0.25, (h1, ref)
+
+
+# ---------------------------------------------------------------- error integrator (Table 1's measure)
+def _span_integral(t, f, npts=10):
+    """Integral over [0, 1] of a piecewise polynomial with breaks at the knots t,
+    by Gauss-Legendre on every nonempty span (exact for degree < 2 npts)."""
+    x, w = np.polynomial.legendre.leggauss(npts)
+    tot = 0.0
+    for a, b in zip(t[:-1], t[1:]):
+        if b > a:
+            tot += 0.5 * (b - a) * np.sum(w * f(0.5 * (b - a) * x + 0.5 * (a + b)))
+    return tot
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_error_integrator_is_exact_on_an_affine_map(p):
+    """The relative L2 / H1-seminorm errors of Section 4 (Table 1's measure) on an
+    affine map x = A xi + c with a non-symmetric A, distinct non-uniform knots per
+    direction and a solution u = prod_l g_l(xi_l) that lies in the spline space
+    (g_l(t) = t (1 - t)(1 + a_l t), different a_l per direction): the discrete
+    u_h interpolating u has zero error, and u_h + delta b_j has the closed-form
+    errors delta |b_j| / |u| in both norms.  For functions vanishing at both ends
+    the mixed terms integral(g g') vanish, so with S = A^-1 A^-T
+        |grad u|^2 = |det A| sum_a S_aa int(g_a'^2) prod_{l != a} int(g_l^2),
+    and the same for b_j; the 1D integrals come from scipy B-splines and numpy
+    polynomials, independent of the oracle."""
+    rng = np.random.default_rng(11 + p)
+    knots3 = []
+    for ne in (3, 4, 5):
+        inner = np.sort(rng.uniform(0.1, 0.9, ne - 1))
+        knots3.append(np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)]))
+    A = np.array([[1.1, 0.35, -0.2], [0.15, 0.9, 0.3], [-0.25, 0.1, 1.3]])
+    c0 = np.array([0.3, -0.7, 2.0])
+    Ai = np.linalg.inv(A)
+    S = Ai @ Ai.T
+    avals = (0.7, -0.4, 1.3)
+    gpoly = [np.polynomial.Polynomial([0.0, 1.0, -1.0]) * np.polynomial.Polynomial([1.0, a]) for a in avals]
+
+    grev = [synth.greville(k, p) for k in knots3]
+    X1, X2, X3 = grev
+    xi = np.stack(np.meshgrid(X3, X2, X1, indexing="ij")[::-1], -1)   # [k3, k2, k1, (xi1, xi2, xi3)]
+    ctrl = xi @ A.T + c0                                              # linear precision of Greville points
+
+    coef = []
+    for l in range(3):
+        s = make_interp_spline(grev[l], gpoly[l](grev[l]), k=p, t=knots3[l])
+        assert abs(s.c[0]) < 1e-13 and abs(s.c[-1]) < 1e-13
+        coef.append(s.c[1:-1])
+    U = np.einsum("k,j,i->kji", coef[2], coef[1], coef[0]).ravel()
+
+    def u_fn(x):
+        z = (x - c0) @ Ai.T
+        return np.prod(np.stack([gpoly[l](z[..., l]) for l in range(3)], -1), -1)
+
+    def grad_fn(x):
+        z = (x - c0) @ Ai.T
+        g = np.stack([gpoly[l](z[..., l]) for l in range(3)], -1)
+        d = np.stack([gpoly[l].deriv()(z[..., l]) for l in range(3)], -1)
+        gxi = np.stack([d[..., a] * np.prod(np.delete(g, a, -1), -1) for a in range(3)], -1)
+        return gxi @ Ai                                   # A^-T grad_xi, row form
+
+    l2, h1 = errors(knots3, p, ctrl, U, u_fn, grad_fn)
+    assert l2 < 1e-13 and h1 < 1e-13
+
+    def sq(f):
+        return lambda t: f(t) ** 2
+
+    Gm = [(gpoly[l] ** 2).integ()(1.0) for l in range(3)]
+    Gd = [(gpoly[l].deriv() ** 2).integ()(1.0) for l in range(3)]
+    jl = (2, 1, 3)                                           # interior indices (x, y, z), distinct per axis
+    bm, bd = [], []
+    for l in range(3):
+        e = np.zeros(len(knots3[l]) - p - 1)
+        e[jl[l] + 1] = 1.0
+        b = BSpline(knots3[l], e, p)
+        bm.append(_span_integral(knots3[l], sq(b)))
+        bd.append(_span_integral(knots3[l], sq(b.derivative())))
+    def h1sq(m, d):
+        return sum(S[a, a] * d[a] * np.prod([m[l] for l in range(3) if l != a]) for a in range(3))
+    delta = 1e-3
+    n = [len(k) - p - 3 for k in knots3]
+    j = jl[0] + n[0] * (jl[1] + n[1] * jl[2])
+    Up = U.copy()
+    Up[j] += delta
+    l2p, h1p = errors(knots3, p, ctrl, Up, u_fn, grad_fn)
+    assert math.isclose(l2p, delta * math.sqrt(np.prod(bm) / np.prod(Gm)), rel_tol=1e-9)
+    assert math.isclose(h1p, delta * math.sqrt(h1sq(bm, bd) / h1sq(Gm, Gd)), rel_tol=1e-9)
+    # the pullback convention matters: with A^-T A^-1 in place of S the H1 figure differs
+    S_wrong = Ai.T @ Ai
+    wrong = delta * math.sqrt(sum(S_wrong[a, a] * bd[a] * np.prod([bm[l] for l in range(3) if l != a])
+                                  for a in range(3)) /
+                              sum(S_wrong[a, a] * Gd[a] * np.prod([Gm[l] for l in range(3) if l != a])
+                                  for a in range(3)))
+    assert not math.isclose(h1p, wrong, rel_tol=1e-3)
