@@ -43,6 +43,17 @@ def _need(t: torch.Tensor, dtype, numel: int, name: str):
         raise ValueError(f"{name}: need a contiguous {dtype} device tensor with {numel} entries")
 
 
+def _ws_bytes(ws: torch.Tensor, nbytes: int, name: str) -> int:
+    """Byte size of a caller-supplied workspace, checked to be device memory of at least nbytes."""
+    if not ws.is_cuda or not ws.is_contiguous() or ws.numel() * ws.element_size() < nbytes:
+        raise ValueError(f"{name}: need a contiguous device tensor of at least {nbytes} bytes")
+    return ws.numel() * ws.element_size()
+
+
+# planes of N_q doubles that K_q holds for each k_kind (layout in wq_set_coef)
+_K_PLANES = {WQ_K_IDENTITY: 0, WQ_K_SCALAR: 1, WQ_K_SYM6: 6}
+
+
 class WqOp:
     """MF-WQ operator handle (stiffness, plus the reaction term once set); owns its device workspace tensor."""
 
@@ -82,21 +93,32 @@ class FdPc:
 def wq_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, k_kind: int = WQ_K_IDENTITY,
              K_q: Optional[torch.Tensor] = None, prec_mask: int = WQ_F64, device="cuda", stream=None,
              rule: str = "wq") -> WqOp:
-    """rule "wq": weighted quadrature (wq_setup); "gauss": p + 1 Gauss points per element (wq_setup_gauss)."""
+    """rule "wq": weighted quadrature (wq_setup); "gauss": p + 1 Gauss points per element (wq_setup_gauss).
+
+    ctrl holds the control points [m3][m2][m1][3] (m_l = len(knots[l]) - p - 1); a conductivity K_q is
+    installed with wq_set_coef once the operator exists, so that its size is checked against N_q."""
     ks, nk, kp = _knots(knots)
     ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+    m = [len(k) - p - 1 for k in ks]
+    if p >= 1 and min(m) > 0 and ctrl.size != 3 * m[0] * m[1] * m[2]:
+        raise ValueError(f"ctrl: need {m[2]} x {m[1]} x {m[0]} control points of 3 coordinates, got {ctrl.size} values")
+    if k_kind not in _K_PLANES:
+        raise ValueError(f"unknown k_kind {k_kind}")
+    if k_kind != WQ_K_IDENTITY and K_q is None:
+        raise ValueError("K_q is required for this k_kind")
     need = C.c_size_t(0)
     h = C.c_void_p(0)
     L = lib()
     fn, name = {"wq": (L.wq_setup, "wq_setup"), "gauss": (L.wq_setup_gauss, "wq_setup_gauss")}[rule]
-    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, C.c_void_p(0), prec_mask, None, 0,
+    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), WQ_K_IDENTITY, C.c_void_p(0), prec_mask, None, 0,
              C.byref(need), _stream(stream), C.byref(h)), name + "(size)")
     ws = torch.empty(need.value, dtype=torch.uint8, device=device)
-    if K_q is not None:
-        K_q = K_q.contiguous()
-    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), k_kind, _p(K_q), prec_mask, _p(ws), need.value,
+    check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), WQ_K_IDENTITY, C.c_void_p(0), prec_mask, _p(ws), need.value,
              None, _stream(stream), C.byref(h)), name)
-    return WqOp(h, ws, p, prec_mask, k_kind, device)
+    op = WqOp(h, ws, p, prec_mask, WQ_K_IDENTITY, device)
+    if k_kind != WQ_K_IDENTITY:
+        wq_set_coef(op, k_kind, K_q, stream)
+    return op
 
 
 def wq_dims(op: WqOp) -> Tuple[Tuple[int, int, int], Tuple[int, int, int]]:
@@ -119,8 +141,16 @@ def wq_detj(op: WqOp, stream=None) -> torch.Tensor:
 
 
 def wq_set_coef(op: WqOp, k_kind: int, K_q: Optional[torch.Tensor] = None, stream=None):
-    if K_q is not None:
+    """Conductivity at the quadrature points: None for K = I, [N_q] for WQ_K_SCALAR, [6][N_q] for WQ_K_SYM6."""
+    if k_kind not in _K_PLANES:
+        raise ValueError(f"unknown k_kind {k_kind}")
+    if k_kind != WQ_K_IDENTITY:
+        if K_q is None:
+            raise ValueError("K_q is required for this k_kind")
         K_q = K_q.contiguous()
+        _need(K_q, torch.float64, _K_PLANES[k_kind] * op.Nq, "K_q")
+    else:
+        K_q = None
     check(lib().wq_set_coef(op.handle, k_kind, _p(K_q), _stream(stream)), "wq_set_coef")
     op.k_kind = k_kind
 
@@ -245,8 +275,9 @@ def krylov_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = 
     _need(x, torch.float64, A.N, "x")
     nb = lib().krylov_ws_bytes(A.handle)
     ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    wsb = _ws_bytes(ws, nb, "ws")
     it, rel = C.c_int(0), C.c_double(0)
-    rc = lib().krylov_solve(A.handle, P.handle, int(transpose), _p(b), _p(x), rtol, maxit, _p(ws), ws.numel(),
+    rc = lib().krylov_solve(A.handle, P.handle, int(transpose), _p(b), _p(x), rtol, maxit, _p(ws), wsb,
                             C.byref(it), C.byref(rel), _stream(stream))
     if rc != 0 and (raise_on_noconv or rc != -6):
         check(rc, "krylov_solve")
@@ -262,7 +293,8 @@ def ir_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None
     _need(x, torch.float64, A.N, "x")
     nb = lib().ir_ws_bytes(A.handle)
     ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    wsb = _ws_bytes(ws, nb, "ws")
     outer, inner, rel = C.c_int(0), C.c_int(0), C.c_double(0)
     check(lib().ir_solve(A.handle, P.handle, fd_prec, _p(b), _p(x), rtol, tau_inner, max_outer, maxit_inner, _p(ws),
-                         ws.numel(), C.byref(outer), C.byref(inner), C.byref(rel), _stream(stream)), "ir_solve")
+                         wsb, C.byref(outer), C.byref(inner), C.byref(rel), _stream(stream)), "ir_solve")
     return x, outer.value, inner.value, rel.value
