@@ -35,11 +35,14 @@ def bicgstab(A, b, M=None, tol=1e-10, maxit=1000, x0=None):
         alpha = rho / (rh @ v)
         s = r - alpha * v
         if np.linalg.norm(s) / nb <= tol:
-            x = x + alpha * ph
-            rel = np.linalg.norm(b - A(x)) / nb
+            # half step: x + alpha ph is returned only if its true residual
+            # confirms; otherwise x is left as it was and the full step below
+            # adds alpha ph (once) together with omega sh.
+            x_half = x + alpha * ph
+            rel = np.linalg.norm(b - A(x_half)) / nb
             if rel <= tol:
                 hist.append(rel)
-                return x, it, rel, hist
+                return x_half, it, rel, hist
         sh = M(s)
         t = A(sh)
         omega = (t @ s) / (t @ t)

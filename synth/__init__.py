@@ -29,6 +29,7 @@ import numpy as np
 __all__ = [
     "uniform_knots", "greville", "control_net", "Workload", "WORKLOADS",
     "workload", "random_vector", "kappa_field", "sym6_field", "alpha_field",
+    "u_sine", "grad_u_sine", "f_sine", "u_paper", "grad_u_paper", "f_paper", "f_smooth",
 ]
 
 
@@ -241,6 +242,33 @@ def u_paper(x):
     rho = x1 * x1 + x2 * x2
     k = 5.0 * math.pi
     return xp.sin(k * x1) * xp.sin(k * x2) * xp.sin(k * x3) * (rho - 1.0) * (rho - 4.0)
+
+
+def grad_u_paper(x):
+    """Gradient of u_paper in closed form, shape (..., 3).  With s_l = sin(k x_l),
+    c_l = cos(k x_l), g(rho) = (rho - 1)(rho - 4), g'(rho) = 2 rho - 5:
+    du/dx1 = k c1 s2 s3 g + s1 s2 s3 g' 2 x1, du/dx2 likewise, du/dx3 = k s1 s2 c3 g."""
+    xp = _ns(x)
+    x1, x2, x3 = x[..., 0], x[..., 1], x[..., 2]
+    k = 5.0 * math.pi
+    s1, s2, s3 = xp.sin(k * x1), xp.sin(k * x2), xp.sin(k * x3)
+    c1, c2, c3 = xp.cos(k * x1), xp.cos(k * x2), xp.cos(k * x3)
+    rho = x1 * x1 + x2 * x2
+    g = (rho - 1.0) * (rho - 4.0)
+    gp = 2.0 * rho - 5.0
+    s = s1 * s2 * s3
+    return _stack(xp, [k * c1 * s2 * s3 * g + s * gp * 2.0 * x1,
+                       k * s1 * c2 * s3 * g + s * gp * 2.0 * x2,
+                       k * s1 * s2 * c3 * g])
+
+
+def grad_u_sine(x):
+    """Gradient of u_sine, shape (..., 3)."""
+    xp = _ns(x)
+    a, b, c = (math.pi * x[..., l] for l in range(3))
+    return _stack(xp, [math.pi * xp.cos(a) * xp.sin(b) * xp.sin(c),
+                       math.pi * xp.sin(a) * xp.cos(b) * xp.sin(c),
+                       math.pi * xp.sin(a) * xp.sin(b) * xp.cos(c)])
 
 
 def f_paper(x):

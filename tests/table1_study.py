@@ -63,7 +63,7 @@ def main():
             info = f"{it} it, relres {res:.1e}, {1e3 * t:.1f} ms"
         k = synth.uniform_knots(ne, p)
         kn = (k, k, k)
-        h1 = errors(kn, p, synth.control_net(args.geometry, kn, p, 0.0, 0), x, synth.u_paper)[1]
+        h1 = errors(kn, p, synth.control_net(args.geometry, kn, p, 0.0, 0), x, synth.u_paper, synth.grad_u_paper)[1]
         col = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}.get(ne)
         ref = paper[p][col] if (p in paper and col is not None) else float("nan")
         print(f"2^-{int(np.log2(ne)):d} {p:2d} {h1:12.2e} {ref:8.1e}  {info}", flush=True)

@@ -226,7 +226,7 @@ def test_manufactured_solution_converges_at_spline_rate(p):
         # identity geometry: FD is the exact inverse (pinned below), one iteration
         u, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(synth.f_sine), FD(pr.spaces).apply, tol=1e-13)
         assert it == 1
-        h1s.append(errors(kn, p, ctrl, u, synth.u_sine)[1])
+        h1s.append(errors(kn, p, ctrl, u, synth.u_sine, synth.grad_u_sine)[1])
     r = _rates(h1s)[-1]
     assert abs(r - p) < 0.3
     assert abs(r - paper_rate) < 0.4
@@ -247,6 +247,12 @@ def _shear_problem(ne, p):
     def u(x):
         return uhat(x @ Ai.T)
 
+    def grad_u(x):
+        xi = x @ Ai.T
+        s, c = np.sin(np.pi * xi), np.cos(np.pi * xi)
+        gxi = np.stack([np.pi * c[..., a] * np.prod(np.delete(s, a, -1), -1) for a in range(3)], -1)
+        return gxi @ Ai                                   # A^-T grad_xi, row form
+
     def f(x):
         xi = x @ Ai.T
         s, c = np.sin(np.pi * xi), np.cos(np.pi * xi)
@@ -256,7 +262,7 @@ def _shear_problem(ne, p):
                 fa = [c[..., l] if l in (a, b) and a != b else s[..., l] for l in range(3)]
                 H[..., a, b] = np.pi ** 2 * np.prod(np.stack(fa, -1), -1) * (-1.0 if a == b else 1.0)
         return -np.einsum("...ab,ab->...", H, S)
-    return kn, ctrl, u, f
+    return kn, ctrl, u, grad_u, f
 
 
 def test_coefficient_convention_by_sheared_map(monkeypatch):
@@ -264,10 +270,10 @@ def test_coefficient_convention_by_sheared_map(monkeypatch):
     def h1_errs():
         out = []
         for ne in (4, 8):
-            kn, ctrl, u, f = _shear_problem(ne, p)
+            kn, ctrl, u, gu, f = _shear_problem(ne, p)
             pr = Problem(kn, p, ctrl)
             x = spla.spsolve(pr.assemble().tocsc(), pr.rhs_from(f))
-            out.append(errors(kn, p, ctrl, x, u)[1])
+            out.append(errors(kn, p, ctrl, x, u, gu)[1])
         return out
     good = h1_errs()
     assert good[1] < 1.5e-3 and _rates(good)[0] > p - 0.4
@@ -401,7 +407,7 @@ def _reaction_h1_errors(p):
         b = pr.rhs_from(lambda x: synth.f_sine(x) + alpha_fn(x) * synth.u_sine(x))
         u, it, rel, _ = bicgstab(pr.apply, b, FD(pr.spaces, shift=20.0).apply, tol=1e-12)
         assert rel <= 1e-12
-        out.append(errors(kn, p, ctrl, u, synth.u_sine)[1])
+        out.append(errors(kn, p, ctrl, u, synth.u_sine, synth.grad_u_sine)[1])
     return out
 
 
@@ -423,6 +429,9 @@ def test_reaction_without_det_J_fails_on_a_scaled_cube():
     def u(x):
         return synth.u_sine(x / 2.0)
 
+    def grad_u(x):
+        return 0.5 * synth.grad_u_sine(x / 2.0)
+
     def f(x):
         return 0.25 * synth.f_sine(x / 2.0) + alpha_fn(x) * u(x)
 
@@ -433,7 +442,7 @@ def test_reaction_without_det_J_fails_on_a_scaled_cube():
         if planted:                             # the mistake: alpha without det J on the diagonal
             pr.Cm = np.asarray(a_q).reshape(pr.detJ.shape) * 1.0
         x, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(f), FD(pr.spaces, shift=80.0).apply, tol=1e-12)
-        return errors(kn, p, ctrl, x, u)[1]
+        return errors(kn, p, ctrl, x, u, grad_u)[1]
     good, bad = err(False), err(True)
     assert bad > 5 * good
 
@@ -614,7 +623,7 @@ def test_table1_coarse_levels_reproduced(ne, p):
     ctrl = synth.control_net("ring_interp", kn, p)
     pr = Problem(kn, p, ctrl)
     u, it, rel, _ = bicgstab(pr.apply, pr.rhs_from(synth.f_paper), FD(pr.spaces).apply, tol=1e-12)
-    h1 = errors(kn, p, ctrl, u, synth.u_paper)[1]
+    h1 = errors(kn, p, ctrl, u, synth.u_paper, synth.grad_u_paper)[1]
     assert rel <= 1e-12 and abs(h1 / ref - 1) < 0.25, (h1, ref)
 
 
@@ -710,3 +719,76 @@ def test_error_integrator_is_exact_on_an_affine_map(p):
                               sum(S_wrong[a, a] * Gd[a] * np.prod([Gm[l] for l in range(3) if l != a])
                                   for a in range(3)))
     assert not math.isclose(h1p, wrong, rel_tol=1e-3)
+
+
+# ---------------------------------------------------------------- manufactured solutions (eq. exact-solution)
+def _sympy_fields(kind):
+    """u, grad u and -Laplace u of the manufactured solutions, differentiated
+    symbolically by sympy (independent of the closed forms in synth)."""
+    import sympy as sp
+    x1, x2, x3 = sp.symbols("x1 x2 x3", real=True)
+    if kind == "paper":
+        k = 5 * sp.pi
+        rho = x1 ** 2 + x2 ** 2
+        u = sp.sin(k * x1) * sp.sin(k * x2) * sp.sin(k * x3) * (rho - 1) * (rho - 4)
+    else:
+        u = sp.sin(sp.pi * x1) * sp.sin(sp.pi * x2) * sp.sin(sp.pi * x3)
+    X = (x1, x2, x3)
+    grad = [sp.diff(u, v) for v in X]
+    mlap = -sum(sp.diff(u, v, 2) for v in X)
+    lam = lambda e: sp.lambdify(X, e, "numpy")
+    return lam(u), [lam(g) for g in grad], lam(mlap)
+
+
+@pytest.mark.parametrize("kind", ["paper", "sine"])
+def test_manufactured_solution_gradient_and_source_by_symbolic_differentiation(kind):
+    """The closed-form gradient (used by the H1 error of Table 1) and source
+    f = -Laplace u of each manufactured solution equal sympy's symbolic
+    derivatives at random points of the ring's bounding box; a planted slip in
+    the gradient (the g'(rho) term of the paper's solution dropped) fails."""
+    x = np.random.default_rng(4).uniform([-0.1, -0.1, -0.1], [2.1, 2.1, 1.1], (500, 3))
+    su, sg, sf = _sympy_fields(kind)
+    u_fn = synth.u_paper if kind == "paper" else synth.u_sine
+    g_fn = synth.grad_u_paper if kind == "paper" else synth.grad_u_sine
+    f_fn = synth.f_paper if kind == "paper" else synth.f_sine
+    ref_g = np.stack([np.broadcast_to(g(x[:, 0], x[:, 1], x[:, 2]), (len(x),)) for g in sg], -1)
+    assert np.abs(u_fn(x) - su(x[:, 0], x[:, 1], x[:, 2])).max() <= 1e-13 * np.abs(u_fn(x)).max()
+    assert np.abs(g_fn(x) - ref_g).max() <= 1e-13 * np.abs(ref_g).max()
+    ref_f = sf(x[:, 0], x[:, 1], x[:, 2])
+    assert np.abs(f_fn(x) - ref_f).max() <= 1e-13 * np.abs(ref_f).max()
+    if kind == "paper":
+        k = 5.0 * math.pi
+        s = np.sin(k * x)
+        c = np.cos(k * x)
+        rho = x[:, 0] ** 2 + x[:, 1] ** 2
+        g = (rho - 1) * (rho - 4)
+        slip = np.stack([k * c[:, 0] * s[:, 1] * s[:, 2] * g, k * s[:, 0] * c[:, 1] * s[:, 2] * g,
+                         k * s[:, 0] * s[:, 1] * c[:, 2] * g], -1)
+        assert np.abs(slip - ref_g).max() > 1e-2 * np.abs(ref_g).max()
+
+
+# ---------------------------------------------------------------- BiCGStab half-step confirmation (R8)
+def test_bicgstab_half_step_that_fails_confirmation_continues_with_one_update():
+    """Reading R8: when the half-step residual s meets the tolerance but the true
+    residual of x + alpha p^ does not confirm, the iteration goes on with x
+    unchanged, and the full step adds alpha p^ + omega s^ once.  Hand-worked
+    case: A = diag(1, 2), b = (1, 1), no preconditioner, tol 0.4, and an
+    operator whose second call (the confirmation) is off by (1/2, 1/2), as an
+    inexact low-precision product can be.  Iteration 1: alpha = 2/3,
+    s = (1/3, -1/3) (|s|/|b| = 1/3 <= 0.4), the confirmation reads a relative
+    residual of sqrt(26)/(6 sqrt 2) = 0.60 and fails, omega = 3/5, so
+    x = (2/3, 2/3) + 3/5 (1/3, -1/3) = (13/15, 7/15) with true relative
+    residual |(2/15, 1/15)| / sqrt 2 = sqrt(10)/30 = 0.105.  Adding alpha p^ twice would give
+    (23/15, 17/15)."""
+    d = np.array([1.0, 2.0])
+    calls = []
+
+    def A(x):
+        calls.append(1)
+        y = d * x
+        return y + 0.5 if len(calls) == 2 else y
+
+    x, it, rel, _ = bicgstab(A, np.ones(2), tol=0.4, maxit=1)
+    assert len(calls) >= 3
+    assert np.allclose(x, [13 / 15, 7 / 15], rtol=0, atol=1e-15), x
+    assert it == 1 and math.isclose(rel, math.sqrt(10) / 30, rel_tol=1e-12)
