@@ -15,6 +15,12 @@ R2 (the local exactness systems are underdetermined and, for derivative trial
    unit 2-norm: that leaves the solution set of the (consistent) system, hence
    its minimum-norm element, unchanged and makes the solve far better
    conditioned (trial functions that barely overlap supp(b_i) give tiny rows).
+   On strongly graded knots the systems still reach condition numbers of 1e6
+   and more, and the SVD solution then leaks into the null space of A (it is no
+   longer the minimum-norm element to FP64 accuracy).  It is refined once on
+   the two conditions that define the minimum-norm solution, w = A^T z (row
+   space) and A w = r, with both residuals formed with exact products and one
+   rounding; the correction is computed by the same pseudo-inverse.
 R3 (exactness trial set): exactness is imposed for every trial B-spline b_j,
    j = 0..m-1 (boundary ones included), not only the interior ones; functions
    with |j - i| > p vanish with their first derivative on supp(b_i) for p >= 2,
@@ -26,6 +32,8 @@ Weights depend on (a, b) = (test derivative order, trial derivative order):
 for interior test functions i = 1..m-2 (0-based), giving W^{ab} in R^{n x n_q}.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -73,6 +81,41 @@ def local_system(knots, p, xq, i, a, b, Bfull=None, G=None):
     return S, T, A, rhs
 
 
+def _split(x):
+    """Veltkamp splitting x = hi + lo, each half with at most 26 significant
+    bits, so products of halves are exact in FP64."""
+    c = 134217729.0 * x                      # 2^27 + 1
+    hi = c - (c - x)
+    return hi, x - hi
+
+
+def exact_residual(A, w, r):
+    """r - A w for each row, with every product A_ts w_s formed exactly (as the
+    sum of four products of split halves) and the whole sum rounded once
+    (math.fsum)."""
+    ah, al = _split(np.asarray(A, dtype=np.float64))
+    wh, wl = _split(np.asarray(w, dtype=np.float64))
+    parts = [ah * wh, ah * wl, al * wh, al * wl]
+    return np.array([math.fsum([float(r[t])] + [-float(x) for P in parts for x in P[t]])
+                     for t in range(A.shape[0])])
+
+
+def min_norm_solve(A, rhs):
+    """Minimum-norm solution of the consistent system A w = rhs (reading R2):
+    rows equilibrated, SVD pseudo-inverse with relative cut-off RANK_RTOL, then
+    one refinement step of the pair of conditions w - A^T z = 0, A w = r:
+    with f = A^T z - w and g = r - A w (exactly rounded), the correction
+    dw = f + pinv(A) (g - A f) restores both."""
+    d = 1.0 / np.linalg.norm(A, axis=1)
+    As, rs = d[:, None] * A, d * rhs
+    w, _, _, _ = np.linalg.lstsq(As, rs, rcond=RANK_RTOL)
+    z, _, _, _ = np.linalg.lstsq(As.T, w, rcond=RANK_RTOL)
+    f = -exact_residual(As.T, z, w)
+    g = exact_residual(As, w, rs)
+    dv, _, _, _ = np.linalg.lstsq(As, g - As @ f, rcond=RANK_RTOL)
+    return w + (f + dv)
+
+
 def weights(knots, p: int, xq=None):
     """All four 1D weight matrices {(a, b): W^{ab}} (each n x n_q)."""
     t = np.asarray(knots, dtype=np.float64)
@@ -88,9 +131,7 @@ def weights(knots, p: int, xq=None):
             W = np.zeros((m - 2, nq))
             for i in range(1, m - 1):
                 S, T, A, rhs = local_system(t, p, xq, i, a, b, Bf[b], G)
-                d = 1.0 / np.linalg.norm(A, axis=1)
-                w, _, _, _ = np.linalg.lstsq(d[:, None] * A, d * rhs, rcond=RANK_RTOL)
-                W[i - 1, S] = w
+                W[i - 1, S] = min_norm_solve(A, rhs)
             out[(a, b)] = W
     return out
 

@@ -73,8 +73,32 @@ int find_span(const std::vector<double>& U, int p, int m, double x) {
     return lo;
 }
 
+// r - sum_s a[s] x[s] with every product split exactly by an FMA and the sum
+// accumulated as a double-double (error-free TwoSum), rounded once at the end:
+// accurate as if computed in twice the working precision.
+double dot_residual(double r, const double* a, size_t stride, const double* x, int n) {
+#pragma clang fp contract(off)
+    // (no contraction: the error-free transformations need each product and
+    // sum rounded on its own)
+    double hi = r, lo = 0.0;
+    for (int s = 0; s < n; ++s) {
+        const double pr = a[(size_t)s * stride] * x[s];
+        const double pe = std::fma(a[(size_t)s * stride], x[s], -pr);   // exact: a x = pr + pe
+        const double t = hi - pr;                                         // TwoSum(hi, -pr)
+        const double bb = t - hi;
+        lo += (hi - (t - bb)) + (-pr - bb) - pe;
+        hi = t;
+    }
+    return hi + lo;
+}
+
 // Minimum-norm solution of A w = r, A is nt x ns (row-major), via one-sided
-// Jacobi on the columns of A^T.  Returns the numerical rank.
+// Jacobi on the columns of A^T, then one refinement step of the two
+// conditions that define the minimum-norm solution, w = A^T z and A w = r:
+// with f = A^T z - w and g = r - A w (both exactly rounded), the correction
+// w += f + pinv(A) (g - A f).  On graded knots and at high degree the local
+// systems reach condition numbers of 1e7 and more; without the step the
+// solution leaks into the null space of A.  Returns the numerical rank.
 int min_norm_solve(int nt, int ns, const std::vector<double>& A, const std::vector<double>& r,
                    std::vector<double>& w) {
     // M = A^T  (ns x nt), column k = equation k
@@ -114,23 +138,55 @@ int min_norm_solve(int nt, int ns, const std::vector<double>& A, const std::vect
         }
         if (off < 1e-15) break;
     }
-    std::vector<double> sig(nt);
+    // A^T V = M with V orthogonal and the columns m_k of M orthogonal, so
+    // A = V M^T and pinv(A) y = sum_k m_k (v_k . y) / |m_k|^2 over the kept k
+    std::vector<double> sig2(nt);
     double smax = 0.0;
     for (int k = 0; k < nt; ++k) {
         double s2 = 0;
         for (int s = 0; s < ns; ++s) s2 += M[s * nt + k] * M[s * nt + k];
-        sig[k] = std::sqrt(s2);
-        smax = std::max(smax, sig[k]);
+        sig2[k] = s2;
+        smax = std::max(smax, std::sqrt(s2));
     }
-    w.assign(ns, 0.0);
+    std::vector<char> keep(nt);
     int rank = 0;
     for (int k = 0; k < nt; ++k) {
-        if (!(sig[k] > 1e-12 * smax)) continue;
-        ++rank;
-        double vr = 0;
-        for (int t = 0; t < nt; ++t) vr += V[t * nt + k] * r[t];
-        double f = vr / (sig[k] * sig[k]);
-        for (int s = 0; s < ns; ++s) w[s] += f * M[s * nt + k];
+        keep[k] = std::sqrt(sig2[k]) > 1e-12 * smax;
+        rank += keep[k];
+    }
+    auto pinv = [&](const std::vector<double>& y, std::vector<double>& out) {   // out = pinv(A) y (ns)
+        out.assign(ns, 0.0);
+        for (int k = 0; k < nt; ++k) {
+            if (!keep[k]) continue;
+            double vy = 0;
+            for (int t = 0; t < nt; ++t) vy += V[t * nt + k] * y[t];
+            const double f = vy / sig2[k];
+            for (int s = 0; s < ns; ++s) out[s] += f * M[s * nt + k];
+        }
+    };
+    auto pinvT = [&](const std::vector<double>& x, std::vector<double>& out) {  // out = pinv(A^T) x (nt)
+        out.assign(nt, 0.0);
+        for (int k = 0; k < nt; ++k) {
+            if (!keep[k]) continue;
+            double mx = 0;
+            for (int s = 0; s < ns; ++s) mx += M[s * nt + k] * x[s];
+            const double f = mx / sig2[k];
+            for (int t = 0; t < nt; ++t) out[t] += f * V[t * nt + k];
+        }
+    };
+    pinv(r, w);
+    std::vector<double> z, f(ns), g(nt), h(nt), dv;
+    {
+        pinvT(w, z);
+        for (int s = 0; s < ns; ++s) f[s] = -dot_residual(w[s], &A[s], ns, z.data(), nt);    // A^T z - w
+        for (int t = 0; t < nt; ++t) g[t] = dot_residual(r[t], &A[(size_t)t * ns], 1, w.data(), ns);  // r - A w
+        for (int t = 0; t < nt; ++t) {
+            double af = 0;
+            for (int s = 0; s < ns; ++s) af += A[(size_t)t * ns + s] * f[s];
+            h[t] = g[t] - af;
+        }
+        pinv(h, dv);
+        for (int s = 0; s < ns; ++s) w[s] += f[s] + dv[s];
     }
     return rank;
 }

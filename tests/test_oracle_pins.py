@@ -792,3 +792,61 @@ def test_bicgstab_half_step_that_fails_confirmation_continues_with_one_update():
     assert len(calls) >= 3
     assert np.allclose(x, [13 / 15, 7 / 15], rtol=0, atol=1e-15), x
     assert it == 1 and math.isclose(rel, math.sqrt(10) / 30, rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------- minimum-norm weights on graded knots (R2)
+def _graded_knots(p, seed):
+    rng = np.random.default_rng(seed)
+    br = np.unique(np.round(np.sort(rng.uniform(0.08, 0.92, 8)), 3))
+    return np.concatenate([np.zeros(p + 1), br, np.ones(p + 1)])
+
+
+@pytest.mark.parametrize("p,kind", [(6, "graded"), (8, "uniform"), (10, "graded")])
+def test_minimum_norm_weights_match_50_digit_arithmetic(p, kind):
+    """Reading R2 on ill-conditioned local systems (graded knots with elements
+    of 0.002 next to 0.4, and p up to 10: condition numbers 1e6 to 1e9): the
+    oracle's weights equal the minimum-norm solution of the same FP64 system
+    computed by mpmath in 50 digits (w = A^T (A A^T)^-1 r for the full-row-rank
+    value systems, the 50-digit SVD with the same relative cut-off for the
+    rank-deficient derivative systems) to 1e-14 of max |W|, in the rows where
+    a plain FP64 SVD solve is least accurate."""
+    import mpmath as mp
+    from oracle import bspline as obs
+    mp.mp.dps = 50
+    k = synth.uniform_knots(11, p) if kind == "uniform" else _graded_knots(p, 100 + p)
+    S = wq.Space1D(k, p)
+    for a, b in [(0, 0), (1, 1)]:
+        G = obs.galerkin_1d(S.knots, p, a, b)
+        scale = np.abs(S.W[(a, b)]).max()
+        conds = []
+        for i in range(1, S.m - 1):
+            _, _, A, _ = wq.local_system(S.knots, p, S.xq, i, a, b, S.Bfull[b], G)
+            sv = np.linalg.svd(A / np.linalg.norm(A, axis=1)[:, None], compute_uv=False)
+            conds.append(sv[0] / sv[sv > 1e-12 * sv[0]][-1])
+        for i in [int(np.argmax(conds)) + 1, 1, S.m // 2]:
+            Sx, T, A, rhs = wq.local_system(S.knots, p, S.xq, i, a, b, S.Bfull[b], G)
+            d = 1.0 / np.linalg.norm(A, axis=1)
+            Am, rm = mp.matrix((d[:, None] * A).tolist()), mp.matrix((d * rhs).tolist())
+            if b == 0:
+                wm = Am.T * mp.lu_solve(Am * Am.T, rm)
+            else:
+                U, Sg, V = mp.svd_r(Am)
+                wm = mp.matrix(A.shape[1], 1)
+                for kk in range(len(Sg)):
+                    if Sg[kk] > mp.mpf(wq.RANK_RTOL) * max(Sg):
+                        c = sum(U[t, kk] * rm[t] for t in range(A.shape[0])) / Sg[kk]
+                        for s in range(A.shape[1]):
+                            wm[s] += c * V[kk, s]
+            exact = np.array([float(x) for x in wm])
+            err = np.abs(S.W[(a, b)][i - 1, Sx] - exact).max() / scale
+            assert err <= 1e-14, (a, b, i, err, max(conds))
+    # the plain FP64 SVD solution (no refinement) misses the bar on these systems
+    if (p, kind) == (6, "graded"):
+        G = obs.galerkin_1d(S.knots, p, 0, 0)
+        worst = 0.0
+        for i in range(1, S.m - 1):
+            Sx, T, A, rhs = wq.local_system(S.knots, p, S.xq, i, 0, 0, S.Bfull[0], G)
+            d = 1.0 / np.linalg.norm(A, axis=1)
+            w0 = np.linalg.lstsq(d[:, None] * A, d * rhs, rcond=wq.RANK_RTOL)[0]
+            worst = max(worst, np.abs(w0 - S.W[(0, 0)][i - 1, Sx]).max())
+        assert worst > 1e-13 * np.abs(S.W[(0, 0)]).max()
