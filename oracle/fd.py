@@ -48,6 +48,14 @@ class FD:
         Rh = Rh / self.D
         return mode(U3, mode(U2, mode(U1, Rh, 2), 1), 0).ravel()
 
+    def apply_abs(self, r):
+        """Entry-wise rounding-error scale of ``apply``: the same six mode
+        products on |U_l|, |U_l^T|, |r| and the scaling by 1 / |diagonal|."""
+        A1, A2, A3 = (np.abs(U) for U in self.U)
+        R = np.abs(np.asarray(r, dtype=np.float64)).reshape(self.n[2], self.n[1], self.n[0])
+        Rh = mode(A3.T, mode(A2.T, mode(A1.T, R, 2), 1), 0) / np.abs(self.D)
+        return mode(A3, mode(A2, mode(A1, Rh, 2), 1), 0).ravel()
+
     def P_apply(self, v):
         """P v from the Kronecker form (no eigen-decomposition)."""
         M1, M2, M3 = self.M

@@ -119,13 +119,13 @@ class Problem:
         return (Wk @ sp.diags(self.Cm.ravel()) @ Bk).tocsr()
 
     # -- matrix-free products ---------------------------------------------
-    def _shape(self, v, q=False):
+    def _shape(self, v, q=False, dtype=np.float64):
         n = self.nq if q else self.n
-        return np.asarray(v, dtype=np.float64).reshape(n[2], n[1], n[0])
+        return np.asarray(v, dtype=dtype).reshape(n[2], n[1], n[0])
 
-    def grad_at_quad(self, v):
+    def grad_at_quad(self, v, dtype=np.float64):
         """v~^(beta) = B^(beta) v for beta = 1..3 (Algorithm 2, first step)."""
-        V = self._shape(v)
+        V = self._shape(v, dtype=dtype)
         out = []
         for be in range(3):
             B1, B2, B3 = self.Bk(be)
@@ -140,48 +140,98 @@ class Problem:
         W1, W2, W3 = self.Wk(alpha, beta)
         return mode(W3.T, mode(W2.T, mode(W1.T, Y, 2), 1), 0)
 
-    def apply(self, v):
-        """w = K~ v following Algorithm 2 step by step (plus M~ v when alpha is set)."""
-        g = self.grad_at_quad(v)
-        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+    def apply(self, v, dtype=np.float64):
+        """w = K~ v following Algorithm 2 step by step (plus M~ v when alpha is set).
+        dtype=np.longdouble evaluates the same steps in extended precision (the
+        FP64 factors converted exactly), for residuals of reference solves."""
+        g = self.grad_at_quad(v, dtype)
+        w = np.zeros((self.n[2], self.n[1], self.n[0]), dtype=dtype)
         for be in range(3):
             for al in range(3):
                 w += self.test_contract(al, be, self.plane(al, be) * g[be])
         if self.Cm is not None:
-            w += self.mass_apply(v).reshape(w.shape)
+            w += self.mass_apply(v, dtype).reshape(w.shape)
         return w.ravel()
 
-    def values_at_quad(self, v):
+    def values_at_quad(self, v, dtype=np.float64):
         """v~ = (B_3 (x) B_2 (x) B_1) v, the values of v_h at the points (Algorithm 1, first step)."""
         S = self.spaces
-        return mode(S[2].B[0], mode(S[1].B[0], mode(S[0].B[0], self._shape(v), 2), 1), 0)
+        return mode(S[2].B[0], mode(S[1].B[0], mode(S[0].B[0], self._shape(v, dtype=dtype), 2), 1), 0)
 
-    def mass_apply(self, v):
+    def mass_apply(self, v, dtype=np.float64):
         """w = M~ v by the three steps of Algorithm 1: values at the points, the
         diagonal D = diag(alpha det J), the W^(00) rules."""
-        vt = self.values_at_quad(v)
+        vt = self.values_at_quad(v, dtype)
         vtt = self.Cm * vt
         return self.W00(vtt).ravel()
 
-    def mass_apply_T(self, v):
+    def mass_apply_T(self, v, dtype=np.float64):
         """w = M~^T v = B^T D W^(00)^T v."""
         S = self.spaces
-        Y = self.Cm * self.W00_T(self._shape(v))
+        Y = self.Cm * self.W00_T(self._shape(v, dtype=dtype))
         return mode(S[2].B[0].T, mode(S[1].B[0].T, mode(S[0].B[0].T, Y, 2), 1), 0).ravel()
 
-    def apply_T(self, v):
-        """w = K~^T v = sum_{alpha,beta} B^(beta)^T D^(alpha,beta) W^(alpha,beta)^T v."""
-        Y = self._shape(v)
-        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+    def apply_T(self, v, dtype=np.float64):
+        """w = K~^T v = sum_{alpha,beta} B^(beta)^T D^(alpha,beta) W^(alpha,beta)^T v
+        (dtype as in ``apply``)."""
+        Y = self._shape(v, dtype=dtype)
+        w = np.zeros((self.n[2], self.n[1], self.n[0]), dtype=dtype)
         for be in range(3):
-            acc = np.zeros((self.nq[2], self.nq[1], self.nq[0]))
+            acc = np.zeros((self.nq[2], self.nq[1], self.nq[0]), dtype=dtype)
             for al in range(3):
                 acc += self.plane(al, be) * self.test_contract_T(al, be, Y)
             B1, B2, B3 = self.Bk(be)
             w += mode(B3.T, mode(B2.T, mode(B1.T, acc, 2), 1), 0)
         if self.Cm is not None:
-            w += self.mass_apply_T(v).reshape(w.shape)
+            w += self.mass_apply_T(v, dtype).reshape(w.shape)
         return w.ravel()
+
+    # -- rounding-error scales (reading R11) ---------------------------------
+    def apply_abs(self, v):
+        """Entry-wise rounding-error scale of ``apply``: the same chain on the
+        absolute values of every factor and of v, sum_ab |W^(ab)| |D^(ab)| |B^(b)| |v|
+        (plus |W^(00)| |D_alpha| |B| |v| with a reaction term).  Any evaluation order
+        of K~ v in floating point differs from the exact product by at most a small
+        multiple of the unit roundoff times this, entry by entry."""
+        V = np.abs(self._shape(v))
+        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+        for be in range(3):
+            B1, B2, B3 = (np.abs(B) for B in self.Bk(be))
+            g = mode(B3, mode(B2, mode(B1, V, 2), 1), 0)
+            for al in range(3):
+                W1, W2, W3 = (np.abs(W) for W in self.Wk(al, be))
+                w += mode(W3, mode(W2, mode(W1, np.abs(self.plane(al, be)) * g, 2), 1), 0)
+        if self.Cm is not None:
+            S = self.spaces
+            g = mode(np.abs(S[2].B[0]), mode(np.abs(S[1].B[0]), mode(np.abs(S[0].B[0]), V, 2), 1), 0)
+            w += self._W00_abs(np.abs(self.Cm) * g)
+        return w.ravel()
+
+    def apply_T_abs(self, v):
+        """Entry-wise rounding-error scale of ``apply_T``: sum_ab |B^(b)|^T |D^(ab)| |W^(ab)|^T |v|."""
+        Y = np.abs(self._shape(v))
+        w = np.zeros((self.n[2], self.n[1], self.n[0]))
+        for be in range(3):
+            acc = np.zeros((self.nq[2], self.nq[1], self.nq[0]))
+            for al in range(3):
+                W1, W2, W3 = (np.abs(W) for W in self.Wk(al, be))
+                acc += np.abs(self.plane(al, be)) * mode(W3.T, mode(W2.T, mode(W1.T, Y, 2), 1), 0)
+            B1, B2, B3 = (np.abs(B) for B in self.Bk(be))
+            w += mode(B3.T, mode(B2.T, mode(B1.T, acc, 2), 1), 0)
+        if self.Cm is not None:
+            S = self.spaces
+            Q = np.abs(self.Cm) * mode(np.abs(S[2].W[(0, 0)]).T, mode(np.abs(S[1].W[(0, 0)]).T,
+                                                                         mode(np.abs(S[0].W[(0, 0)]).T, Y, 2), 1), 0)
+            w += mode(np.abs(S[2].B[0]).T, mode(np.abs(S[1].B[0]).T, mode(np.abs(S[0].B[0]).T, Q, 2), 1), 0)
+        return w.ravel()
+
+    def rhs_abs(self, f_q):
+        """Entry-wise rounding-error scale of ``rhs``: |W^(00)| |det J f|."""
+        return self._W00_abs(np.abs(self.detJ * np.asarray(f_q).reshape(self.detJ.shape))).ravel()
+
+    def _W00_abs(self, Q):
+        S = self.spaces
+        return mode(np.abs(S[2].W[(0, 0)]), mode(np.abs(S[1].W[(0, 0)]), mode(np.abs(S[0].W[(0, 0)]), Q, 2), 1), 0)
 
     def explicit_row(self, i):
         """Row i of K~ from the definition eq. Kwq, without forming the matrix:

@@ -27,7 +27,7 @@ from typing import Callable, Dict, Optional, Tuple
 import numpy as np
 
 __all__ = [
-    "uniform_knots", "greville", "control_net", "Workload", "WORKLOADS",
+    "uniform_knots", "nonuniform_knots", "greville", "control_net", "Workload", "WORKLOADS",
     "workload", "random_vector", "kappa_field", "sym6_field", "alpha_field",
     "u_sine", "grad_u_sine", "f_sine", "u_paper", "grad_u_paper", "f_paper", "f_smooth",
 ]
@@ -55,6 +55,16 @@ def uniform_knots(n_el: int, p: int) -> np.ndarray:
     knots (maximum regularity C^{p-1}, Section 2.1).  Length ``n_el + 2p + 1``."""
     inner = np.arange(1, n_el) / n_el
     return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def nonuniform_knots(n_el: int, p: int, seed: int, ratio: float = 4.0) -> np.ndarray:
+    """Open knot vector with ``n_el`` elements of seeded random lengths (log-uniform
+    within a factor ``ratio`` of each other) and simple interior knots: the
+    non-uniform meshes the paper's algorithms are written for (Section 4)."""
+    rng = np.random.default_rng(seed)
+    h = np.exp(rng.uniform(-0.5, 0.5, n_el) * math.log(ratio))
+    br = np.cumsum(h / h.sum())[:-1]
+    return np.concatenate([np.zeros(p + 1), br, np.ones(p + 1)])
 
 
 def greville(knots: np.ndarray, p: int) -> np.ndarray:
@@ -314,8 +324,11 @@ class Workload:
     k_kind: str = "identity"    # identity | scalar | sym6
     source: str = "sine"        # sine | paper | smooth
     geom_seed: int = 0
+    knot_seed: Optional[int] = None   # None: uniform knots; else non-uniform, seeds knot_seed + l per direction
 
     def knots(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        if self.knot_seed is not None:
+            return tuple(nonuniform_knots(self.n_el, self.p, self.knot_seed + l) for l in range(3))
         k = uniform_knots(self.n_el, self.p)
         return (k, k.copy(), k.copy())
 
@@ -366,6 +379,13 @@ def _mk() -> Dict[str, Workload]:
     # several 16-point tiles per direction and a ragged last tile (n_q = 53)
     w["ring20_p6"] = Workload("ring20_p6", 20, 6, "ring", 0.02, "identity", "paper")
     w["shear6_p3"] = Workload("shear6_p3", 6, 3, "shear", 0.0, "identity", "sine")
+    # non-uniform knots (element lengths within a factor 4, different per direction)
+    for p in (2, 3, 4, 5, 6):
+        w[f"ring8nu_p{p}"] = Workload(f"ring8nu_p{p}", 8, p, "ring", 0.02, "identity", "paper", knot_seed=200 + 10 * p)
+    w["ring20nu_p6"] = Workload("ring20nu_p6", 20, 6, "ring", 0.02, "identity", "paper", knot_seed=300)
+    w["ring6nu_p8"] = Workload("ring6nu_p8", 6, 8, "ring", 0.02, "identity", "paper", knot_seed=310)
+    w["twist6nu_p5"] = Workload("twist6nu_p5", 6, 5, "twist", 0.0, "sym6", "smooth", knot_seed=320)
+    w["ring64nu_p4"] = Workload("ring64nu_p4", 64, 4, "ring", 0.02, "identity", "paper", knot_seed=330)
     w["cube5_p2"] = Workload("cube5_p2", 5, 2, "identity")
     return w
 

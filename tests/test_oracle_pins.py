@@ -52,7 +52,7 @@ import scipy.sparse.linalg as spla
 from scipy.interpolate import BSpline, make_interp_spline
 
 import synth
-from oracle import bspline, geometry, wq
+from oracle import bspline, geometry, krylov, wq
 from oracle.errors import errors
 from oracle.fd import FD
 from oracle.krylov import bicgstab
@@ -850,3 +850,96 @@ def test_minimum_norm_weights_match_50_digit_arithmetic(p, kind):
             w0 = np.linalg.lstsq(d[:, None] * A, d * rhs, rcond=wq.RANK_RTOL)[0]
             worst = max(worst, np.abs(w0 - S.W[(0, 0)][i - 1, Sx]).max())
         assert worst > 1e-13 * np.abs(S.W[(0, 0)]).max()
+
+
+# ---------------------------------------------------------------- reference solves (reading R10)
+@pytest.mark.parametrize("transpose", [False, True])
+def test_refined_reference_solve_on_an_ill_conditioned_case(transpose):
+    """The solve reference of the parity tests: iterative refinement with
+    extended-precision residuals of the matrix-free operator (Algorithm 2 in
+    longdouble) around FP64 BiCGStab.  On the twisted cube with p = 6 on 6^3
+    elements (cond(K~) ~ 1.6e7) FP64 alone cannot pin 1e-10: an FP64-residual
+    refinement and the plain FP64 solve differ from it by 1e-11 .. 2e-11, and an
+    LU solve of the assembled matrix (entries rounded once) by 1.5e-10.  The
+    certificate here is convergence: two refinements from different starts (a
+    1e-14 and a 1e-9 inner solve) agree to 1e-13 with extended residuals below
+    1e-16, and the planted FP64-residual variant misses them by more than 1e-12."""
+    wl = synth.workload("twist6_p6")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    b = pr.rhs_from(wl.f())
+    fd = FD(pr.spaces)
+    A = pr.apply_T if transpose else pr.apply
+    Ae = (lambda x: pr.apply_T(x, np.longdouble)) if transpose else (lambda x: pr.apply(x, np.longdouble))
+    x1, r1 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
+    x2, r2 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-9, maxit=400)[0], b,
+                                  steps=8)
+    x3, _ = krylov.refined_solve(lambda x: A(x).astype(np.longdouble),
+                                 lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
+    d12 = np.linalg.norm(x1 - x2) / np.linalg.norm(x1)
+    d13 = np.linalg.norm(x1 - x3) / np.linalg.norm(x1)
+    assert r1 <= 1e-16 and r2 <= 1e-16, (r1, r2)
+    assert d12 <= 1e-13, d12
+    assert d13 > 1e-12, d13
+
+
+def test_refined_reference_solve_equals_direct_solve_when_well_conditioned():
+    """On a moderately conditioned curved case the refined matrix-free solution
+    equals scipy's sparse LU solve of the explicitly assembled K~ (eq. Kwq) to
+    1e-13, transposed system included."""
+    import scipy.sparse.linalg as spla
+    wl = synth.workload("ring8_p3")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    b = pr.rhs_from(wl.f())
+    fd = FD(pr.spaces)
+    K = pr.assemble()
+    for A, Ae, Kx in ((pr.apply, lambda x: pr.apply(x, np.longdouble), K),
+                      (pr.apply_T, lambda x: pr.apply_T(x, np.longdouble), K.T)):
+        x, r = krylov.refined_solve(Ae, lambda rr: krylov.bicgstab(A, rr, fd.apply, tol=1e-14, maxit=400)[0], b)
+        xd = spla.spsolve(Kx.tocsc(), b)
+        assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-13
+
+
+def test_extended_precision_apply_agrees_with_fp64_apply():
+    """The longdouble evaluation of Algorithm 2 (and of its transpose, with the
+    reaction term) agrees with the FP64 one to FP64 rounding, and with the
+    assembled matrix."""
+    wl = synth.workload("twist5_p4")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    pr.set_alpha(synth.alpha_field(50.0)(pr.F))
+    v = synth.random_vector(pr.N, 3)
+    K = pr.assemble()
+    for f, ref in ((pr.apply, K @ v), (pr.apply_T, K.T @ v)):
+        we = f(v, np.longdouble)
+        assert we.dtype == np.longdouble
+        assert np.abs(np.asarray(we, dtype=np.float64) - f(v)).max() <= 1e-14 * np.abs(ref).max()
+        assert np.abs(np.asarray(we, dtype=np.float64) - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------- rounding-error scales (reading R11)
+def test_rounding_scales_bound_the_results_and_match_the_abs_matrix():
+    """apply_abs / apply_T_abs / rhs_abs / FD.apply_abs are the chains of the
+    operator on absolute values.  They dominate |K~ v| entry by entry (triangle
+    inequality), they are at least sum_j |K~_ij| |v_j| of the assembled matrix
+    and at most 1e3 times it (they add |terms| that cancel inside an entry of
+    K~, not more) and positively homogeneous; the FD scale equals the dense
+    Kronecker product of the |U_l| around 1 / |diagonal|."""
+    wl = synth.workload("twist5_p4")
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    v = synth.random_vector(pr.N, 4)
+    K = pr.assemble()
+    for f, fa, M in ((pr.apply, pr.apply_abs, K), (pr.apply_T, pr.apply_T_abs, K.T)):
+        s = fa(v)
+        lower = abs(M) @ np.abs(v)
+        assert (s >= np.abs(f(v)) * (1 - 1e-14)).all()
+        assert (s >= lower * (1 - 1e-12)).all()
+        assert (s <= 1e3 * lower).all(), float((s / lower).max())
+        assert np.allclose(fa(-3.0 * v), 3.0 * s, rtol=1e-14, atol=0)
+    fq = synth.f_smooth(pr.F).ravel()
+    assert (pr.rhs_abs(fq) >= np.abs(pr.rhs(fq)) * (1 - 1e-14)).all()
+    fd = FD(pr.spaces)
+    r = synth.random_vector(pr.N, 5)
+    sf = fd.apply_abs(r)
+    assert (sf >= np.abs(fd.apply(r)) * (1 - 1e-14)).all()
+    Ui = [np.abs(U) for U in fd.U]
+    dense = np.kron(Ui[2], np.kron(Ui[1], Ui[0]))
+    assert np.allclose(sf, dense @ ((dense.T @ np.abs(r)) / np.abs(fd.D).ravel()), rtol=1e-12, atol=0)
