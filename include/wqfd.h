@@ -196,6 +196,23 @@ int fd_setup(int p, const int32_t nknots[3], const double* const knots[3], int p
  * accumulation.  r, z device (may alias).  Async on s. */
 int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s);
 
+/* z = P^{-1} r exactly as fd_apply (same kernels, same results bit for bit),
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * intermediate between the mode passes lives in a static device array of
+ * WQ_FD_NOALLOC_BYTES (32 MiB) that the library holds on each device it runs on
+ * until the process ends, instead of the preconditioner's workspace.  The call
+ * allocates nothing; its first call on a device looks up that array's device
+ * address (with the device current).  Limit: N <= WQ_FD_NOALLOC_BYTES / 8
+ * (4,194,304 unknowns, every precision); larger N returns WQ_ENOMEM.  Every call
+ * on one device shares the one array: calls that overlap in time on that device
+ * (different streams, or different host threads) race and give wrong results;
+ * calls ordered on one stream are safe.  Runs on the current device, which must
+ * be the device the preconditioner was set up on.  Arguments as fd_apply.
+ * Errors: WQ_EINVAL, WQ_ENOMEM, WQ_EHIP. */
+#define WQ_FD_NOALLOC_BYTES (32u << 20)
+int fd_apply_noalloc(fd_pc P, int prec, const void* r, void* z, wq_stream_t s);
+
 /* Shift for the reaction term: P becomes P + sigma M3 x M2 x M1, whose inverse
  * has the diagonal 1/(l1_i + l2_j + l3_k + sigma) in the same eigenbasis.
  * sigma is a representative value of alpha det J (e.g. its mean); 0 restores

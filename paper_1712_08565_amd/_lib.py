@@ -14,6 +14,7 @@ WQ_OK, WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR, WQ_ENOMEM, WQ_EHIP, WQ_ENOCONV, WQ_EBR
     0, -1, -2, -3, -4, -5, -6, -7, -8
 WQ_F64, WQ_F32, WQ_BF16 = 1, 2, 4
 WQ_K_IDENTITY, WQ_K_SCALAR, WQ_K_SYM6 = 0, 1, 6
+WQ_FD_NOALLOC_BYTES = 32 << 20
 
 ERROR_NAMES = {WQ_EINVAL: "WQ_EINVAL", WQ_EGEOM: "WQ_EGEOM", WQ_ESINGULAR: "WQ_ESINGULAR",
                WQ_ENOMEM: "WQ_ENOMEM", WQ_EHIP: "WQ_EHIP", WQ_ENOCONV: "WQ_ENOCONV",
@@ -44,6 +45,7 @@ SIGNATURES = [
     ("fd_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), C.c_int, _vp, C.c_size_t, _szp, _vp,
                            C.POINTER(C.c_void_p)]),
     ("fd_apply", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    ("fd_apply_noalloc", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("fd_set_shift", C.c_int, [_vp, C.c_double, _vp]),
     ("fd_factors", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fd_destroy", None, [_vp]),

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -430,6 +431,42 @@ uint16_t f32_to_bf16_bits(float f) {
     return (uint16_t)(u >> 16);
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------- allocation-free FD apply
+// The intermediate buffer of fd_apply_noalloc: one file-scope device array,
+// instantiated on every device the library's code object is loaded on and held
+// until the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress reports, looked up once per device.
+namespace {
+constexpr size_t kFdNoAllocBytes = size_t(32) << 20;   // WQ_FD_NOALLOC_BYTES
+constexpr int kMaxDevices = 64;
+static_assert(kFdNoAllocBytes == WQ_FD_NOALLOC_BYTES, "header and library disagree on the scratch size");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kFdNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (first call per device
+// looks it up with that device current).
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(WQ_EINVAL, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(WQ_EHIP, "hipGetSymbolAddress(scratch) returned a null address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return WQ_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -879,6 +916,23 @@ int fd_apply(fd_pc P, int prec, const void* r, void* z, wq_stream_t s) {
     if ((prec != WQ_F64 && prec != WQ_F32 && prec != WQ_BF16) || !(P->pc.prec_mask & prec))
         return fail(WQ_EINVAL, "precision not prepared for this preconditioner");
     HIP_TRY(wqfd::launch_fd_apply(P->pc, prec, r, z, reinterpret_cast<hipStream_t>(s)), "fd_apply");
+    return WQ_OK;
+}
+
+int fd_apply_noalloc(fd_pc P, int prec, const void* r, void* z, wq_stream_t s) {
+    if (!P || !r || !z) return fail(WQ_EINVAL, "null argument");
+    if ((prec != WQ_F64 && prec != WQ_F32 && prec != WQ_BF16) || !(P->pc.prec_mask & prec))
+        return fail(WQ_EINVAL, "precision not prepared for this preconditioner");
+    // the passes keep N values between them; reserve 8 bytes per value (the
+    // bound fd_setup reserves in its workspace, for every precision)
+    if (P->pc.N > kFdNoAllocBytes / 8)
+        return fail(WQ_ENOMEM, "fd_apply_noalloc: N = " + std::to_string(P->pc.N) +
+                                   " exceeds the static scratch (at most " + std::to_string(kFdNoAllocBytes / 8) +
+                                   " unknowns); use fd_apply");
+    void* tmp = nullptr;
+    int rc = noalloc_scratch(&tmp);
+    if (rc) return rc;
+    HIP_TRY(wqfd::launch_fd_apply(P->pc, prec, r, z, tmp, reinterpret_cast<hipStream_t>(s)), "fd_apply_noalloc");
     return WQ_OK;
 }
 

@@ -101,8 +101,12 @@ hipError_t launch_set_alpha(const WqOp& op, const double* alpha_q, hipStream_t s
 hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, hipStream_t s);
 hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s);
 
-// FD preconditioner (fd_kernels.hip)
-hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s);
+// FD preconditioner (fd_kernels.hip).  `scratch` holds the intermediate between
+// the passes: N values of the precision's type (at most N * 8 bytes).
+hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, void* scratch, hipStream_t s);
+inline hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s) {
+    return launch_fd_apply(P, prec, r, z, P.scratch, s);
+}
 
 // BLAS-1 helpers for the Krylov drivers (blas1.hip)
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, size_t n, double scale, hipStream_t s);

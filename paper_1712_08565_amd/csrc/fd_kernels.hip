@@ -240,10 +240,11 @@ inline dim3 grid_cols(int C, int n, int A) {
 }
 
 template <int PREC>
-hipError_t fd_apply_t(const FdPc& P, const typename Tr<PREC>::T* r, typename Tr<PREC>::T* z, hipStream_t s) {
+hipError_t fd_apply_t(const FdPc& P, const typename Tr<PREC>::T* r, typename Tr<PREC>::T* z, void* scratch,
+                      hipStream_t s) {
     using T = typename Tr<PREC>::T;
     const int n1 = P.n[0], n2 = P.n[1], n3 = P.n[2];
-    T* tmp = reinterpret_cast<T*>(P.scratch);
+    T* tmp = reinterpret_cast<T*>(scratch);
     const T* U[3];
     for (int l = 0; l < 3; ++l) U[l] = PREC == 1 ? (const T*)P.U64[l] : (const T*)P.U32[l];
     const dim3 blk(64 * kWaves);
@@ -269,9 +270,9 @@ hipError_t fd_apply_t(const FdPc& P, const typename Tr<PREC>::T* r, typename Tr<
     return hipGetLastError();
 }
 
-hipError_t fd_apply_bf16(const FdPc& P, const float* r, float* z, hipStream_t s) {
+hipError_t fd_apply_bf16(const FdPc& P, const float* r, float* z, void* scratch, hipStream_t s) {
     const int n1 = P.n[0], n2 = P.n[1], n3 = P.n[2];
-    float* tmp = reinterpret_cast<float*>(P.scratch);
+    float* tmp = reinterpret_cast<float*>(scratch);
     const dim3 blk(64 * kWaves);
     Scale none;
     Scale sc;
@@ -305,12 +306,12 @@ hipError_t fd_apply_bf16(const FdPc& P, const float* r, float* z, hipStream_t s)
 
 // Six LDS-tiled mode products (fd_gemm.hip): x, y, z forward with U^T (scaling
 // fused into z), then x, y, z backward with U.  Ping-pongs between z and the
-// preconditioner's scratch buffer, so r and z may alias.
+// scratch buffer (N values), so r and z may alias.
 template <typename T, typename S>
-hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], const S* const Tb[3],
+hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, void* scratch, const S* const Tf[3], const S* const Tb[3],
                          const int ld[3], hipStream_t s) {
     const int n1 = P.n[0], n2 = P.n[1], n3 = P.n[2];
-    T* tmp = reinterpret_cast<T*>(P.scratch);
+    T* tmp = reinterpret_cast<T*>(scratch);
     auto mode = [&](int axis, const T* in, T* out, const S* mat, bool scale) {
         FdModeArgs<T, S> a;
         a.in = in;
@@ -356,14 +357,14 @@ hipError_t fd_apply_gemm(const FdPc& P, const T* r, T* z, const S* const Tf[3], 
 
 }  // namespace
 
-hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipStream_t s) {
+hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, void* scratch, hipStream_t s) {
     const bool small = P.n[0] <= 144 && P.n[1] <= 144 && P.n[2] <= 144;
     if (small && P.ldp && (prec == 1 || prec == 2) && !std::getenv("WQFD_FD_MODES")) {
         if (prec == 1) {
             FdFusedArgs<double> f;
             f.r = static_cast<const double*>(r);
             f.z = static_cast<double*>(z);
-            f.tmp = reinterpret_cast<double*>(P.scratch);
+            f.tmp = reinterpret_cast<double*>(scratch);
             for (int l = 0; l < 3; ++l) {
                 f.U[l] = P.Up64[l];
                 f.UT[l] = P.UTp64[l];
@@ -380,7 +381,7 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
         FdFusedArgs<float> f;
         f.r = static_cast<const float*>(r);
         f.z = static_cast<float*>(z);
-        f.tmp = reinterpret_cast<float*>(P.scratch);
+        f.tmp = reinterpret_cast<float*>(scratch);
         for (int l = 0; l < 3; ++l) {
             f.U[l] = P.Up32[l];
             f.UT[l] = P.UTp32[l];
@@ -399,14 +400,14 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
             const double* Tf[3] = {P.UT64[0], P.UT64[1], P.UT64[2]};
             const double* Tb[3] = {P.U64[0], P.U64[1], P.U64[2]};
             const int ld[3] = {P.n[0], P.n[1], P.n[2]};
-            return fd_apply_gemm<double, double>(P, static_cast<const double*>(r), static_cast<double*>(z), Tf, Tb,
+            return fd_apply_gemm<double, double>(P, static_cast<const double*>(r), static_cast<double*>(z), scratch, Tf, Tb,
                                                  ld, s);
         }
         if (prec == 2) {
             const float* Tf[3] = {P.UT32[0], P.UT32[1], P.UT32[2]};
             const float* Tb[3] = {P.U32[0], P.U32[1], P.U32[2]};
             const int ld[3] = {P.n[0], P.n[1], P.n[2]};
-            return fd_apply_gemm<float, float>(P, static_cast<const float*>(r), static_cast<float*>(z), Tf, Tb, ld,
+            return fd_apply_gemm<float, float>(P, static_cast<const float*>(r), static_cast<float*>(z), scratch, Tf, Tb, ld,
                                                s);
         }
         const __bf16 *Tf[3], *Tb[3];
@@ -416,11 +417,12 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, hipS
             Tf[l] = reinterpret_cast<const __bf16*>(P.Ubf[l]);
             Tb[l] = Tf[l] + (size_t)ld[l] * ld[l];
         }
-        return fd_apply_gemm<float, __bf16>(P, static_cast<const float*>(r), static_cast<float*>(z), Tf, Tb, ld, s);
+        return fd_apply_gemm<float, __bf16>(P, static_cast<const float*>(r), static_cast<float*>(z), scratch, Tf, Tb, ld,
+                                            s);
     }
-    if (prec == 1) return fd_apply_t<1>(P, static_cast<const double*>(r), static_cast<double*>(z), s);
-    if (prec == 2) return fd_apply_t<2>(P, static_cast<const float*>(r), static_cast<float*>(z), s);
-    return fd_apply_bf16(P, static_cast<const float*>(r), static_cast<float*>(z), s);
+    if (prec == 1) return fd_apply_t<1>(P, static_cast<const double*>(r), static_cast<double*>(z), scratch, s);
+    if (prec == 2) return fd_apply_t<2>(P, static_cast<const float*>(r), static_cast<float*>(z), scratch, s);
+    return fd_apply_bf16(P, static_cast<const float*>(r), static_cast<float*>(z), scratch, s);
 }
 
 }  // namespace wqfd

@@ -11,11 +11,12 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 import torch
 
-from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_K_IDENTITY, WQ_K_SCALAR, WQ_K_SYM6, WQError, check, lib)
+from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_FD_NOALLOC_BYTES, WQ_K_IDENTITY, WQ_K_SCALAR, WQ_K_SYM6, WQError,
+                   check, lib)
 
 __all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
            "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f",
-           "wq_grad_alpha", "fd_setup", "fd_apply", "fd_set_shift", "fd_factors",
+           "wq_grad_alpha", "fd_setup", "fd_apply", "fd_apply_noalloc", "fd_set_shift", "fd_factors",
            "krylov_solve", "ir_solve", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
            "WQ_K_SYM6", "WQError"]
 
@@ -250,6 +251,16 @@ def fd_apply(P: FdPc, r: torch.Tensor, z: Optional[torch.Tensor] = None, prec: O
     z = torch.empty_like(r) if z is None else z
     _need(z, _DT[prec], P.N, "z")
     check(lib().fd_apply(P.handle, prec, _p(r), _p(z), _stream(stream)), "fd_apply")
+    return z
+
+
+def fd_apply_noalloc(P: FdPc, r: torch.Tensor, z: torch.Tensor, prec: Optional[int] = None, stream=None) -> torch.Tensor:
+    """z = P^{-1} r with the library's static scratch instead of the
+    preconditioner's workspace (the C call allocates nothing; z must be given)."""
+    prec = prec or (WQ_F64 if r.dtype == torch.float64 else WQ_F32)
+    _need(r, _DT[prec], P.N, "r")
+    _need(z, _DT[prec], P.N, "z")
+    check(lib().fd_apply_noalloc(P.handle, prec, _p(r), _p(z), _stream(stream)), "fd_apply_noalloc")
     return z
 
 

@@ -39,6 +39,17 @@ def test_library_loads_and_exports_every_declared_symbol():
     assert b"gfx950" in L.wq_version()
 
 
+def test_noalloc_entry_checks_arguments_on_the_host():
+    """fd_apply_noalloc refuses a null handle or vector before any device work,
+    and the binding's scratch limit is the header's."""
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    assert L.fd_apply_noalloc(None, _lib.WQ_F64, None, None, None) == _lib.WQ_EINVAL
+    assert len(L.wq_last_error()) > 0
+    m = re.search(r"#define\s+WQ_FD_NOALLOC_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.WQ_FD_NOALLOC_BYTES
+
+
 def _setup_args(p, knots):
     ks = [np.ascontiguousarray(k, dtype=np.float64) for k in knots]
     nk = (C.c_int32 * 3)(*[len(k) for k in ks])
