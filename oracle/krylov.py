@@ -69,12 +69,18 @@ def refined_solve(apply_ext, solve, b, steps=4):
     relative accuracy), so the error contracts by that factor per step until
     the extended-precision residual, about cond(A) 2^-64 relative, limits it:
     below FP64 rounding up to cond(A) ~ 1e7, where an FP64 residual alone
-    stalls near cond(A) 1e-16.  Returns (x, relative extended residual)."""
+    stalls near cond(A) 1e-16.  Returns (x, relative extended residual of x,
+    relative size of the last correction); the residual cannot fall below that
+    of x* rounded to FP64 (about 1e-16 |A| |x| / |b|), the last correction is
+    the convergence certificate."""
     b = np.asarray(b, dtype=np.float64)
     bl = b.astype(np.longdouble)
     x = solve(b)
+    step = np.inf
     for _ in range(steps):
         r = bl - apply_ext(x)
-        x = x + solve(np.asarray(r, dtype=np.float64))
+        d = solve(np.asarray(r, dtype=np.float64))
+        x = x + d
+        step = float(np.linalg.norm(d) / np.linalg.norm(x))
     r = bl - apply_ext(x)
-    return x, float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(bl * bl)))
+    return x, float(np.sqrt(np.sum(r * r)) / np.sqrt(np.sum(bl * bl))), step

@@ -870,14 +870,15 @@ def test_refined_reference_solve_on_an_ill_conditioned_case(transpose):
     fd = FD(pr.spaces)
     A = pr.apply_T if transpose else pr.apply
     Ae = (lambda x: pr.apply_T(x, np.longdouble)) if transpose else (lambda x: pr.apply(x, np.longdouble))
-    x1, r1 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
-    x2, r2 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-9, maxit=400)[0], b,
-                                  steps=8)
-    x3, _ = krylov.refined_solve(lambda x: A(x).astype(np.longdouble),
-                                 lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
+    x1, r1, d1 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
+    x2, r2, d2 = krylov.refined_solve(Ae, lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-9, maxit=400)[0], b,
+                                      steps=8)
+    x3, _, _ = krylov.refined_solve(lambda x: A(x).astype(np.longdouble),
+                                    lambda r: krylov.bicgstab(A, r, fd.apply, tol=1e-14, maxit=400)[0], b)
     d12 = np.linalg.norm(x1 - x2) / np.linalg.norm(x1)
     d13 = np.linalg.norm(x1 - x3) / np.linalg.norm(x1)
     assert r1 <= 1e-16 and r2 <= 1e-16, (r1, r2)
+    assert d1 <= 1e-14 and d2 <= 1e-14, (d1, d2)
     assert d12 <= 1e-13, d12
     assert d13 > 1e-12, d13
 
@@ -894,8 +895,10 @@ def test_refined_reference_solve_equals_direct_solve_when_well_conditioned():
     K = pr.assemble()
     for A, Ae, Kx in ((pr.apply, lambda x: pr.apply(x, np.longdouble), K),
                       (pr.apply_T, lambda x: pr.apply_T(x, np.longdouble), K.T)):
-        x, r = krylov.refined_solve(Ae, lambda rr: krylov.bicgstab(A, rr, fd.apply, tol=1e-14, maxit=400)[0], b)
+        x, r, d = krylov.refined_solve(Ae, lambda rr: krylov.bicgstab(A, rr, fd.apply, tol=1e-14, maxit=400)[0],
+                                       b)
         xd = spla.spsolve(Kx.tocsc(), b)
+        assert d <= 1e-14, d
         assert np.linalg.norm(x - xd) / np.linalg.norm(xd) <= 1e-13
 
 
