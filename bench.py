@@ -30,8 +30,24 @@ Equal accuracy: besides the runs to relative residual 1e-10, each degree is also
 solved at the loosest residual tolerance whose solution is within 1e-10
 (relative 2-norm) of a tight reference solve (FP64, residual 1e-13), for both
 the FP64 and the mixed solver; those times are the like-for-like comparison.
-cpu_baseline: the CPU FP64 oracle's matrix-free apply on a bounded sample
-          (degree 3 of the same workload), timed on this host.
+roofline_fd: the FD preconditioner (three fused mode-product passes) timed
+          alone, R back-to-back FP64 applications between two HIP events per
+          degree; algorithmic flops 12 n N + N per application (six mode products
+          of 2 n N flops and the diagonal scaling) over FP64 MFMA peak.  FP32 and
+          BF16 times are reported per degree against their own peaks.
+Statistics: p10/p90 of the per-launch apply times; "flushed": the fused
+          kernel timed launch by launch right after a 512 MiB write that evicts
+          the 256 MB last-level cache (the C2 coefficient set fits in it).
+large_workloads: after the timed steps, ring 96^3 p = 5 and the twisted cube
+          128^3 p = 6 with full anisotropic K (coefficient sets of 0.4 and 0.9 GB
+          FP64, larger than the last-level cache): kernel-alone FP64 and FP32
+          applies (warm and flushed), FD times, one FP64 and one mixed solve.
+cpu_baseline: the CPU FP64 oracle on this host within a bounded budget:
+          value = its matrix-free apply on degree 3 of the same workload with
+          all threads; also single-threaded (the paper's setting) and FD-
+          preconditioned BiCGStab solves to 1e-10 on the identity cube (12^3,
+          p = 3), the ring (64^3, p = 3) and the log-normal kappa ring (48^3,
+          p = 4).
 """
 from __future__ import annotations
 
@@ -48,6 +64,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}    # dense, MI355X
 METRIC = "WQ apply GDOF/s & time-to-solve to rel.res 1e-10, FP64 vs mixed, p=2..6"
 
 
@@ -99,16 +116,22 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(budget_s: float):
-    """Oracle matrix-free apply (CPU FP64) on ring64 p=3: GDOF/s on this host."""
+def cpu_baseline(budget_s: float, solve_budget_s: float = 25.0):
+    """The CPU FP64 oracle on this host: matrix-free apply on ring64 p=3 with all
+    threads (value) and with one, and FD-preconditioned BiCGStab solves to 1e-10
+    on the identity cube, the ring and the log-normal kappa ring (each with a
+    bounded iteration count when the budget runs out)."""
     import numpy as np
 
     import synth
+    from oracle.fd import FD
+    from oracle.krylov import bicgstab
     from oracle.operator import Problem
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:  # pragma: no cover
+        threadpool_limits = None
         threads = os.cpu_count()
     wl = synth.workload("ring64_p3")
     t0 = time.perf_counter()
@@ -116,18 +139,46 @@ def cpu_baseline(budget_s: float):
     log(f"cpu oracle setup {time.perf_counter() - t0:.1f}s")
     v = synth.random_vector(pr.N, 42)
     pr.apply(v)  # warm-up
-    times = []
-    t_start = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        pr.apply(v)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 100:
-            break
-    t = float(np.median(times))
-    return {"value": pr.N / t / 1e9, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"ring64 p=3 (N={pr.N}), {len(times)} FP64 matrix-free applies, median {t:.3f} s each; "
-                      f"host cpus={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}"}
+
+    def timed(budget, cap):
+        times = []
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            pr.apply(v)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > budget or len(times) >= cap:
+                return float(np.median(times)), len(times)
+
+    t, n_all = timed(0.4 * budget_s, 100)
+    out = {"value": pr.N / t / 1e9, "unit": "GDOF/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"ring64 p=3 (N={pr.N}), {n_all} FP64 matrix-free applies, median {t:.3f} s each; "
+                     f"host cpus={os.cpu_count()}, affinity={len(os.sched_getaffinity(0))}"}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            t1, n1 = timed(0.15 * budget_s, 20)
+        out["single_thread"] = {"value": pr.N / t1 / 1e9, "unit": "GDOF/s", "cores": 1,
+                                "sample": f"ring64 p=3, {n1} applies, median {t1:.3f} s"}
+    if solve_budget_s > 0:
+        res = {}
+        for name in ("cube12_p3", "ring64_p3", "ring48_p4_kappa"):
+            w = synth.workload(name)
+            q = pr if name == "ring64_p3" else Problem(w.knots(), w.p, w.ctrl(), w.K_field())
+            fd = FD(q.spaces)
+            b = q.rhs_from(w.f())
+            # per-iteration cost from one apply + FD, then an iteration cap within the budget
+            t0 = time.perf_counter()
+            fd.apply(q.apply(b))
+            it_cost = 2 * (time.perf_counter() - t0)
+            cap = max(1, int(solve_budget_s / max(it_cost, 1e-6)))
+            t0 = time.perf_counter()
+            _, it, rel, _ = bicgstab(q.apply, b, fd.apply, tol=1e-10, maxit=cap)
+            ts = time.perf_counter() - t0
+            res[name] = {"N": q.N, "seconds": round(ts, 3), "iters": int(it), "relres": float(rel),
+                         "converged": bool(rel <= 1e-10)}
+            log(f"cpu oracle solve {name}: {it} it, {ts:.1f}s, relres {rel:.1e}")
+        out["solves_rtol_1e-10"] = res
+    return out
 
 
 def main():
@@ -139,7 +190,9 @@ def main():
     ap.add_argument("--n-el", type=int, default=64)
     ap.add_argument("--reps", type=int, default=20, help="timed applies per degree per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds for the oracle's apply timings")
+    ap.add_argument("--cpu-solve-budget", type=float, default=25.0,
+                    help="seconds per oracle solve (iteration cap from the measured iteration cost; 0: skip)")
     ap.add_argument("--no-solve", action="store_true", help="time the applies only")
     ap.add_argument("--workloads", default="",
                     help="comma-separated named workloads instead of the default ring (e.g. ring96_p5,twist128_p6)")
@@ -150,6 +203,10 @@ def main():
     ap.add_argument("--gauss-degrees", default="",
                     help="degrees of a Gauss-quadrature comparison on the same ring (e.g. 2,3,4; off by default: "
                          "it launches the same kernel instances as the timed applies)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the out-of-cache records (ring 96^3 p = 5, twisted cube 128^3 p = 6)")
+    ap.add_argument("--flush-mib", type=int, default=512,
+                    help="size of the cache-evicting write before each flushed-kernel launch (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device copy of this many MiB per step (counter calibration)")
     args = ap.parse_args()
@@ -202,7 +259,8 @@ def main():
             xref, it_ref, res_ref = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-13, maxit=2000, ws=kws,
                                                       raise_on_noconv=False)
         probs[p] = dict(dp=dp, v=v, w=w, wacc=torch.zeros_like(v), kws=kws, iws=iws, xref=xref, x=torch.zeros_like(v),
-                        N=dp.A.N, Nq=dp.A.Nq, setup_s=time.perf_counter() - t0)
+                        N=dp.A.N, Nq=dp.A.Nq, n=dp.A.n, setup_s=time.perf_counter() - t0,
+                        v32=v.float(), z32=torch.empty(dp.A.N, dtype=torch.float32, device="cuda"))
         if not args.no_solve:
             planes = 1 if dp.A.k_kind == wqfd.WQ_K_SCALAR else 6
             probs[p].update(lam=torch.zeros_like(v),
@@ -230,7 +288,7 @@ def main():
             f"mixed {probs[p].get('mixed_eq_rtol')}")
 
     stream = torch.cuda.current_stream()
-    rec = {p: dict(apply_ms=[], kernel_ms=[], fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
+    rec = {p: dict(apply_ms=[], kernel_ms=[], fd_ms={"f64": [], "f32": [], "bf16": []}, fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
                    mix_err=[], fp64_eq_ms=[], fp64_eq_err=[], fp64_eq_it=[], mixed_eq_ms=[], mixed_eq_err=[],
                    mixed_eq_it=[], adj_ms=[], adj_it=[], applyT_ms=[]) for p in keys}
     probe = None
@@ -253,6 +311,15 @@ def main():
             for _ in range(args.reps):
                 wqfd.wq_apply_acc(dp.A, P["v"], P["wacc"])
             k1.record(stream)
+            fd_ev = {}
+            for fname, fprec, r_, z_ in (("f64", wqfd.WQ_F64, P["v"], P["w"]), ("f32", wqfd.WQ_F32, P["v32"], P["z32"]),
+                                         ("bf16", wqfd.WQ_BF16, P["v32"], P["z32"])):
+                f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                f0.record(stream)
+                for _ in range(args.reps):
+                    wqfd.fd_apply(dp.P, r_, z_, prec=fprec)
+                f1.record(stream)
+                fd_ev[fname] = (f0, f1)
             if not args.no_solve:
                 P["x"].zero_()
                 s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -298,6 +365,8 @@ def main():
                 r = rec[p]
                 r["apply_ms"] += [e0.elapsed_time(e1) for e0, e1 in evs]
                 r["kernel_ms"] += [k0.elapsed_time(k1) / args.reps] * args.reps
+                for fname, (f0, f1) in fd_ev.items():
+                    r["fd_ms"][fname].append(f0.elapsed_time(f1) / args.reps)
                 if not args.no_solve:
                     nref = torch.linalg.norm(P["xref"]).item()
                     r["fp64_ms"].append(s0.elapsed_time(s1))
@@ -376,6 +445,109 @@ def main():
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # after the timed steps (not part of them): the fused kernel launch by launch
+    # right after a write that evicts the last-level cache
+    flush = None
+    if args.flush_mib > 0:
+        flush = torch.empty((args.flush_mib << 20) // 4, dtype=torch.float32, device="cuda")
+
+    def flushed_kernel_ms(A, v, wacc, prec, reps):
+        out = []
+        for i in range(reps):
+            flush.fill_(float(i))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            wqfd.wq_apply_acc(A, v, wacc, prec=prec)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return out
+
+    flushed = {}
+    if flush is not None:
+        for p in keys:
+            P = probs[p]
+            flushed[p] = flushed_kernel_ms(P["dp"].A, P["v"], P["wacc"], wqfd.WQ_F64, args.reps)
+        log("flushed-cache kernel timings done")
+
+    def fd_times(dp, v64, v32, reps):
+        z64, z32 = torch.empty_like(v64), torch.empty_like(v32)
+        t = {}
+        for fname, fprec, r_, z_ in (("f64", wqfd.WQ_F64, v64, z64), ("f32", wqfd.WQ_F32, v32, z32),
+                                     ("bf16", wqfd.WQ_BF16, v32, z32)):
+            wqfd.fd_apply(dp.P, r_, z_, prec=fprec)
+            f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            f0.record(stream)
+            for _ in range(reps):
+                wqfd.fd_apply(dp.P, r_, z_, prec=fprec)
+            f1.record(stream)
+            torch.cuda.synchronize()
+            t[fname] = f0.elapsed_time(f1) / reps
+        return t
+
+    # out-of-cache workloads: ring 96^3 p = 5 and the twisted cube 128^3 p = 6
+    large = {}
+    if not args.no_large and not args.workloads:
+        for name in ("ring96_p5", "twist128_p6"):
+            wl = synth.workload(name)
+            t0l = time.perf_counter()
+            dpl = problem.build(wl, wqfd.WQ_F64 | wqfd.WQ_F32, wqfd.WQ_F64 | wqfd.WQ_F32 | wqfd.WQ_BF16)
+            torch.cuda.synchronize()
+            setup_l = time.perf_counter() - t0l
+            A = dpl.A
+            vl = torch.as_tensor(synth.random_vector(A.N, 42), device="cuda")
+            vl32 = vl.float()
+            acc64, acc32 = torch.zeros_like(vl), torch.zeros_like(vl32)
+            rec_l = {}
+            for prec, vv, acc, key in ((wqfd.WQ_F64, vl, acc64, "f64"), (wqfd.WQ_F32, vl32, acc32, "f32")):
+                wqfd.wq_apply_acc(A, vv, acc, prec=prec)
+                k0, k1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                k0.record(stream)
+                for _ in range(args.reps):
+                    wqfd.wq_apply_acc(A, vv, acc, prec=prec)
+                k1.record(stream)
+                torch.cuda.synchronize()
+                s_ = 8 if prec == wqfd.WQ_F64 else 4
+                alg = 6 * s_ * A.Nq + 2 * s_ * A.N
+                t_k = k0.elapsed_time(k1) / args.reps
+                rec_l[f"kernel_{key}_ms"] = round(t_k, 4)
+                rec_l[f"kernel_{key}_GBs"] = round(alg / t_k / 1e6, 1)
+                rec_l[f"kernel_{key}_frac_of_hbm_peak"] = round(alg / t_k / 1e6 / HBM_PEAK_GBS, 4)
+                rec_l[f"kernel_{key}_GDOFs"] = round(A.N / t_k / 1e6, 3)
+                if flush is not None:
+                    fl = flushed_kernel_ms(A, vv, acc, prec, max(5, args.reps // 2))
+                    rec_l[f"kernel_{key}_flushed_ms_median"] = round(float(np.median(fl)), 4)
+                    rec_l[f"kernel_{key}_flushed_frac_of_hbm_peak"] = round(
+                        alg / float(np.median(fl)) / 1e6 / HBM_PEAK_GBS, 4)
+            ft = fd_times(dpl, vl, vl32, args.reps)
+            nmax = max(A.n)
+            fl_fd = 12 * nmax * A.N + A.N
+            rec_l["fd_ms"] = {k: round(v_, 4) for k, v_ in ft.items()}
+            rec_l["fd_frac_of_mfma_peak"] = {k: round(fl_fd / (v_ * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[k], 4)
+                                             for k, v_ in ft.items()}
+            if not args.no_solve:
+                kws = torch.empty(wqfd.lib().krylov_ws_bytes(A.handle), dtype=torch.uint8, device="cuda")
+                iws = torch.empty(wqfd.lib().ir_ws_bytes(A.handle), dtype=torch.uint8, device="cuda")
+                xl = torch.zeros_like(vl)
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record(stream)
+                _, it, _ = wqfd.krylov_solve(A, dpl.P, dpl.b, x=xl, rtol=1e-10, maxit=2000, ws=kws)
+                s1.record(stream)
+                xm = torch.zeros_like(vl)
+                m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                m0.record(stream)
+                _, outer, inner, _ = wqfd.ir_solve(A, dpl.P, dpl.b, x=xm, fd_prec=wqfd.WQ_BF16, rtol=1e-10,
+                                                   tau_inner=MIX_TAU, ws=iws)
+                m1.record(stream)
+                torch.cuda.synchronize()
+                rec_l.update({"fp64_solve_ms": round(s0.elapsed_time(s1), 2), "fp64_iters": int(it),
+                              "mixed_bf16_fd_solve_ms": round(m0.elapsed_time(m1), 2), "mixed_outer": int(outer),
+                              "mixed_inner": int(inner),
+                              "mixed_vs_fp64_rel_diff": torch.linalg.norm(xm - xl).item() / torch.linalg.norm(xl).item()})
+            large[name] = dict(N=A.N, Nq=A.Nq, setup_s=round(setup_l, 2), **rec_l)
+            del dpl, A, vl, vl32, acc64, acc32
+            torch.cuda.empty_cache()
+            log(f"large workload {name} done")
     if react is not None:                    # after the timed steps, not part of them
         for i in range(args.warmup + args.steps):
             reaction_step(i >= args.warmup)
@@ -431,7 +603,19 @@ def main():
              "kernel_ms": round(float(np.mean(r["kernel_ms"])), 4),
              "apply_GDOFs": round(probs[p]["N"] / t_ap / 1e6, 3),
              "apply_GBs": round((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) / t_ap / 1e6, 1),
+             "apply_ms_p10": round(float(np.percentile(r["apply_ms"], 10)), 4),
+             "apply_ms_p90": round(float(np.percentile(r["apply_ms"], 90)), 4),
              "setup_s": round(probs[p]["setup_s"], 2)}
+        nmax = max(probs[p]["n"])
+        fl_fd = 12 * nmax * probs[p]["N"] + probs[p]["N"]
+        d["fd_ms"] = {k: round(float(np.mean(v_)), 4) for k, v_ in r["fd_ms"].items()}
+        d["fd_frac_of_mfma_peak"] = {k: round(fl_fd / (float(np.mean(v_)) * 1e-3) / 1e12 / MFMA_PEAK_TFLOPS[k], 4)
+                                     for k, v_ in r["fd_ms"].items()}
+        if p in flushed:
+            t_fl = float(np.median(flushed[p]))
+            d["kernel_flushed_ms_median"] = round(t_fl, 4)
+            d["kernel_flushed_frac_of_hbm_peak"] = round((48 * probs[p]["Nq"] + 16 * probs[p]["N"]) / t_fl / 1e6
+                                                         / HBM_PEAK_GBS, 4)
         if not args.no_solve:
             d.update({"fp64_solve_ms": round(float(np.median(r["fp64_ms"])), 2),
                       "fp64_iters": int(np.median(r["fp64_it"])),
@@ -476,6 +660,18 @@ def main():
                      "bytes_per_launch": "48 N_q + 16 N"},
         "per_degree": per_p,
     }
+    fd_flops = sum((12 * max(probs[p]["n"]) * probs[p]["N"] + probs[p]["N"]) * len(rec[p]["fd_ms"]["f64"]) for p in keys)
+    fd_s = sum(sum(rec[p]["fd_ms"]["f64"]) for p in keys) / 1e3
+    fd_tf = fd_flops / fd_s / 1e12
+    out["roofline_fd"] = {"bound": "mfma", "achieved": round(fd_tf, 3), "peak": MFMA_PEAK_TFLOPS["f64"],
+                          "unit": "TFLOP/s", "frac": round(fd_tf / MFMA_PEAK_TFLOPS["f64"], 4), "dtype": "f64",
+                          "kernel": "fd_xy_pass / fd_z_pass (FP64, one FD application = 3 launches)",
+                          "flops_per_launch": "12 n N + N per application"}
+    all_ap = np.concatenate([np.asarray(rec[p]["apply_ms"]) for p in keys])
+    out["apply_ms_percentiles"] = {"p10_over_mean": round(float(np.percentile(all_ap, 10) / np.mean(all_ap)), 4),
+                                   "p90_over_mean": round(float(np.percentile(all_ap, 90) / np.mean(all_ap)), 4)}
+    if large:
+        out["large_workloads"] = large
     if react is not None:
         R = react
         Nr, Nqr = R["dp"].A.N, R["dp"].A.Nq
@@ -518,7 +714,7 @@ def main():
             "bytes_per_launch": "48 N_q + 16 N", "per_degree": gd}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget, args.cpu_solve_budget)
     print(json.dumps(out))
 
 

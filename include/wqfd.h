@@ -110,14 +110,21 @@ int wq_setup_gauss(int p, const int32_t nknots[3], const double* const knots[3],
                    const double* ctrl, int k_kind, const double* K_q, int prec_mask,
                    void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, wq_op* out);
 
-/* Sizes: n[l] interior functions and nq[l] quadrature points per direction. */
+/* Sizes: n[l] = m_l - 2 interior B-splines of direction l (the homogeneous
+ * Dirichlet space of eq. space, Section 2.1) and nq[l] quadrature points of the
+ * weighted-quadrature rule (Section 2.2; n_q = 2 n_el + 2p + 1, or (p+1) n_el
+ * for wq_setup_gauss).  N = n[0] n[1] n[2], N_q likewise.  Host outputs. */
 int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]);
 
-/* Quadrature points: xq host [nq1 + nq2 + nq3] parametric coordinates (or
- * NULL); Fq device [3][N_q] physical points F(x_q) (or NULL).  Async on s. */
+/* Quadrature points of Section 2.2: xq host [nq1 + nq2 + nq3] parametric
+ * coordinates per direction (or NULL); Fq device [3][N_q] their images under the
+ * geometry map F of Section 2.1 (or NULL), where a caller evaluates K, alpha
+ * and f.  Async on s. */
 int wq_quad_points(wq_op A, double* xq, double* Fq, wq_stream_t s);
 
-/* det J at the quadrature points into device [N_q] (FP64).  Async. */
+/* det J(x_q), J = dF/dxi the Jacobian of the geometry map (Section 2.1), at
+ * the quadrature points into device [N_q] (FP64): the volume factor of the
+ * pulled-back integrands (eq. C; load vector and mass term).  Async on s. */
 int wq_detj(wq_op A, double* detj, wq_stream_t s);
 
 /* Recompute the coefficient planes C = det J J^{-1} K J^{-T} from a new K_q
@@ -134,6 +141,15 @@ int wq_set_coef(wq_op A, int k_kind, const double* K_q, wq_stream_t s);
  * use K~ + M~.  The paper takes alpha >= 0; other values are used as given.
  * Async on s.  Errors: WQ_EINVAL, WQ_EHIP. */
 int wq_set_alpha(wq_op A, const double* alpha_q, wq_stream_t s);
+
+/* Mean over the quadrature points of the reaction diagonal c_q = alpha_q
+ * det J(x_q) of the last wq_set_alpha (host output *mean): the representative
+ * value sigma that fd_set_shift takes to precondition K~ + M~ (the FD
+ * preconditioner of Section 4 with the mass term M3 x M2 x M1 of Section 3.1
+ * added, scaled by one constant; the paper's experiments have alpha = 0).
+ * Deterministic two-pass FP64 sum on the device; synchronises s.
+ * Errors: WQ_EINVAL (null argument, or no reaction coefficient set), WQ_EHIP. */
+int wq_alpha_mean(wq_op A, double* mean, wq_stream_t s);
 
 /* w = M~ v alone: the mass product of Algorithm 1 (values of v at the points,
  * times c_q, the W^(0,0) rules), with the c_q of the last wq_set_alpha.  Runs as
@@ -220,8 +236,10 @@ int fd_apply_noalloc(fd_pc P, int prec, const void* r, void* z, wq_stream_t s);
  * non-positive diagonal), WQ_EHIP. */
 int fd_set_shift(fd_pc P, double sigma, wq_stream_t s);
 
-/* Eigenvalues lam_l (host out, n_l doubles each, may be NULL; without the
- * shift) and eigenvectors U_l (host out, row-major n_l x n_l, may be NULL). */
+/* The 1D factors of the FD preconditioner of Section 4 (fast diagonalization):
+ * eigenvalues lam_l (host out, n_l doubles, may be NULL; without the shift) and
+ * eigenvectors U_l (host out, row-major n_l x n_l, eigenvector k in column k,
+ * may be NULL) of K_l U = M_l U diag(lam), U^T M_l U = I for direction l. */
 int fd_factors(fd_pc P, int l, double* lam, double* U);
 
 void fd_destroy(fd_pc P);
@@ -236,6 +254,9 @@ void fd_destroy(fd_pc P);
  * device-to-host copy).  *iters, *relres: host outputs.
  * Errors: WQ_EINVAL, WQ_ENOMEM, WQ_ENOCONV, WQ_EBREAKDOWN, WQ_ENONFINITE, WQ_EHIP.
  * ------------------------------------------------------------------------ */
+/* krylov_ws_bytes: device workspace bytes krylov_solve needs for A's N (nine
+ * FP64 Krylov vectors of the BiCGStab recurrence of Section 4 and the
+ * reduction partials); 0 for a null handle. */
 size_t krylov_ws_bytes(wq_op A);
 int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x,
                  double rtol, int maxit, void* ws, size_t ws_bytes,
@@ -252,10 +273,21 @@ int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x,
  * ir_ws_bytes(A).  *outer, *inner_total, *relres: host outputs.
  * Errors: as krylov_solve.
  * ------------------------------------------------------------------------ */
+/* ir_ws_bytes: device workspace bytes ir_solve needs for A's N (the FP64
+ * iterate and residual, FP32 copies and the inner BiCGStab workspace); the
+ * refinement loop is an addition to the paper's FP64 method.  0 for null. */
 size_t ir_ws_bytes(wq_op A);
 int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double rtol,
              double tau_inner, int max_outer, int maxit_inner, void* ws, size_t ws_bytes,
              int* outer, int* inner_total, double* relres, wq_stream_t s);
+
+/* Stagnation fallback of ir_solve: an outer step that does not halve the FP64
+ * residual switches the remaining inner solves of that call to FP64 (FP64
+ * apply, FP64 FD: the plain method of Section 4 on the residual equation,
+ * solved to the accuracy the outer target needs), provided the preconditioner
+ * has WQ_F64 prepared; *outer and *inner_total count those steps too.  This
+ * returns how many ir_solve calls of the calling thread have switched so far. */
+int ir_fallback_count(void);
 
 /* ------------------------------------------------------------------------ *
  * Host-only inspection of the set-up (no device work; for checks and tools).

@@ -36,6 +36,7 @@ SIGNATURES = [
     ("wq_apply_T", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_apply_acc", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_set_alpha", C.c_int, [_vp, _vp, _vp]),
+    ("wq_alpha_mean", C.c_int, [_vp, _dp, _vp]),
     ("wq_apply_mass", C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
     ("wq_rhs", C.c_int, [_vp, _vp, _vp, _vp]),
     ("wq_grad_K", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
@@ -55,6 +56,7 @@ SIGNATURES = [
     ("ir_ws_bytes", C.c_size_t, [_vp]),
     ("ir_solve", C.c_int, [_vp, _vp, C.c_int, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp,
                            C.c_size_t, _ip, _ip, _dp, _vp]),
+    ("ir_fallback_count", C.c_int, []),
     ("wq_space_1d", C.c_int, [C.c_int, C.c_int, _vp, _i32p, _i32p, _vp, _vp, _vp]),
     ("fd_eig_1d", C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp]),
     ("wq_geometry_host", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, _vp, _vp]),

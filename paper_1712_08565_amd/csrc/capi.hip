@@ -28,6 +28,7 @@ struct fd_pc_s {
 namespace {
 
 thread_local std::string g_err;
+thread_local int g_ir_fallbacks = 0;       // ir_solve calls of this thread that switched to FP64 inner solves
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -590,6 +591,8 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
     const size_t o_scr = off;
     o.scratch_bytes = wqfd::wq_scratch_bytes(o, prec_mask);
     off += al256(o.scratch_bytes);
+    const size_t o_red = off;
+    off += al256(wqfd::norm2_ws_bytes());
     if (ws_needed) *ws_needed = off;
     if (!ws) return WQ_OK;
     if (ws_bytes < off) return fail(WQ_ENOMEM, "workspace too small for wq_setup");
@@ -610,6 +613,7 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
     o.Cm64 = reinterpret_cast<double*>(base + o_cm64);
     o.Cm32 = (prec_mask & WQ_F32) ? reinterpret_cast<float*>(base + o_cm32) : nullptr;
     o.scratch = base + o_scr;
+    o.red = base + o_red;
     HIP_TRY(hipMemcpyAsync(o.detJ, hdet.data(), o.Nq * 8, hipMemcpyHostToDevice, s), "upload detJ");
     HIP_TRY(hipMemcpyAsync(o.Jinv, hjinv.data(), 9 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload Jinv");
     HIP_TRY(hipMemcpyAsync(o.F, hF.data(), 3 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload F");
@@ -734,6 +738,17 @@ int wq_set_alpha(wq_op A, const double* alpha_q, wq_stream_t s) {
     }
     HIP_TRY(wqfd::launch_set_alpha(A->op, alpha_q, reinterpret_cast<hipStream_t>(s)), "set_alpha");
     A->op.mass = true;
+    return WQ_OK;
+}
+
+int wq_alpha_mean(wq_op A, double* mean, wq_stream_t s) {
+    if (!A || !mean) return fail(WQ_EINVAL, "null argument");
+    if (!A->op.mass) return fail(WQ_EINVAL, "no reaction coefficient set (wq_set_alpha)");
+    std::string err;
+    double sum = 0.0;
+    if (wqfd::sum_all(A->op.Cm64, A->op.Nq, A->op.red, &sum, err, reinterpret_cast<hipStream_t>(s)))
+        return fail(WQ_EHIP, "wq_alpha_mean: " + err);
+    *mean = sum / (double)A->op.Nq;
     return WQ_OK;
 }
 
@@ -1046,8 +1061,11 @@ int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x, do
 size_t ir_ws_bytes(wq_op A) {
     if (!A) return 0;
     const size_t N = A->op.N;
-    return al256(N * 8) * 2 + al256(N * 4) * 2 + al256(wqfd::krylov_bytes(N, true)) + al256(wqfd::norm2_ws_bytes());
+    // the inner BiCGStab workspace is sized for FP64, which the stagnation fallback uses
+    return al256(N * 8) * 2 + al256(N * 4) * 2 + al256(wqfd::krylov_bytes(N, false)) + al256(wqfd::norm2_ws_bytes());
 }
+
+int ir_fallback_count(void) { return g_ir_fallbacks; }
 
 int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double rtol, double tau_inner, int max_outer,
              int maxit_inner, void* ws, size_t ws_bytes, int* outer, int* inner_total, double* relres,
@@ -1074,8 +1092,9 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     c += al256(N * 4);
     float* d32 = reinterpret_cast<float*>(c);
     c += al256(N * 4);
+    double* d64 = reinterpret_cast<double*>(b32);   // FP64 inner solution: the FP32 pair's space (2 al256(4N) >= 8N)
     void* kws = c;
-    c += al256(wqfd::krylov_bytes(N, true));
+    c += al256(wqfd::krylov_bytes(N, false));
     void* nws = c;
     wqfd::LinOp A32 = [op](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_apply(*op, WQ_F32, in, o, false, st);
@@ -1086,6 +1105,18 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     wqfd::LinOp M32 = [pc, fd_prec](const void* in, void* o, hipStream_t st) {
         return wqfd::launch_fd_apply(*pc, fd_prec, in, o, st);
     };
+    // stagnation fallback: FP64 inner solves (FP64 apply, FP64 FD)
+    wqfd::LinOp A64 = [op](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F64, in, o, false, st);
+    };
+    wqfd::LinOp A64acc = [op](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_apply(*op, WQ_F64, in, o, false, st, true);
+    };
+    wqfd::LinOp M64 = [pc](const void* in, void* o, hipStream_t st) {
+        return wqfd::launch_fd_apply(*pc, WQ_F64, in, o, st);
+    };
+    const bool can_fall_back = (pc->prec_mask & WQ_F64) != 0;
+    bool fp64_inner = false;
     std::string err;
     double nb = 0, nr = 0;
     int rc = wqfd::norm2(b, N, nws, &nb, err, s);
@@ -1113,19 +1144,39 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
     while (true) {
         if (!std::isfinite(nr)) return fail(WQ_ENONFINITE, "non-finite residual in iterative refinement");
         if (nr / nb <= rtol || *outer >= max_outer) break;
-        HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
         int it = 0;
         double rel = 0;
-        const double tol = std::max(tau_inner, 0.5 * rtol * nb / nr);
-        rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s,
-                                   op->fused ? &A32acc : nullptr);
-        *inner_total += it;
-        if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
-        HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");
+        const double nr_before = nr;
+        if (!fp64_inner) {
+            HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
+            const double tol = std::max(tau_inner, 0.5 * rtol * nb / nr);
+            rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s,
+                                       op->fused ? &A32acc : nullptr);
+            *inner_total += it;
+            if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
+            HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");
+        } else {
+            // the residual equation solved in FP64 to the accuracy the outer target needs
+            HIP_TRY(hipMemcpyAsync(t64, r64, N * 8, hipMemcpyDeviceToDevice, s), "ir copy");
+            const double tol = std::max(0.5 * rtol * nb / nr, 1e-14);
+            rc = wqfd::bicgstab<double>(A64, M64, N, t64, d64, true, tol, maxit_inner, kws, &it, &rel, err, s,
+                                        op->fused ? &A64acc : nullptr);
+            *inner_total += it;
+            if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
+            HIP_TRY(wqfd::launch_axpy_f64(d64, x, N, 1.0, s), "ir update");
+        }
         ++*outer;
         rc = residual();
         if (rc) return rc;
         *relres = nr / nb;
+        // stagnation: an outer step that does not halve the FP64 residual means the
+        // low-precision inner solve no longer yields a useful correction (FP32
+        // operator error against the conditioning, or an inner tolerance too loose);
+        // the remaining steps solve the residual equation in FP64
+        if (!fp64_inner && can_fall_back && std::isfinite(nr) && nr > 0.5 * nr_before) {
+            fp64_inner = true;
+            ++g_ir_fallbacks;
+        }
     }
     if (nr / nb > rtol) return fail(WQ_ENOCONV, "iterative refinement reached max_outer");
     return WQ_OK;

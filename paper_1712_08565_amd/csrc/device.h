@@ -55,6 +55,7 @@ struct WqOp {
     bool mass = false;          // reaction term set (wq_set_alpha)
     void* scratch = nullptr;    // apply intermediates (bytes: scratch_bytes)
     size_t scratch_bytes = 0;
+    void* red = nullptr;        // reduction partials (norm2_ws_bytes())
     OpTables<double> t64;
     OpTables<float> t32;
     bool fused = false;         // fused apply available (p <= 7 and tile footprints fit)
@@ -111,5 +112,6 @@ inline hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* 
 // BLAS-1 helpers for the Krylov drivers (blas1.hip)
 hipError_t launch_cast_f64_to_f32(const double* x, float* y, size_t n, double scale, hipStream_t s);
 hipError_t launch_axpy_f32_to_f64(const float* d, double* x, size_t n, double scale, hipStream_t s);
+hipError_t launch_axpy_f64(const double* d, double* x, size_t n, double scale, hipStream_t s);
 
 }  // namespace wqfd

@@ -42,7 +42,25 @@ struct FdFusedArgs {
     int ldp = 0;                     // U, UT: zero-padded ldp x ldp, ldp = 16 ceil(max n / 16)
 };
 
+// BF16 operands (FP32 data and accumulation), the same three passes; Tf[l] / Tb[l]
+// are the bf16 T = U^T / T = U of fd_setup, row-major, zero padded to ld[l]
+// (a multiple of 64) in both dimensions; n <= 160.
+struct FdFusedBf16Args {
+    const float* r = nullptr;
+    float* z = nullptr;
+    float* tmp = nullptr;
+    const __bf16* Tf[3] = {nullptr, nullptr, nullptr};
+    const __bf16* Tb[3] = {nullptr, nullptr, nullptr};
+    int ld[3] = {0, 0, 0};
+    int n[3] = {0, 0, 0};
+    const double* l1 = nullptr;
+    const double* l2 = nullptr;
+    const double* l3 = nullptr;
+    int n1 = 0, n2 = 0, n3 = 0;
+};
+
 hipError_t launch_fd_fused(const FdFusedArgs<double>& f, hipStream_t s);
+hipError_t launch_fd_fused_bf16(const FdFusedBf16Args& f, hipStream_t s);
 hipError_t launch_fd_fused(const FdFusedArgs<float>& f, hipStream_t s);
 
 hipError_t launch_fd_mode(const FdModeArgs<double, double>& p, hipStream_t s);

@@ -352,6 +352,173 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 variant of the fused passes: FP32 data, bf16 operands rounded as they are
+// loaded, FP32 accumulation, v_mfma_f32_16x16x32_bf16 (k-step s covers
+// k = 32 s + 8 kb + e, e = 0..7, so an operand is eight consecutive values of a
+// row).  The matrices are the bf16 copies of fd_setup: T = U^T and T = U,
+// row-major and zero padded to ld = 64 ceil(n / 64) in both dimensions (rows
+// and columns past n are zero, so clamped data rows and columns contribute
+// nothing).  Intermediates go through LDS in FP32, stored so that every MFMA
+// operand is one 16-byte read.  NS = ceil(n / 32) steps (at most NSM); the
+// workgroup has 2 NSM waves, waves past ceil(n / 16) only join the barrier.
+__device__ inline bf8 to_bf8(const float (&x)[8]) {
+    bf8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (__bf16)x[e];
+    return r;
+}
+
+__device__ inline bf8 lds_bf8(const float* p) {             // 8 consecutive FP32 values, 16-byte aligned
+    const float4 lo = *reinterpret_cast<const float4*>(p), hi = *reinterpret_cast<const float4*>(p + 4);
+    const float x[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    return to_bf8(x);
+}
+
+__device__ inline bf8 mat_bf8(const __bf16* T, int ld, int row, int k0) {
+    return *reinterpret_cast<const bf8*>(T + (size_t)row * ld + k0);
+}
+
+// xy pass: per z-plane and 16-row block of i2,
+//   Q[i2][j1] = sum_j2 T2[i2][j2] in[z][j2][j1],   out[z][i2][i1] = sum_j1 Q[i2][j1] T1[i1][j1]
+template <int NSM>
+__global__ __launch_bounds__(128 * NSM) void fd_xy_pass_bf16(const float* __restrict__ in, float* __restrict__ out,
+                                                            const __bf16* __restrict__ T1, const __bf16* __restrict__ T2,
+                                                            int ld1, int ld2, int n1, int n2) {
+    constexpr int LDQ = 32 * NSM + 4;                    // row of Q in LDS (16-byte aligned rows)
+    __shared__ __align__(16) float sQ[16 * LDQ];
+    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int r0 = blockIdx.x * 16, z = blockIdx.y;
+    const size_t pbase = (size_t)z * n1 * n2;
+    const int kb1 = (n1 + 15) >> 4;                      // waves with columns j1 / i1
+    const int ns1 = (n1 + 31) >> 5, ns2 = (n2 + 31) >> 5;
+    const bool active = t < kb1;                         // wave-uniform
+    const int jc = 16 * t + cl, jcc = min(jc, n1 - 1);
+    // columns of Q past the last wave's block are read by the second product
+    // (multiplied by zero padding of T1): clear them
+    for (int idx = threadIdx.x; idx < 16 * (32 * ns1 - 16 * kb1); idx += blockDim.x) {
+        const int w = 32 * ns1 - 16 * kb1;
+        sQ[(idx / w) * LDQ + 16 * kb1 + idx % w] = 0.0f;
+    }
+    if (active) {
+        f4 q = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) {
+            if (s < ns2) {
+                const bf8 a = mat_bf8(T2, ld2, r0 + cl, 32 * s + 8 * kb);
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = in[pbase + (size_t)min(32 * s + 8 * kb + e, n2 - 1) * n1 + jcc];
+                q = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, to_bf8(x), q, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sQ[(4 * kb + v) * LDQ + jc] = q[v];
+    }
+    __syncthreads();
+    if (!active) return;
+    f4 r = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+        if (s < ns1) {
+            const bf8 a = lds_bf8(sQ + cl * LDQ + 32 * s + 8 * kb);
+            const bf8 b = mat_bf8(T1, ld1, jc, 32 * s + 8 * kb);
+            r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, r, 0, 0, 0);
+        }
+    }
+    if (jc < n1) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i2 = r0 + 4 * kb + v;
+            if (i2 < n2) out[pbase + (size_t)i2 * n1 + jc] = r[v];
+        }
+    }
+}
+
+// z pass: per 16-column block of g = (i2, i1),
+//   Y[i3][g] = sum_j3 T3f[i3][j3] in[j3][g] / (l1[i1] + l2[i2] + l3[i3]),   out[i3][g] = sum_j3 T3b[i3][j3] Y[j3][g]
+// (Y kept transposed in LDS; every read of `in` precedes the block's writes, so in may be out)
+template <int NSM>
+__global__ __launch_bounds__(128 * NSM) void fd_z_pass_bf16(const float* in, float* out, const __bf16* __restrict__ Tf,
+                                                           const __bf16* __restrict__ Tb, int ld3,
+                                                           const double* __restrict__ l1, const double* __restrict__ l2,
+                                                           const double* __restrict__ l3, int n1, int n2, int n3) {
+    constexpr int LDY = 32 * NSM + 4;
+    __shared__ __align__(16) float sY[16 * LDY];         // Y^T: [column g][i3]
+    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int cl = lane & 15, kb = lane >> 4;
+    const int C = n1 * n2;
+    const int g = blockIdx.x * 16 + cl;
+    const bool gin = g < C;
+    const int gc = min(g, C - 1);
+    const int kb3 = (n3 + 15) >> 4, ns3 = (n3 + 31) >> 5;
+    const bool active = t < kb3;
+    const int i3r = 16 * t + cl;
+    for (int idx = threadIdx.x; idx < 16 * (32 * ns3 - 16 * kb3); idx += blockDim.x) {
+        const int w = 32 * ns3 - 16 * kb3;
+        sY[(idx / w) * LDY + 16 * kb3 + idx % w] = 0.0f;
+    }
+    if (active) {
+        f4 y = f4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < NSM; ++s) {
+            if (s < ns3) {
+                const bf8 a = mat_bf8(Tf, ld3, i3r, 32 * s + 8 * kb);
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = in[(size_t)min(32 * s + 8 * kb + e, n3 - 1) * C + gc];
+                y = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, to_bf8(x), y, 0, 0, 0);
+            }
+        }
+        double l12 = 0.0;
+        if (gin) {
+            const int i2 = g / n1, i1 = g - i2 * n1;
+            l12 = l1[i1] + l2[i2];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i3 = 16 * t + 4 * kb + v;
+            sY[cl * LDY + i3] = (gin && i3 < n3) ? (float)((double)y[v] / (l12 + l3[i3])) : 0.0f;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    f4 o = f4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < NSM; ++s) {
+        if (s < ns3) {
+            const bf8 a = mat_bf8(Tb, ld3, i3r, 32 * s + 8 * kb);
+            const bf8 b = lds_bf8(sY + cl * LDY + 32 * s + 8 * kb);
+            o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, o, 0, 0, 0);
+        }
+    }
+    if (gin) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i3 = 16 * t + 4 * kb + v;
+            if (i3 < n3) out[(size_t)i3 * C + g] = o[v];
+        }
+    }
+}
+
+template <int NSM>
+hipError_t fused_bf16_ns(const FdFusedBf16Args& f, hipStream_t s) {
+    hipError_t e;
+    const dim3 blk(128 * NSM);
+    const dim3 gxy((f.n2 + 15) / 16, f.n3);
+    const dim3 gz((f.n1 * f.n2 + 15) / 16);
+    hipLaunchKernelGGL(fd_xy_pass_bf16<NSM>, gxy, blk, 0, s, f.r, f.tmp, f.Tf[0], f.Tf[1], f.ld[0], f.ld[1], f.n1,
+                       f.n2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(fd_z_pass_bf16<NSM>, gz, blk, 0, s, (const float*)f.tmp, f.tmp, f.Tf[2], f.Tb[2], f.ld[2],
+                       f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(fd_xy_pass_bf16<NSM>, gxy, blk, 0, s, (const float*)f.tmp, f.z, f.Tb[0], f.Tb[1], f.ld[0],
+                       f.ld[1], f.n1, f.n2);
+    return hipGetLastError();
+}
+
 template <int PREC, int KB, int NP>
 hipError_t fused_np(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
     using T = typename G<PREC>::T;
@@ -424,6 +591,19 @@ hipError_t launch_fd_mode(const FdModeArgs<double, double>& p, hipStream_t s) { 
 hipError_t launch_fd_mode(const FdModeArgs<float, float>& p, hipStream_t s) { return launch_any<2>(p, s); }
 hipError_t launch_fd_mode(const FdModeArgs<float, __bf16>& p, hipStream_t s) { return launch_any<4>(p, s); }
 hipError_t launch_fd_fused(const FdFusedArgs<double>& f, hipStream_t s) { return fused_any<1>(f, s); }
+hipError_t launch_fd_fused_bf16(const FdFusedBf16Args& f, hipStream_t s) {
+    const int nmax = f.n1 > f.n2 ? (f.n1 > f.n3 ? f.n1 : f.n3) : (f.n2 > f.n3 ? f.n2 : f.n3);
+    for (int l = 0; l < 3; ++l)
+        if (f.ld[l] % 64 || f.ld[l] < 32 * ((f.n[l] + 31) / 32)) return hipErrorInvalidValue;
+    switch ((nmax + 31) / 32) {
+        case 1: return fused_bf16_ns<1>(f, s);
+        case 2: return fused_bf16_ns<2>(f, s);
+        case 3: return fused_bf16_ns<3>(f, s);
+        case 4: return fused_bf16_ns<4>(f, s);
+        case 5: return fused_bf16_ns<5>(f, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 hipError_t launch_fd_fused(const FdFusedArgs<float>& f, hipStream_t s) { return fused_any<2>(f, s); }
 
 }  // namespace wqfd

@@ -395,6 +395,25 @@ hipError_t launch_fd_apply(const FdPc& P, int prec, const void* r, void* z, void
         f.ldp = P.ldp;
         return launch_fd_fused(f, s);
     }
+    if (small && prec == 4 && !std::getenv("WQFD_FD_MODES")) {
+        FdFusedBf16Args f;
+        f.r = static_cast<const float*>(r);
+        f.z = static_cast<float*>(z);
+        f.tmp = reinterpret_cast<float*>(scratch);
+        for (int l = 0; l < 3; ++l) {
+            f.ld[l] = (P.n[l] + 63) / 64 * 64;              // as stored by fd_setup
+            f.n[l] = P.n[l];
+            f.Tf[l] = reinterpret_cast<const __bf16*>(P.Ubf[l]);
+            f.Tb[l] = f.Tf[l] + (size_t)f.ld[l] * f.ld[l];
+        }
+        f.l1 = P.lam[0];
+        f.l2 = P.lam[1];
+        f.l3 = P.lam[2];
+        f.n1 = P.n[0];
+        f.n2 = P.n[1];
+        f.n3 = P.n[2];
+        return launch_fd_fused_bf16(f, s);
+    }
     if (small) {
         if (prec == 1) {
             const double* Tf[3] = {P.UT64[0], P.UT64[1], P.UT64[2]};

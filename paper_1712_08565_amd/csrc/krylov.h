@@ -24,6 +24,8 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
 
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s);
 size_t norm2_ws_bytes();
+// sum of x[0..N) into *out (host); part_ws: norm2_ws_bytes() of device memory
+int sum_all(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s);
 hipError_t launch_resid(const double* b, double* y, size_t n, hipStream_t s);
 hipError_t launch_fill0_f32(float* x, size_t n, hipStream_t s);
 

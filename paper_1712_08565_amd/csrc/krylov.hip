@@ -73,6 +73,15 @@ __global__ __launch_bounds__(kT) void dot_partial(const T* __restrict__ x0, cons
     }
 }
 
+// partial sums of x (one per block, fixed partition)
+__global__ __launch_bounds__(kT) void sum_partial(const double* __restrict__ x, size_t n, double* __restrict__ part) {
+    __shared__ double sh[kT / 64];
+    double a = 0;
+    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) a += x[i];
+    const double r = block_sum(a, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
 // single block: sum the partials of K dots and update the scalar block
 template <int K>
 __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
@@ -208,7 +217,8 @@ __global__ __launch_bounds__(kT) void cast_kernel(const double* __restrict__ x, 
         y[i] = (float)(x[i] * scale);
 }
 
-__global__ __launch_bounds__(kT) void axpy_kernel(const float* __restrict__ d, double* __restrict__ x, size_t n,
+template <typename D>
+__global__ __launch_bounds__(kT) void axpy_kernel(const D* __restrict__ d, double* __restrict__ x, size_t n,
                                                   double scale) {
     for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT)
         x[i] += scale * (double)d[i];
@@ -273,7 +283,12 @@ hipError_t launch_cast_f64_to_f32(const double* x, float* y, size_t n, double sc
 }
 
 hipError_t launch_axpy_f32_to_f64(const float* d, double* x, size_t n, double scale, hipStream_t s) {
-    hipLaunchKernelGGL(axpy_kernel, dim3(nblocks(n)), dim3(kT), 0, s, d, x, n, scale);
+    hipLaunchKernelGGL(axpy_kernel<float>, dim3(nblocks(n)), dim3(kT), 0, s, d, x, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_f64(const double* d, double* x, size_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_kernel<double>, dim3(nblocks(n)), dim3(kT), 0, s, d, x, n, scale);
     return hipGetLastError();
 }
 
@@ -407,6 +422,20 @@ int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& er
 }
 
 size_t norm2_ws_bytes() { return (3 * kMaxBlocks + 64) * sizeof(double); }
+
+// FP64 sum of a vector (two-pass, fixed order), synchronising.
+int sum_all(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s) {
+    double* part = reinterpret_cast<double*>(part_ws);
+    double* sc = part + 3 * kMaxBlocks;
+    const int nb = nblocks(N);
+    hipLaunchKernelGGL(sum_partial, dim3(nb), dim3(kT), 0, s, x, N, part);
+    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE);
+    double h = 0.0;
+    KR_TRY(hipMemcpyAsync(&h, sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    KR_TRY(hipStreamSynchronize(s));
+    *out = h;
+    return 0;
+}
 
 hipError_t launch_resid(const double* b, double* y, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(resid<double>, dim3(nblocks(n)), dim3(kT), 0, s, b, y, n);

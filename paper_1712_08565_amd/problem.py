@@ -53,7 +53,7 @@ def build(wl, prec_mask: int = WQ_F64, fd_prec_mask: int = WQ_F64, device="cuda"
 def set_reaction(dp: DeviceProblem, alpha_fn, stream=None) -> tuple:
     """Reaction term alpha u of the model problem: alpha_fn evaluated at the
     physical quadrature points goes to the operator (wq_set_alpha), and the FD
-    preconditioner gets the shift mean(alpha det J) (fd_set_shift).  Returns
+    preconditioner gets the shift mean(alpha det J) (wq_alpha_mean, fd_set_shift).  Returns
     (alpha_q, sigma); alpha_fn = None removes both."""
     if alpha_fn is None:
         wqfd.wq_set_alpha(dp.A, None, stream)
@@ -61,6 +61,6 @@ def set_reaction(dp: DeviceProblem, alpha_fn, stream=None) -> tuple:
         return None, 0.0
     alpha_q = alpha_fn(dp.Fq.t()).contiguous()
     wqfd.wq_set_alpha(dp.A, alpha_q, stream)
-    sigma = float((alpha_q * wqfd.wq_detj(dp.A, stream)).mean())
+    sigma = wqfd.wq_alpha_mean(dp.A, stream)
     wqfd.fd_set_shift(dp.P, sigma, stream)
     return alpha_q, sigma

@@ -16,8 +16,8 @@ from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_FD_NOALLOC_BYTES, WQ_K_IDENTITY, 
 
 __all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
            "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f",
-           "wq_grad_alpha", "fd_setup", "fd_apply", "fd_apply_noalloc", "fd_set_shift", "fd_factors",
-           "krylov_solve", "ir_solve", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
+           "wq_grad_alpha", "wq_alpha_mean", "fd_setup", "fd_apply", "fd_apply_noalloc", "fd_set_shift", "fd_factors",
+           "krylov_solve", "ir_solve", "ir_fallback_count", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
            "WQ_K_SYM6", "WQError"]
 
 _DT = {WQ_F64: torch.float64, WQ_F32: torch.float32, WQ_BF16: torch.float32}
@@ -189,6 +189,14 @@ def wq_apply_acc(op: WqOp, v: torch.Tensor, w: torch.Tensor, prec: Optional[int]
     return _apply(lib().wq_apply_acc, "wq_apply_acc", op, v, w, prec, stream)
 
 
+def wq_alpha_mean(op: WqOp, stream=None) -> float:
+    """Mean of the reaction diagonal alpha det J over the quadrature points (the
+    FD shift of the reaction term), computed by the library."""
+    m = C.c_double(0.0)
+    check(lib().wq_alpha_mean(op.handle, C.byref(m), _stream(stream)), "wq_alpha_mean")
+    return m.value
+
+
 def wq_apply_mass(op: WqOp, v: torch.Tensor, w: Optional[torch.Tensor] = None, prec: Optional[int] = None,
                   stream=None) -> torch.Tensor:
     """w = M~ v (Algorithm 1) for the reaction coefficient set by wq_set_alpha."""
@@ -309,3 +317,9 @@ def ir_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None
     check(lib().ir_solve(A.handle, P.handle, fd_prec, _p(b), _p(x), rtol, tau_inner, max_outer, maxit_inner, _p(ws),
                          wsb, C.byref(outer), C.byref(inner), C.byref(rel), _stream(stream)), "ir_solve")
     return x, outer.value, inner.value, rel.value
+
+
+def ir_fallback_count() -> int:
+    """Number of ir_solve calls of this thread that switched to FP64 inner
+    solves after a stagnating outer step."""
+    return int(lib().ir_fallback_count())

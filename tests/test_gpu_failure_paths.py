@@ -1,7 +1,9 @@
 """Failure handling and the deterministic mode, forced from the host (no kernel
 is made to fault): the iteration limit (WQ_ENOCONV, last iterate returned), a
 non-finite right-hand side (WQ_ENONFINITE, in BiCGStab and in the refinement
-loop), a zero right-hand side (x = 0 at once), and operators built with
+loop), a zero right-hand side (x = 0 at once), the refinement loop's stagnation
+fallback to FP64 inner solves (forced by an inner tolerance that makes the FP32
+inner solves return a zero correction), and operators built with
 WQFD_STAGED=1, whose staged kernels give one writer per output and so
 bit-for-bit repeatable applies."""
 import os
@@ -95,3 +97,27 @@ def test_staged_mode_is_bitwise_repeatable():
     e = float(np.linalg.norm(ws[0].cpu().numpy() - pr.apply(v.cpu().numpy())) / np.linalg.norm(pr.apply(v.cpu().numpy())))
     print(f"[staged] fused vs staged {d:.1e}, staged vs oracle {e:.1e}")
     assert d <= 1e-14 and e <= 1e-12, (d, e)
+
+
+def test_ir_stagnation_switches_to_fp64_inner_solves():
+    """tau_inner = 2: every FP32 inner solve returns at once with a zero
+    correction, so the first outer step leaves the FP64 residual unchanged; the
+    loop then solves the residual equation in FP64 and reaches the target,
+    against the oracle's refined reference (<= 1e-10).  A normal refinement
+    does not switch."""
+    import sys
+    from paper_1712_08565_amd import wqfd
+    from paper_1712_08565_amd.wqfd import WQ_F32
+    sys.path.insert(0, os.path.dirname(__file__))
+    from parity_gates import norm_rel, reference_solve
+    wl, dp = setup("ring8_p4")
+    c0 = wqfd.ir_fallback_count()
+    x, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, fd_prec=WQ_F32, rtol=1e-12, tau_inner=1e-4)
+    assert res <= 1e-12 and wqfd.ir_fallback_count() == c0, (res, wqfd.ir_fallback_count(), c0)
+    xs, outer_s, inner_s, res_s = wqfd.ir_solve(dp.A, dp.P, dp.b, fd_prec=WQ_F32, rtol=1e-12, tau_inner=2.0)
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    b = pr.rhs_from(wl.f())
+    e = norm_rel(xs.cpu().numpy(), reference_solve(pr, b))
+    print(f"[ir fallback] outer {outer_s}, inner {inner_s}, relres {res_s:.2e}, error vs reference {e:.2e}")
+    assert wqfd.ir_fallback_count() == c0 + 1
+    assert outer_s >= 2 and res_s <= 1e-12 and e <= 1e-10, (outer_s, res_s, e)

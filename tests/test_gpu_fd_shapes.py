@@ -2,35 +2,44 @@
 direction (the fused passes split planes and columns by direction, so square
 planes would hide a swapped extent).  Reference: the oracle's FD application
 (Section 3.3, the eigen-decomposition form of the Kronecker-product
-preconditioner), FP64 to 1e-12 relative, FP32 to 1e-5, also in place."""
+preconditioner), element by element: FP64 max |d_i| <= 1e-12 max |ref_i|, FP32
+<= 1e-5, BF16 operands <= 5e-2 (stated), also in place; non-uniform knots in one
+case."""
 import numpy as np
 import pytest
 
 import synth
 from oracle.fd import FD
 from oracle.wq import Space1D
+from parity_gates import max_rel
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("els", [(5, 19, 40), (40, 19, 5), (70, 13, 30), (13, 97, 9), (9, 130, 17)])
+@pytest.mark.parametrize("els", [(5, 19, 40), (40, 19, 5), (70, 13, 30), (13, 97, 9), (9, 130, 17), "nu"])
 def test_fd_parity_box(els):
     import torch
     from paper_1712_08565_amd import wqfd
     p = 3
-    knots = [synth.uniform_knots(e, p) for e in els]
+    if els == "nu":
+        knots = [synth.nonuniform_knots(e, p, 400 + e) for e in (11, 37, 23)]
+    else:
+        knots = [synth.uniform_knots(e, p) for e in els]
     fd = FD([Space1D(k, p) for k in knots])
-    P = wqfd.fd_setup(p, knots, wqfd.WQ_F64 | wqfd.WQ_F32)
+    P = wqfd.fd_setup(p, knots, wqfd.WQ_F64 | wqfd.WQ_F32 | wqfd.WQ_BF16)
     N = int(np.prod(P.n))
     r = synth.random_vector(N, 46)
     ref = fd.apply(r)
-    print(f"[fd box] elements {els}: n = {P.n}", flush=True)
+    print(f"[fd box] {els}: n = {P.n}", flush=True)
     x = torch.as_tensor(r, device="cuda")
     z = wqfd.fd_apply(P, x).cpu().numpy()
     z32 = wqfd.fd_apply(P, x.float(), prec=wqfd.WQ_F32).double().cpu().numpy()
-    e = np.linalg.norm(z - ref) / np.linalg.norm(ref)
-    e32 = np.linalg.norm(z32 - ref) / np.linalg.norm(ref)
-    assert e <= 1e-12 and e32 <= 1e-5, (e, e32)
+    zbf = wqfd.fd_apply(P, x.float(), prec=wqfd.WQ_BF16).double().cpu().numpy()
+    e = max_rel(z, ref)
+    e32 = max_rel(z32, ref)
+    ebf = max_rel(zbf, ref)
+    print(f"[fd box] max entry error / max |ref|: fp64 {e:.2e}, fp32 {e32:.2e}, bf16 {ebf:.2e}")
+    assert e <= 1e-12 and e32 <= 1e-5 and ebf <= 5e-2, (e, e32, ebf)
     wqfd.fd_apply(P, x, x)                                   # in place
-    e_in = np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)
+    e_in = max_rel(x.cpu().numpy(), ref)
     assert e_in <= 1e-12, e_in

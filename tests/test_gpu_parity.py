@@ -1,12 +1,17 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU FP64 oracle on
-the same seeded inputs.  Gates:
-  FP64 apply / apply_T / FD / rhs: |d|_2 / |ref|_2 <= 1e-12 (random N(0,1) inputs)
-  FP64 solves: relative error vs the oracle's direct solve <= 1e-10, with the
-     solve run to a residual tight enough for that to be attainable (reading
-     R10: a residual of 1e-10 alone does not bound the error by 1e-10); where
-     cond(K~) makes 1e-10 unattainable in FP64 the oracle's own residual of the
-     GPU solution is gated instead and the error bound cond * residual is checked.
+the same seeded inputs.  Gates (element by element, see parity_gates.py):
+  FP64 apply / apply_T / FD / rhs: max |d_i| <= 1e-12 max |ref_i| on N(0,1)
+     inputs (reading R11); for a smooth input, whose K~ v is small against the
+     rounding of its terms, |d_i| <= 1e-12 times the entry's rounding scale
+     (the oracle's chain on absolute values).
+  FP64 solves: relative error <= 1e-10 (reading R10) against the oracle's
+     reference solution: FP64 BiCGStab refined with extended-precision residuals
+     of the matrix-free operator, which is accurate to about 1e-13 even where
+     cond(K~) ~ 1e7 (twist6_p6) and FP64 residuals alone are not.
   FP32 / BF16 results: error stated (bounds are about ten times the observed error).
+Non-uniform knots (element lengths within a factor 4, different per direction)
+run through the same cases: the fused kernels (p <= 7, one and several tiles)
+and the staged ones (p = 8).
 """
 import numpy as np
 import pytest
@@ -15,11 +20,14 @@ import scipy.sparse.linalg as spla
 import synth
 from oracle.fd import FD
 from oracle.operator import Problem
+from parity_gates import max_rel, norm_rel, oracle_fp64_solve_error, per_entry, reference_solve
 
 pytestmark = pytest.mark.gpu
 
 APPLY_CASES = ["cube12_p3", "ring8_p2", "ring8_p3", "ring8_p4", "ring8_p5", "ring8_p6", "ring7_p4_kappa",
-               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7", "ring5_p10"]
+               "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7", "ring5_p10",
+               "ring8nu_p2", "ring8nu_p3", "ring8nu_p4", "ring8nu_p5", "ring8nu_p6", "ring20nu_p6", "ring6nu_p8",
+               "twist6nu_p5"]
 
 _cache = {}
 
@@ -37,10 +45,6 @@ def setup(name):
     torch.cuda.synchronize()
     _cache[name] = (wl, dp, pr)
     return _cache[name]
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def dev(x, dtype=None):
@@ -70,8 +74,26 @@ def test_apply_fp64_parity(name):
     from paper_1712_08565_amd import wqfd
     wl, dp, pr = setup(name)
     v = synth.random_vector(pr.N, 42)
-    e = rel(host(wqfd.wq_apply(dp.A, dev(v))), pr.apply(v))
+    e = max_rel(host(wqfd.wq_apply(dp.A, dev(v))), pr.apply(v))
+    print(f"[apply] {name}: max entry error / max |K~ v| {e:.2e}")
     assert e <= 1e-12, f"{e:.3e}"
+
+
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p6", "twist6_p6", "ring20nu_p6", "ring6_p8"])
+def test_apply_smooth_input_on_rounding_scale(name):
+    """A smooth v (a spline interpolant-like sample of a smooth function) makes
+    K~ v and K~^T v small against their terms; each entry is then compared on
+    its own rounding scale (reading R11)."""
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    n1, n2, n3 = pr.n
+    g = [np.arange(1, m + 1) / (m + 1) for m in (n1, n2, n3)]
+    Z, Y, X = np.meshgrid(g[2], g[1], g[0], indexing="ij")
+    v = (np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z) * (1 + X * Y)).ravel()
+    e = per_entry(host(wqfd.wq_apply(dp.A, dev(v))), pr.apply(v), pr.apply_abs(v))
+    eT = per_entry(host(wqfd.wq_apply_T(dp.A, dev(v))), pr.apply_T(v), pr.apply_T_abs(v))
+    print(f"[apply smooth] {name}: worst entry / rounding scale {e:.2e}, transpose {eT:.2e}")
+    assert e <= 1e-12 and eT <= 1e-12, (e, eT)
 
 
 @pytest.mark.parametrize("name", ["cube12_p3", "ring8_p6", "ring20_p6"])
@@ -85,9 +107,9 @@ def test_apply_acc_parity(name):
     Kv = pr.apply(v)
     w = dev(w0)
     wqfd.wq_apply_acc(dp.A, dev(v), w)
-    e1 = rel(host(w), w0 + Kv)
+    e1 = max_rel(host(w), w0 + Kv)
     wqfd.wq_apply_acc(dp.A, dev(v), w)
-    e2 = rel(host(w), w0 + 2 * Kv)
+    e2 = max_rel(host(w), w0 + 2 * Kv)
     print(f"[apply acc] {name}: {e1:.2e}, {e2:.2e}")
     assert e1 <= 1e-12 and e2 <= 1e-12, (e1, e2)
 
@@ -129,26 +151,27 @@ def test_apply_T_fp64_parity_and_adjoint_identity(name):
     v = synth.random_vector(pr.N, 43)
     u = synth.random_vector(pr.N, 44)
     gT = host(wqfd.wq_apply_T(dp.A, dev(v)))
-    e = rel(gT, pr.apply_T(v))
+    e = max_rel(gT, pr.apply_T(v))
+    print(f"[apply_T] {name}: max entry error / max |K~^T v| {e:.2e}")
     assert e <= 1e-12, f"{e:.3e}"
     gu = host(wqfd.wq_apply(dp.A, dev(u)))
     d = abs(gu @ v - u @ gT) / (np.linalg.norm(gu) * np.linalg.norm(v))
     assert d <= 1e-13, f"{d:.3e}"
 
 
-@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p3", "ring8_p6", "twist6_p6"])
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p3", "ring8_p6", "twist6_p6", "ring8nu_p4", "ring20nu_p6"])
 def test_apply_fp32_error(name):
     import torch
     from paper_1712_08565_amd import wqfd
     wl, dp, pr = setup(name)
     v = synth.random_vector(pr.N, 42)
-    e = rel(host(wqfd.wq_apply(dp.A, dev(v, torch.float32))), pr.apply(v))
-    eT = rel(host(wqfd.wq_apply_T(dp.A, dev(v, torch.float32))), pr.apply_T(v))
-    print(f"[fp32 apply] {name}: rel error {e:.2e}, transpose {eT:.2e}")
+    e = max_rel(host(wqfd.wq_apply(dp.A, dev(v, torch.float32))), pr.apply(v))
+    eT = max_rel(host(wqfd.wq_apply_T(dp.A, dev(v, torch.float32))), pr.apply_T(v))
+    print(f"[fp32 apply] {name}: max entry error / max |ref| {e:.2e}, transpose {eT:.2e}")
     assert e <= 1e-5 and eT <= 1e-5, (e, eT)
 
 
-@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p2", "ring8_p6", "twist6_p6"])
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p2", "ring8_p6", "twist6_p6", "ring8nu_p3", "ring20nu_p6"])
 def test_fd_parity(name):
     import torch
     from paper_1712_08565_amd import wqfd
@@ -157,21 +180,21 @@ def test_fd_parity(name):
     fd = FD(pr.spaces)
     r = synth.random_vector(pr.N, 45)
     ref = fd.apply(r)
-    e = rel(host(wqfd.fd_apply(dp.P, dev(r))), ref)
-    e32 = rel(host(wqfd.fd_apply(dp.P, dev(r, torch.float32), prec=WQ_F32)), ref)
-    ebf = rel(host(wqfd.fd_apply(dp.P, dev(r, torch.float32), prec=WQ_BF16)), ref)
-    print(f"[fd] {name}: fp64 {e:.2e}, fp32 {e32:.2e}, bf16 {ebf:.2e}")
+    e = max_rel(host(wqfd.fd_apply(dp.P, dev(r))), ref)
+    e32 = max_rel(host(wqfd.fd_apply(dp.P, dev(r, torch.float32), prec=WQ_F32)), ref)
+    ebf = max_rel(host(wqfd.fd_apply(dp.P, dev(r, torch.float32), prec=WQ_BF16)), ref)
+    print(f"[fd] {name}: max entry error / max |ref|: fp64 {e:.2e}, fp32 {e32:.2e}, bf16 {ebf:.2e}")
     assert e <= 1e-12 and e32 <= 1e-5 and ebf <= 5e-2, (e, e32, ebf)
     x = dev(r)                      # r and z may alias
     wqfd.fd_apply(dp.P, x, x)
-    e_in = rel(host(x), ref)
+    e_in = max_rel(host(x), ref)
     assert e_in <= 1e-12, f"{e_in:.3e}"
 
 
-@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p3", "twist6_p6"])
+@pytest.mark.parametrize("name", ["cube12_p3", "ring8_p3", "twist6_p6", "ring8nu_p5"])
 def test_rhs_parity(name):
     wl, dp, pr = setup(name)
-    e = rel(host(dp.b), pr.rhs_from(wl.f()))
+    e = max_rel(host(dp.b), pr.rhs_from(wl.f()))
     assert e <= 1e-12, f"{e:.3e}"
 
 
@@ -180,47 +203,59 @@ def test_identity_cube_solves_in_one_iteration():
     wl, dp, pr = setup("cube12_p3")
     x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-12)
     xd = spla.spsolve(pr.assemble().tocsc(), pr.rhs_from(wl.f()))
-    e = rel(host(x), xd)
+    e = norm_rel(host(x), xd)
     assert it == 1 and res <= 1e-12 and e <= 1e-10, (it, res, e)
 
 
-def _solve_check(K, b, x, res, label):
-    """Error vs the direct solve; where the bound cond * residual exceeds 1e-10
-    (reading R10), gate the oracle's residual of the GPU solution instead."""
-    xd = spla.spsolve(K.tocsc(), b)
-    e = rel(x, xd)
-    r_or = float(np.linalg.norm(K @ x - b) / np.linalg.norm(b))
-    print(f"[{label}] relres {res:.2e}, oracle residual {r_or:.2e}, rel err vs direct {e:.2e}")
-    assert r_or <= 1e-12, f"{r_or:.3e}"
-    if e > 1e-10:
-        cond = np.linalg.cond(K.toarray()) if K.shape[0] <= 4000 else np.inf
-        print(f"[{label}] cond(K~) = {cond:.2e}: error {e:.2e} within cond * residual {cond * r_or:.2e}")
-        assert e <= 10 * cond * r_or, (e, cond, r_or)
+_refs = {}
 
 
-@pytest.mark.parametrize("name", ["ring8_p2", "ring8_p4", "ring8_p6", "ring7_p4_kappa", "twist5_p4"])
+def reference_solution(name, pr, b, transpose=False):
+    key = (name, transpose)
+    if key not in _refs:
+        _refs[key] = reference_solve(pr, b, transpose)
+    return _refs[key]
+
+
+def _solve_check(pr, A, b, x, xref, res, label, transpose=False):
+    """Error against the refined reference <= 1e-10, or <= 3 times the error of
+    the oracle's own FP64 BiCGStab where that floor is higher (reading R10)."""
+    e = norm_rel(x, xref)
+    e_or = oracle_fp64_solve_error(pr, b, xref, transpose)
+    r_or = float(np.linalg.norm(A(x) - b) / np.linalg.norm(b))
+    print(f"[{label}] relres {res:.2e}, oracle residual {r_or:.2e}, rel err vs reference {e:.2e} "
+          f"(oracle FP64 BiCGStab: {e_or:.2e})")
+    assert r_or <= 1e-12 and e <= max(1e-10, 3 * e_or), (r_or, e, e_or)
+
+
+@pytest.mark.parametrize("name", ["ring8_p2", "ring8_p4", "ring8_p6", "ring7_p4_kappa", "twist5_p4", "twist6_p6",
+                                  "ring8nu_p3", "ring8nu_p6", "twist6nu_p5", "ring6nu_p8"])
 def test_solve_parity(name):
     from paper_1712_08565_amd import wqfd
     wl, dp, pr = setup(name)
-    K = pr.assemble()
     b = pr.rhs_from(wl.f())
     x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-14, maxit=400, raise_on_noconv=False)
     assert res <= 1e-13, f"{res:.3e}"
-    _solve_check(K, b, host(x), res, f"solve {name} ({it} it)")
+    _solve_check(pr, pr.apply, b, host(x), reference_solution(name, pr, b), res, f"solve {name} ({it} it)")
     xt, itt, rest = wqfd.krylov_solve(dp.A, dp.P, dp.b, transpose=True, rtol=1e-14, maxit=400,
                                       raise_on_noconv=False)
     assert rest <= 1e-13, f"{rest:.3e}"
-    _solve_check(K.T.tocsr(), b, host(xt), rest, f"solve^T {name} ({itt} it)")
+    _solve_check(pr, pr.apply_T, b, host(xt), reference_solution(name, pr, b, True), rest,
+                 f"solve^T {name} ({itt} it)", transpose=True)
 
 
 @pytest.mark.parametrize("fd_prec", ["f32", "bf16"])
-def test_mixed_precision_refinement_parity(fd_prec):
+@pytest.mark.parametrize("name", ["ring8_p4", "twist6_p6", "ring7_p4_kappa", "ring8nu_p5"])
+def test_mixed_precision_refinement_parity(name, fd_prec):
     from paper_1712_08565_amd import wqfd
     from paper_1712_08565_amd.wqfd import WQ_BF16, WQ_F32
-    wl, dp, pr = setup("ring8_p4")
-    xd = spla.spsolve(pr.assemble().tocsc(), pr.rhs_from(wl.f()))
+    wl, dp, pr = setup(name)
+    b = pr.rhs_from(wl.f())
+    xref = reference_solution(name, pr, b)
     prec = WQ_F32 if fd_prec == "f32" else WQ_BF16
-    x, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, fd_prec=prec, rtol=1e-12, tau_inner=1e-4)
-    e = rel(host(x), xd)
-    print(f"[ir {fd_prec}] outer {outer}, inner {inner}, relres {res:.2e}, rel err {e:.2e}")
-    assert res <= 1e-12 and e <= 1e-10, (res, e)
+    x, outer, inner, res = wqfd.ir_solve(dp.A, dp.P, dp.b, fd_prec=prec, rtol=1e-13, tau_inner=1e-4)
+    e = norm_rel(host(x), xref)
+    r_or = float(np.linalg.norm(pr.apply(host(x)) - b) / np.linalg.norm(b))
+    print(f"[ir {fd_prec}] {name}: outer {outer}, inner {inner}, relres {res:.2e}, oracle residual {r_or:.2e}, "
+          f"rel err {e:.2e}")
+    assert res <= 1e-13 and r_or <= 1e-12 and e <= 1e-10, (res, r_or, e)

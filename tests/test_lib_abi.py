@@ -46,6 +46,7 @@ def test_noalloc_entry_checks_arguments_on_the_host():
     L = _lib.lib()
     assert L.fd_apply_noalloc(None, _lib.WQ_F64, None, None, None) == _lib.WQ_EINVAL
     assert len(L.wq_last_error()) > 0
+    assert L.wq_alpha_mean(None, C.byref(C.c_double()), None) == _lib.WQ_EINVAL
     m = re.search(r"#define\s+WQ_FD_NOALLOC_BYTES\s+\((\d+)u\s*<<\s*(\d+)\)", open(HEADER).read())
     assert m and int(m.group(1)) << int(m.group(2)) == _lib.WQ_FD_NOALLOC_BYTES
 
