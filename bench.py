@@ -290,7 +290,7 @@ def main():
     stream = torch.cuda.current_stream()
     rec = {p: dict(apply_ms=[], kernel_ms=[], fd_ms={"f64": [], "f32": [], "bf16": []}, fp64_ms=[], fp64_it=[], fp64_err=[], mix_ms=[], mix_outer=[], mix_inner=[],
                    mix_err=[], fp64_eq_ms=[], fp64_eq_err=[], fp64_eq_it=[], mixed_eq_ms=[], mixed_eq_err=[],
-                   mixed_eq_it=[], adj_ms=[], adj_it=[], applyT_ms=[]) for p in keys}
+                   mixed_eq_it=[], adj_ms=[], adj_it=[], grad_ms=[], applyT_ms=[]) for p in keys}
     probe = None
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 8
@@ -352,6 +352,13 @@ def main():
                 wqfd.wq_grad_K(dp.A, P["lam"], P["x"], P["gK"])
                 wqfd.wq_grad_f(dp.A, P["lam"], P["gf"])
                 a1.record(stream)
+                # the gradient kernels alone (dJ/dK and dJ/df at the adjoint state)
+                g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                g0.record(stream)
+                for _ in range(max(1, args.reps // 4)):
+                    wqfd.wq_grad_K(dp.A, P["lam"], P["x"], P["gK"])
+                    wqfd.wq_grad_f(dp.A, P["lam"], P["gf"])
+                g1.record(stream)
                 evT = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                        for _ in range(max(1, args.reps // 4))]
                 for e0, e1 in evT:
@@ -378,6 +385,7 @@ def main():
                     r["mix_err"].append(torch.linalg.norm(xm - P["xref"]).item() / nref)
                     r["adj_ms"].append(a0.elapsed_time(a1))
                     r["adj_it"].append(ait)
+                    r["grad_ms"].append(g0.elapsed_time(g1) / max(1, args.reps // 4))
                     r["applyT_ms"] += [e0.elapsed_time(e1) for e0, e1 in evT]
                     for kind, (q0, q1, xq, last) in eq.items():
                         r[f"{kind}_eq_ms"].append(q0.elapsed_time(q1))
@@ -626,6 +634,8 @@ def main():
             d["apply_T_ms"] = round(float(np.mean(r["applyT_ms"])), 4)
             d["adjoint_ms"] = round(float(np.median(r["adj_ms"])), 2)
             d["adjoint_iters"] = int(np.median(r["adj_it"]))
+            d["gradient_kernels_ms"] = round(float(np.median(r["grad_ms"])), 4)
+            d["gradient_over_apply"] = round(float(np.median(r["grad_ms"])) / t_ap, 2)
             for kind in ("fp64", "mixed"):
                 if r[f"{kind}_eq_ms"]:
                     d[f"{kind}_equal_accuracy"] = {

@@ -589,6 +589,7 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
         off += al256(o.Nq * 4);
     }
     const size_t o_scr = off;
+    o.fused = fused_ok;                 // (the gradient's scratch need depends on it; tables filled below)
     o.scratch_bytes = wqfd::wq_scratch_bytes(o, prec_mask);
     off += al256(o.scratch_bytes);
     const size_t o_red = off;

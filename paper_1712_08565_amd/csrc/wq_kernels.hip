@@ -279,6 +279,46 @@ __global__ __launch_bounds__(kThreads) void set_coef_kernel(const double* __rest
 //   gC_ab = -(W^(ab)^T lam)_q (B^(b) u)_q ;  scalar: sum_ab gC_ab G_ab, G = det Ji Ji^T;
 //   sym6: H = det Ji^T gC Ji, diagonal H_aa, off-diagonal H_ab + H_ba;
 //   identity kind: the six stored C planes (g_ab + g_ba off the diagonal).
+// dJ/dC (the 3 x 3 g at point q) chained through eq. C to the layout of K_q.
+__device__ inline void grad_chain(const double (&g)[3][3], const double* __restrict__ detJ,
+                                  const double* __restrict__ Jinv, int k_kind, double* __restrict__ out, size_t Nq,
+                                  size_t q) {
+    if (k_kind == 0) {
+        out[q] = g[0][0];
+        out[Nq + q] = g[1][1];
+        out[2 * Nq + q] = g[2][2];
+        out[3 * Nq + q] = g[0][1] + g[1][0];
+        out[4 * Nq + q] = g[0][2] + g[2][0];
+        out[5 * Nq + q] = g[1][2] + g[2][1];
+        return;
+    }
+    double Ji[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Ji[r][c] = Jinv[(size_t)(3 * r + c) * Nq + q];
+    const double d = detJ[q];
+    if (k_kind == 1) {
+        double acc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double G = Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2];
+                acc += g[a][b] * G;
+            }
+        out[q] = d * acc;
+    } else {
+        double T[3][3], H[3][3];   // T = g Ji ; H = Ji^T T
+        for (int a = 0; a < 3; ++a)
+            for (int c = 0; c < 3; ++c) T[a][c] = g[a][0] * Ji[0][c] + g[a][1] * Ji[1][c] + g[a][2] * Ji[2][c];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) H[r][c] = d * (Ji[0][r] * T[0][c] + Ji[1][r] * T[1][c] + Ji[2][r] * T[2][c]);
+        out[q] = H[0][0];
+        out[Nq + q] = H[1][1];
+        out[2 * Nq + q] = H[2][2];
+        out[3 * Nq + q] = H[0][1] + H[1][0];
+        out[4 * Nq + q] = H[0][2] + H[2][0];
+        out[5 * Nq + q] = H[1][2] + H[2][1];
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void grad_K_kernel(const double* __restrict__ wtl,  // [9][Nq] (al*3+be)
                                                           const double* __restrict__ gu,   // [3][Nq]
                                                           const double* __restrict__ detJ,
@@ -288,40 +328,142 @@ __global__ __launch_bounds__(kThreads) void grad_K_kernel(const double* __restri
         double g[3][3];
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) g[a][b] = -wtl[(size_t)(3 * a + b) * Nq + q] * gu[(size_t)b * Nq + q];
-        if (k_kind == 0) {
-            out[q] = g[0][0];
-            out[Nq + q] = g[1][1];
-            out[2 * Nq + q] = g[2][2];
-            out[3 * Nq + q] = g[0][1] + g[1][0];
-            out[4 * Nq + q] = g[0][2] + g[2][0];
-            out[5 * Nq + q] = g[1][2] + g[2][1];
-            continue;
+        grad_chain(g, detJ, Jinv, k_kind, out, Nq, q);
+    }
+}
+
+// Fused x/y stage of the gradient expansion (p <= 7, operators with the fused
+// tables).  With the z contractions done (Tl[v3] = W3^(v3)T lam and
+// Tu[b3] = B3^(b3) u, arrays [n_q3][n2][n1]), one workgroup per 16 x 16 tile of
+// quadrature columns and a range of quadrature planes forms, per plane and from
+// the tile's dense 16 x 16 factor blocks (the fused apply's tables), the nine
+// values (W^(ab)T lam)_q and the three values (B^(b) u)_q at its 256 points, as
+// 24 products of 16 x 16 blocks on the matrix cores (y first, then x, in place in
+// LDS), multiplies them to g_ab = -(W^(ab)T lam)_q (B^(b) u)_q and chains g to the
+// layout of K_q: no N_q-sized intermediate is written.
+typedef double gd4 __attribute__((ext_vector_type(4)));
+constexpr int GLD = 17;
+constexpr int GBLK = 16 * GLD;
+
+// c += A B for 16 x 16 blocks in LDS: A[m][k] = At[m][k]; B[k][n] = Bt[k][n]
+// (BT = false) or Bt[n][k] (BT = true).  FP64 MFMA operand layout: lane l holds
+// A row l % 16 and B column l % 16 of the k-block l / 16; result row kb + 4 v.
+template <bool BT>
+__device__ inline gd4 gemm16_lds(const double* At, const double* Bt, gd4 c, int cl, int kb) {
+    double a[4], b[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        a[s] = At[cl * GLD + 4 * s + kb];
+        b[s] = BT ? Bt[cl * GLD + 4 * s + kb] : Bt[(4 * s + kb) * GLD + cl];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+    return c;
+}
+
+struct GradXYArgs {
+    const double* tilesX = nullptr;
+    const double* tilesY = nullptr;
+    const int* JX = nullptr;
+    const int* IX = nullptr;
+    const int* JY = nullptr;
+    const int* IY = nullptr;
+    const double* Tl = nullptr;      // [4][nq3][n2][n1]
+    const double* Tu = nullptr;      // [2][nq3][n2][n1]
+    const double* detJ = nullptr;
+    const double* Jinv = nullptr;
+    double* out = nullptr;
+    int k_kind = 0;
+    int n1 = 0, n2 = 0, nq1 = 0, nq2 = 0, nq3 = 0, ntx = 0, nty = 0, zchunk = 0;
+    size_t Nq = 0;
+};
+
+__global__ __launch_bounds__(256) void grad_xy_kernel(GradXYArgs a) {
+    // factor blocks: 0-3 W2^(v) as [q2][i2]; 4, 5 B2_d as [q2][j2]; 6-9 W1^(v) as [i1][q1];
+    // 10, 11 B1_d as [q1][j1] (v = 2 [test derivative] + [trial derivative])
+    __shared__ double sT[12][GBLK];
+    __shared__ double sD[6][GBLK];      // plane data: 0-3 Tl[v3] as [i2][i1], 4, 5 Tu[b3] as [j2][j1]
+    __shared__ double sY[12][GBLK];     // y products, then (in place) the values at the points
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cl = lane & 15, kb = lane >> 4;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int lin = blockIdx.x;
+    const int t1 = lin % a.ntx, t2 = (lin / a.ntx) % a.nty, zc = lin / (a.ntx * a.nty);
+    const int k0 = zc * a.zchunk, k1 = min(a.nq3, k0 + a.zchunk);
+    if (k0 >= k1) return;
+    const int I1 = a.IX[t1], J1 = a.JX[t1], I2 = a.IY[t2], J2 = a.JY[t2];
+    for (int e = tid; e < 12 * 256; e += 256) {
+        const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
+        if (b < 4)
+            sT[b][c * GLD + r] = a.tilesY[((size_t)t2 * 6 + 2 + b) * 256 + r * 16 + c];
+        else if (b < 6)
+            sT[b][r * GLD + c] = a.tilesY[((size_t)t2 * 6 + (b - 4)) * 256 + r * 16 + c];
+        else if (b < 10)
+            sT[b][r * GLD + c] = a.tilesX[((size_t)t1 * 6 + 2 + (b - 6)) * 256 + r * 16 + c];
+        else
+            sT[b][r * GLD + c] = a.tilesX[((size_t)t1 * 6 + (b - 10)) * 256 + r * 16 + c];
+    }
+    // products of this wave: pi = wave + 4 j, j = 0..2.  pi < 9: field f = pi with
+    // (v3, v2, v1) of f = 3 alpha + beta, v_l = 2 [l = alpha] + [l = beta]; pi = 9 + beta:
+    // (B^(beta) u) with (b3, b2, b1) = (beta = z, beta = y, beta = x)
+    const size_t zsz = (size_t)a.nq3 * a.n2 * a.n1;
+    const int q1 = 16 * t1 + tx, q2 = 16 * t2 + ty;
+    const bool in = q1 < a.nq1 && q2 < a.nq2;
+    for (int k = k0; k < k1; ++k) {
+        for (int e = tid; e < 6 * 256; e += 256) {
+            const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            double val = 0.0;
+            if (b < 4) {
+                const int i2 = I2 + r, i1 = I1 + c;
+                if (i2 < a.n2 && i1 < a.n1) val = a.Tl[b * zsz + ((size_t)k * a.n2 + i2) * a.n1 + i1];
+            } else {
+                const int j2 = J2 + r, j1 = J1 + c;
+                if (j2 < a.n2 && j1 < a.n1) val = a.Tu[(b - 4) * zsz + ((size_t)k * a.n2 + j2) * a.n1 + j1];
+            }
+            sD[b][r * GLD + c] = val;
         }
-        double Ji[3][3];
-        for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) Ji[r][c] = Jinv[(size_t)(3 * r + c) * Nq + q];
-        const double d = detJ[q];
-        if (k_kind == 1) {
-            double acc = 0.0;
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    const double G = Ji[a][0] * Ji[b][0] + Ji[a][1] * Ji[b][1] + Ji[a][2] * Ji[b][2];
-                    acc += g[a][b] * G;
-                }
-            out[q] = d * acc;
-        } else {
-            double T[3][3], H[3][3];   // T = g Ji ; H = Ji^T T
-            for (int a = 0; a < 3; ++a)
-                for (int c = 0; c < 3; ++c) T[a][c] = g[a][0] * Ji[0][c] + g[a][1] * Ji[1][c] + g[a][2] * Ji[2][c];
-            for (int r = 0; r < 3; ++r)
-                for (int c = 0; c < 3; ++c) H[r][c] = d * (Ji[0][r] * T[0][c] + Ji[1][r] * T[1][c] + Ji[2][r] * T[2][c]);
-            out[q] = H[0][0];
-            out[Nq + q] = H[1][1];
-            out[2 * Nq + q] = H[2][2];
-            out[3 * Nq + q] = H[0][1] + H[1][0];
-            out[4 * Nq + q] = H[0][2] + H[2][0];
-            out[5 * Nq + q] = H[1][2] + H[2][1];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {                    // y products
+            const int pi = wave + 4 * j;
+            gd4 c = {0, 0, 0, 0};
+            if (pi < 9) {
+                const int al = pi / 3, be = pi % 3;
+                const int v2 = 2 * (al == 1) + (be == 1), v3 = 2 * (al == 2) + (be == 2);
+                c = gemm16_lds<false>(sT[v2], sD[v3], c, cl, kb);
+            } else {
+                const int be = pi - 9;
+                c = gemm16_lds<false>(sT[4 + (be == 1)], sD[4 + (be == 2)], c, cl, kb);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sY[pi][(kb + 4 * v) * GLD + cl] = c[v];
         }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {                    // x products (in place: operands read first)
+            const int pi = wave + 4 * j;
+            gd4 c = {0, 0, 0, 0};
+            if (pi < 9) {
+                const int al = pi / 3, be = pi % 3;
+                const int v1 = 2 * (al == 0) + (be == 0);
+                c = gemm16_lds<false>(sY[pi], sT[6 + v1], c, cl, kb);
+            } else {
+                const int be = pi - 9;
+                c = gemm16_lds<true>(sY[pi], sT[10 + (be == 0)], c, cl, kb);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sY[pi][(kb + 4 * v) * GLD + cl] = c[v];
+        }
+        __syncthreads();
+        if (in) {
+            double g[3][3];
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be)
+                    g[al][be] = -sY[3 * al + be][ty * GLD + tx] * sY[9 + be][ty * GLD + tx];
+            grad_chain(g, a.detJ, a.Jinv, a.k_kind, a.out, a.Nq, ((size_t)k * a.nq2 + q2) * a.nq1 + q1);
+        }
+        __syncthreads();
     }
 }
 
@@ -370,10 +512,12 @@ hipError_t apply_mass_staged(const WqOp& op, const OpTables<T>& tb, const T* Cm,
 }  // namespace
 
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask) {
-    // staged apply in the widest precision, or the gradient fields (12 N_q FP64)
+    // staged apply in the widest precision; the staged gradient (operators
+    // without the fused tables) also needs its fields (12 N_q FP64), the fused
+    // gradient only the staged layout's z-contraction arrays
     size_t e = Staged<double>::elems(op);
     size_t grad = 12 * op.Nq + 2 * (size_t)op.nq[2] * op.nq[1] * op.n[0] + 4 * (size_t)op.nq[2] * op.n[1] * op.n[0];
-    if (grad > e) e = grad;
+    if (!op.fused && grad > e) e = grad;
     (void)prec_mask;
     return e * sizeof(double);
 }
@@ -467,6 +611,48 @@ hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStrea
 }
 
 hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s) {
+    if (op.fused) {
+        // z contractions (four W3 variants of lam, B3 and B-dot3 of u) into the
+        // staged scratch, then the fused x/y stage and the chain rule
+        Staged<double> st(op, op.scratch);
+        const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
+        const Dir1D<double>& dz = op.t64.dir[2];
+        const size_t zsz = (size_t)op.nq[2] * n2 * n1;
+        double* Tl = st.Z[0];                           // Z[0..3] are consecutive [nq3][n2][n1] arrays
+        double* Tu = st.A;                              // A holds [nq3][nq2][n1] >= 2 [nq3][n2][n1] (nq2 > 2 n2)
+        for (int v = 0; v < 4; ++v) WQ_TRY(band<double>(2, dz.WT[v], lam, nullptr, Tl + v * zsz, n1, n2, n3, false, s));
+        WQ_TRY(band<double>(2, dz.B[0], u, nullptr, Tu, n1, n2, n3, false, s));
+        WQ_TRY(band<double>(2, dz.B[1], u, nullptr, Tu + zsz, n1, n2, n3, false, s));
+        GradXYArgs g;
+        const FusedArgs<double>& f = op.fz64;
+        g.tilesX = f.tilesX;
+        g.tilesY = f.tilesY;
+        g.JX = f.JX;
+        g.IX = f.IX;
+        g.JY = f.JY;
+        g.IY = f.IY;
+        g.Tl = Tl;
+        g.Tu = Tu;
+        g.detJ = op.detJ;
+        g.Jinv = op.Jinv;
+        g.out = gK;
+        g.k_kind = op.k_kind;
+        g.n1 = n1;
+        g.n2 = n2;
+        g.nq1 = op.nq[0];
+        g.nq2 = op.nq[1];
+        g.nq3 = op.nq[2];
+        g.ntx = f.ntx;
+        g.nty = f.nty;
+        g.Nq = op.Nq;
+        // z ranges of 8 planes: about five workgroups per CU at the benchmark sizes
+        g.zchunk = 8;
+        const int nz = (g.nq3 + g.zchunk - 1) / g.zchunk;
+        if (2 * n2 > op.nq[1] || st.Z[1] != st.Z[0] + zsz || st.Z[3] != st.Z[0] + 3 * zsz)
+            return hipErrorInvalidValue;                // scratch layout assumed above
+        hipLaunchKernelGGL(grad_xy_kernel, dim3(g.ntx * g.nty * nz), dim3(256), 0, s, g);
+        return hipGetLastError();
+    }
     // fields: wtl [9][Nq] = W^(ab)^T lam, gu [3][Nq] = B^(b) u
     double* base = reinterpret_cast<double*>(op.scratch);
     double* wtl = base;
