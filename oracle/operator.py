@@ -53,7 +53,7 @@ def mode(A, X, axis):
 class Problem:
     """Spaces, geometry and coefficient planes of one single-patch problem."""
 
-    def __init__(self, knots3, p, ctrl, K_fn=None, rule="wq"):
+    def __init__(self, knots3, p, ctrl, K_fn=None, rule="wq", weights=None):
         self.p = p
         self.spaces = [Space1D(k, p, rule) for k in knots3]
         S1, S2, S3 = self.spaces
@@ -61,7 +61,7 @@ class Problem:
         self.nq = (S1.nq, S2.nq, S3.nq)
         self.N = S1.n * S2.n * S3.n
         self.Nq = S1.nq * S2.nq * S3.nq
-        self.F, self.J = map_and_jacobian(self.spaces, ctrl)
+        self.F, self.J = map_and_jacobian(self.spaces, ctrl, weights)
         self.Cm = None                          # reaction diagonal alpha det J (None: alpha = 0)
         self.set_K(K_fn(self.F) if K_fn is not None else None)
 

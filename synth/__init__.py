@@ -89,6 +89,49 @@ def _shear_matrix():
     return np.array([[1.0, 0.3, 0.1], [0.2, 1.2, -0.15], [0.05, 0.25, 0.9]])
 
 
+def _ring_homogeneous(g1, g2, g3):
+    """Homogeneous coordinates (w x, w y, w z, w) of the exact thick quarter ring
+    (1 <= r <= 2, 0 <= theta <= pi/2, 0 <= z <= 1) as a rational map: r = 1 + xi1,
+    z = xi3, and in xi2 the quarter circle as the rational quadratic Bezier curve
+    with control points (1, 0), (1, 1), (0, 1) and weights 1, 1/sqrt(2), 1.  Every
+    component is a polynomial of degree <= 2 in xi2 and <= 1 in xi1 and xi3."""
+    c = math.sqrt(0.5)
+    b0, b1, b2 = (1.0 - g2) ** 2, 2.0 * g2 * (1.0 - g2), g2 ** 2
+    w = b0 + c * b1 + b2
+    r = 1.0 + g1
+    return r * (b0 + c * b1), r * (c * b1 + b2), g3 * w, w
+
+
+def nurbs_net(kind: str, knots3, p: int):
+    """(P [k3, k2, k1, 3], w [k3, k2, k1]) of a rational map of degree p on the
+    given knots: 'ring_nurbs' is the exact thick quarter ring.  Each homogeneous
+    component is a product of polynomials of degree <= 2 <= p in one variable
+    each, so it is the tensor product of the 1D interpolants at the Greville
+    abscissae, which reproduce those polynomials exactly in the spline space."""
+    if kind != "ring_nurbs":
+        raise ValueError(f"unknown rational geometry {kind!r}")
+    from scipy.interpolate import make_interp_spline
+
+    def interp(l, f):
+        g = greville(knots3[l], p)
+        return make_interp_spline(g, f(g), k=p, t=np.asarray(knots3[l], dtype=np.float64)).c
+
+    one = lambda g: np.ones_like(g)                                      # noqa: E731
+    c = math.sqrt(0.5)
+    b0 = lambda g: (1.0 - g) ** 2                                        # noqa: E731
+    b1 = lambda g: 2.0 * g * (1.0 - g)                                   # noqa: E731
+    b2 = lambda g: g ** 2                                                # noqa: E731
+    r1, o1 = interp(0, lambda g: 1.0 + g), interp(0, one)
+    X2 = interp(1, lambda g: b0(g) + c * b1(g))
+    Y2 = interp(1, lambda g: c * b1(g) + b2(g))
+    W2 = interp(1, lambda g: b0(g) + c * b1(g) + b2(g))
+    z3, o3 = interp(2, lambda g: g), interp(2, one)
+    outer = lambda a3, a2, a1: np.einsum("k,j,i->kji", a3, a2, a1)       # noqa: E731
+    w = outer(o3, W2, o1)
+    P = np.stack([outer(o3, X2, r1), outer(o3, Y2, r1), outer(z3, W2, o1)], -1) / w[..., None]
+    return np.ascontiguousarray(P), np.ascontiguousarray(w)
+
+
 def _map_shear(g1, g2, g3):
     A = _shear_matrix()
     X = np.stack([g1, g2, g3], -1) @ A.T
@@ -118,7 +161,8 @@ def control_net(kind: str, knots3, p: int, noise: float = 0.0, seed: int = 0,
     at the images of the Greville abscissae (second order in h).  'ring_interp'
     is the ring map interpolated at the Greville abscissae by the spline of the
     same knots (scipy.interpolate.make_interp_spline along each axis), accurate
-    to order p + 1 in h.
+    to order p + 1 in h.  'ring_nurbs' gives the Euclidean control points of the
+    exact ring as a rational map (its weights from ``nurbs_net``).
     ``noise`` adds 0.02-style smooth perturbations that vanish on the boundary:
     eta_c(g) = sum_{a,b,c in {1,2}} r sin(a pi g1) sin(b pi g2) sin(c pi g3) / 8,
     r ~ U(-1, 1) from ``seed``.
@@ -136,6 +180,8 @@ def control_net(kind: str, knots3, p: int, noise: float = 0.0, seed: int = 0,
             c = make_interp_spline(gl, V, k=p, t=np.asarray(k, dtype=np.float64), axis=axis).c
             V = np.moveaxis(c, 0, axis)                    # (the coefficients come with that axis first)
         X = (V[..., 0], V[..., 1], V[..., 2])
+    elif kind == "ring_nurbs":
+        X = tuple(np.moveaxis(nurbs_net(kind, knots3, p)[0], -1, 0))
     elif kind == "shear":
         X = _map_shear(G1, G2, G3)
     elif kind == "twist":
@@ -319,7 +365,7 @@ class Workload:
     name: str
     n_el: int
     p: int
-    geometry: str               # identity | ring | shear | twist
+    geometry: str               # identity | ring | ring_interp | ring_nurbs | shear | twist
     noise: float = 0.0          # control-net perturbation amplitude
     k_kind: str = "identity"    # identity | scalar | sym6
     source: str = "sine"        # sine | paper | smooth
@@ -334,6 +380,12 @@ class Workload:
 
     def ctrl(self) -> np.ndarray:
         return control_net(self.geometry, self.knots(), self.p, self.noise, self.geom_seed)
+
+    def weights(self) -> Optional[np.ndarray]:
+        """Control weights of a rational map, None for a polynomial one."""
+        if self.geometry == "ring_nurbs":
+            return nurbs_net(self.geometry, self.knots(), self.p)[1]
+        return None
 
     def K_field(self) -> Optional[Callable]:
         if self.k_kind == "identity":
@@ -387,6 +439,12 @@ def _mk() -> Dict[str, Workload]:
     w["twist6nu_p5"] = Workload("twist6nu_p5", 6, 5, "twist", 0.0, "sym6", "smooth", knot_seed=320)
     w["ring64nu_p4"] = Workload("ring64nu_p4", 64, 4, "ring", 0.02, "identity", "paper", knot_seed=330)
     w["cube5_p2"] = Workload("cube5_p2", 5, 2, "identity")
+    # the exact ring as a rational (NURBS) map, the paper's source; several tiles with a ragged tail at p = 5
+    for p in (2, 3, 6):
+        w[f"nurbs8_p{p}"] = Workload(f"nurbs8_p{p}", 8, p, "ring_nurbs", 0.0, "identity", "paper")
+    w["nurbs20_p5"] = Workload("nurbs20_p5", 20, 5, "ring_nurbs", 0.0, "identity", "paper")
+    w["nurbs6nu_p4"] = Workload("nurbs6nu_p4", 6, 4, "ring_nurbs", 0.0, "scalar", "paper", knot_seed=340)
+    w["nurbs6_p8"] = Workload("nurbs6_p8", 6, 8, "ring_nurbs", 0.0, "identity", "paper")
     return w
 
 
