@@ -116,6 +116,16 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def grad_bytes(A):
+    """Algorithmic bytes of one wq_grad_Kf: dJ/dK (six planes for identity or
+    six-component K, one for scalar K) and dJ/df written, det J read (and the nine
+    planes of J^{-1} for the chain of a scalar or six-component K), lam and u read."""
+    from paper_1712_08565_amd.wqfd import WQ_K_IDENTITY, WQ_K_SCALAR
+    out = 1 if A.k_kind == WQ_K_SCALAR else 6
+    geo = 1 if A.k_kind == WQ_K_IDENTITY else 10
+    return 8 * A.Nq * (out + 1 + geo) + 16 * A.N
+
+
 def cpu_baseline(budget_s: float, solve_budget_s: float = 25.0):
     """The CPU FP64 oracle on this host: matrix-free apply on ring64 p=3 with all
     threads (value) and with one, and FD-preconditioned BiCGStab solves to 1e-10
@@ -349,15 +359,13 @@ def main():
                 a0.record(stream)
                 _, ait, _ = wqfd.krylov_solve(dp.A, dp.P, P["x"], x=P["lam"], transpose=True, rtol=1e-10,
                                               maxit=2000, ws=P["kws"])
-                wqfd.wq_grad_K(dp.A, P["lam"], P["x"], P["gK"])
-                wqfd.wq_grad_f(dp.A, P["lam"], P["gf"])
+                wqfd.wq_grad_Kf(dp.A, P["lam"], P["x"], P["gK"], P["gf"])
                 a1.record(stream)
                 # the gradient kernels alone (dJ/dK and dJ/df at the adjoint state)
                 g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 g0.record(stream)
                 for _ in range(max(1, args.reps // 4)):
-                    wqfd.wq_grad_K(dp.A, P["lam"], P["x"], P["gK"])
-                    wqfd.wq_grad_f(dp.A, P["lam"], P["gf"])
+                    wqfd.wq_grad_Kf(dp.A, P["lam"], P["x"], P["gK"], P["gf"])
                 g1.record(stream)
                 evT = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                        for _ in range(max(1, args.reps // 4))]
@@ -527,6 +535,21 @@ def main():
                     rec_l[f"kernel_{key}_flushed_ms_median"] = round(float(np.median(fl)), 4)
                     rec_l[f"kernel_{key}_flushed_frac_of_hbm_peak"] = round(
                         alg / float(np.median(fl)) / 1e6 / HBM_PEAK_GBS, 4)
+            # adjoint gradient kernels (dJ/dK and dJ/df in one pass) at a random state
+            lam_l = torch.as_tensor(synth.random_vector(A.N, 45), device="cuda")
+            gK_l, gf_l = wqfd.wq_grad_Kf(A, lam_l, vl)
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(stream)
+            for _ in range(args.reps):
+                wqfd.wq_grad_Kf(A, lam_l, vl, gK_l, gf_l)
+            g1.record(stream)
+            torch.cuda.synchronize()
+            t_g = g0.elapsed_time(g1) / args.reps
+            rec_l["gradient_kernels_ms"] = round(t_g, 4)
+            rec_l["gradient_over_apply"] = round(t_g / rec_l["kernel_f64_ms"], 2)
+            rec_l["gradient_GBs"] = round(grad_bytes(A) / t_g / 1e6, 1)
+            rec_l["gradient_frac_of_hbm_peak"] = round(grad_bytes(A) / t_g / 1e6 / HBM_PEAK_GBS, 4)
+            del lam_l, gK_l, gf_l
             ft = fd_times(dpl, vl, vl32, args.reps)
             nmax = max(A.n)
             fl_fd = 12 * nmax * A.N + A.N
@@ -636,6 +659,9 @@ def main():
             d["adjoint_iters"] = int(np.median(r["adj_it"]))
             d["gradient_kernels_ms"] = round(float(np.median(r["grad_ms"])), 4)
             d["gradient_over_apply"] = round(float(np.median(r["grad_ms"])) / t_ap, 2)
+            gb = grad_bytes(probs[p]["dp"].A)
+            d["gradient_GBs"] = round(gb / float(np.median(r["grad_ms"])) / 1e6, 1)
+            d["gradient_frac_of_hbm_peak"] = round(gb / float(np.median(r["grad_ms"])) / 1e6 / HBM_PEAK_GBS, 4)
             for kind in ("fp64", "mixed"):
                 if r[f"{kind}_eq_ms"]:
                     d[f"{kind}_equal_accuracy"] = {

@@ -42,6 +42,7 @@ extern "C" {
 typedef struct ihipStream_t* wq_stream_t;   /* same type as hipStream_t */
 typedef struct wq_op_s* wq_op;              /* opaque WQ operator handle */
 typedef struct fd_pc_s* fd_pc;              /* opaque FD preconditioner handle */
+typedef struct wq_eval_s* wq_eval;          /* opaque Gauss-point evaluator handle */
 
 enum {
     WQ_OK = 0,
@@ -94,6 +95,21 @@ enum {
 int wq_setup(int p, const int32_t nknots[3], const double* const knots[3],
              const double* ctrl, int k_kind, const double* K_q, int prec_mask,
              void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s, wq_op* out);
+
+/* The same operator on a rational (NURBS) geometry map, which the paper's
+ * experiments use (Section 2.1 notes that the method carries over to NURBS;
+ * Section 4 takes the thick quarter ring, which polynomial splines cannot
+ * represent exactly): F(xi) = sum_k w_k P_k b_k(xi) / sum_k w_k b_k(xi).
+ *   weights      host [m3][m2][m1] FP64 control weights w_k > 0 (WQ_EINVAL
+ *                otherwise, or if NULL); ctrl holds the Euclidean points P_k.
+ * The discrete space stays the B-spline space of the knot vectors: the map
+ * enters only through J, det J and F at the quadrature points (eq. C), so every
+ * kernel and every other call works unchanged.  Other arguments and errors as
+ * wq_setup. */
+int wq_setup_nurbs(int p, const int32_t nknots[3], const double* const knots[3],
+                   const double* ctrl, const double* weights, int k_kind, const double* K_q,
+                   int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s,
+                   wq_op* out);
 
 /* The same operator with standard Gauss quadrature instead of weighted
  * quadrature (the remark after rem:memory, eq. WDBgaussian): p + 1
@@ -186,6 +202,13 @@ int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream
 
 /* dJ/df_q = det J(q) (W^(0,0)T lam)_q into device [N_q].  Async on s. */
 int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s);
+
+/* wq_grad_K and wq_grad_f together: for operators on the fused kernels
+ * (p <= 7) one pass over the quadrature points that reads lam and u and writes
+ * both gradients (the adjoint of a solve needs both); otherwise the two calls
+ * in turn.  Results equal those of the two calls.  gK, gf device, overwritten.
+ * Async on s.  Errors: WQ_EINVAL, WQ_EHIP. */
+int wq_grad_Kf(wq_op A, const double* lam, const double* u, double* gK, double* gf, wq_stream_t s);
 
 /* dJ/dalpha_q = -det J(q) (W^(0,0)T lam)_q (B u)_q (M~ is linear in alpha_q,
  * eq. WDB) into device [N_q] FP64; lam, u device [N] FP64.  Async on s.
@@ -308,10 +331,38 @@ int wq_space_1d(int p, int nknots, const double* knots, int32_t* n, int32_t* nq,
 int fd_eig_1d(int p, int nknots, const double* knots, double* lam, double* U);
 
 /* Geometry at the quadrature points of wq_setup, on the host: detJ [N_q],
- * Jinv [9][N_q] (entry (r, c) of J^{-1} in plane 3 r + c) and F [3][N_q].
- * Errors: WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR. */
+ * Jinv [9][N_q] (entry (r, c) of J^{-1} in plane 3 r + c) and F [3][N_q];
+ * weights NULL for a polynomial map, else the control weights of a rational
+ * map as in wq_setup_nurbs.  Errors: WQ_EINVAL, WQ_EGEOM, WQ_ESINGULAR. */
 int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
-                     double* detJ, double* Jinv, double* F);
+                     const double* weights, double* detJ, double* Jinv, double* F);
+
+/* ------------------------------------------------------------------------ *
+ * Evaluation of a discrete solution at tensor Gauss points, for the error
+ * measure of the k-refinement study (Section 4, Table 1: relative H1-seminorm
+ * error of u_h = sum_j u_j b_j o F^{-1}), in slabs of elements along z so that
+ * fine levels (256^3 elements, (p+3)^3 points each) need not be held at once.
+ * wq_eval_setup: ng Gauss-Legendre points per element and direction (1..32;
+ *   the study takes p + 3) on the knots of wq_setup; ctrl [m3][m2][m1][3] and
+ *   weights [m3][m2][m1] (NULL: polynomial map) as in wq_setup_nurbs.  ws
+ *   device workspace (NULL: size query into *ws_needed; 256-byte aligned)
+ *   holds the tables and the homogeneous control net, 32 bytes per control
+ *   point.  Synchronises s.  Errors: WQ_EINVAL, WQ_ENOMEM, WQ_EHIP.
+ * wq_eval_dims: elements ne[l] and Gauss points nq[l] = ne[l] ng per direction.
+ * wq_eval_slab: for the elements [e3_begin, e3_end) along z and all elements
+ *   along x and y, at n = nq1 nq2 (e3_end - e3_begin) ng points ordered
+ *   [z][y][x] (x fastest): X [3][n] = F(xi), wdet [n] = w1 w2 w3 |det J|,
+ *   uh [n] = u_h and grad [3][n] = J^{-T} grad_xi u_h, from u [N] (device FP64,
+ *   interior coefficients as in wq_apply).  All device FP64.  Async on s.
+ *   Errors: WQ_EINVAL, WQ_EHIP.
+ * ------------------------------------------------------------------------ */
+int wq_eval_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                  const double* weights, int ng, void* ws, size_t ws_bytes, size_t* ws_needed,
+                  wq_stream_t s, wq_eval* out);
+int wq_eval_dims(wq_eval E, int32_t ne[3], int32_t nq[3]);
+int wq_eval_slab(wq_eval E, const double* u, int e3_begin, int e3_end, double* X, double* wdet,
+                 double* uh, double* grad, wq_stream_t s);
+void wq_eval_destroy(wq_eval E);
 
 /* Thread-local message of the last failing call on this thread ("" if none). */
 const char* wq_last_error(void);

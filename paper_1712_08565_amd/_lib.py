@@ -26,6 +26,8 @@ _vp, _i32p, _dp, _szp, _ip = C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_dou
 SIGNATURES = [
     ("wq_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, C.c_int, _vp, C.c_int, _vp, C.c_size_t,
                            _szp, _vp, C.POINTER(C.c_void_p)]),
+    ("wq_setup_nurbs", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, C.c_int, _vp, C.c_int, _vp,
+                                 C.c_size_t, _szp, _vp, C.POINTER(C.c_void_p)]),
     ("wq_setup_gauss", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, C.c_int, _vp, C.c_int, _vp,
                                  C.c_size_t, _szp, _vp, C.POINTER(C.c_void_p)]),
     ("wq_dims", C.c_int, [_vp, _i32p, _i32p]),
@@ -41,6 +43,7 @@ SIGNATURES = [
     ("wq_rhs", C.c_int, [_vp, _vp, _vp, _vp]),
     ("wq_grad_K", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("wq_grad_f", C.c_int, [_vp, _vp, _vp, _vp]),
+    ("wq_grad_Kf", C.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     ("wq_grad_alpha", C.c_int, [_vp, _vp, _vp, _vp, _vp]),
     ("wq_destroy", None, [_vp]),
     ("fd_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), C.c_int, _vp, C.c_size_t, _szp, _vp,
@@ -50,6 +53,11 @@ SIGNATURES = [
     ("fd_set_shift", C.c_int, [_vp, C.c_double, _vp]),
     ("fd_factors", C.c_int, [_vp, C.c_int, _vp, _vp]),
     ("fd_destroy", None, [_vp]),
+    ("wq_eval_setup", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, C.c_int, _vp, C.c_size_t, _szp,
+                                _vp, C.POINTER(C.c_void_p)]),
+    ("wq_eval_dims", C.c_int, [_vp, _i32p, _i32p]),
+    ("wq_eval_slab", C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _vp, _vp, _vp, _vp]),
+    ("wq_eval_destroy", None, [_vp]),
     ("krylov_ws_bytes", C.c_size_t, [_vp]),
     ("krylov_solve", C.c_int, [_vp, _vp, C.c_int, _vp, _vp, C.c_double, C.c_int, _vp, C.c_size_t, _ip, _dp,
                                _vp]),
@@ -59,7 +67,7 @@ SIGNATURES = [
     ("ir_fallback_count", C.c_int, []),
     ("wq_space_1d", C.c_int, [C.c_int, C.c_int, _vp, _i32p, _i32p, _vp, _vp, _vp]),
     ("fd_eig_1d", C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp]),
-    ("wq_geometry_host", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, _vp, _vp]),
+    ("wq_geometry_host", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, _vp, _vp, _vp]),
     ("wq_last_error", C.c_char_p, []),
     ("wq_version", C.c_char_p, []),
 ]

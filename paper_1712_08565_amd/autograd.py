@@ -13,7 +13,7 @@ for an upstream gradient g = dL/du,
     dL/dalpha_q = -det J(q) (W^(00)T lam)_q (B u)_q
 
 Every step runs in libwqfd.so (wq_set_coef, wq_set_alpha, wq_rhs, krylov_solve,
-wq_grad_K, wq_grad_f, wq_grad_alpha); this module only marshals tensors.
+wq_grad_K, wq_grad_f, wq_grad_Kf, wq_grad_alpha); this module only marshals tensors.
 """
 from __future__ import annotations
 
@@ -54,10 +54,14 @@ class _WqSolve(torch.autograd.Function):
             wqfd.wq_set_coef(A, A.k_kind, K_q)
         wqfd.wq_set_alpha(A, alpha_q)
         lam, _, _ = wqfd.krylov_solve(A, P, gu.contiguous(), transpose=True, rtol=ctx.rtol, maxit=ctx.maxit)
-        gK = wqfd.wq_grad_K(A, lam, u) if (need_K and ctx.has_K) else None
+        want_K = need_K and ctx.has_K
+        if want_K and need_f:
+            gK, gf = wqfd.wq_grad_Kf(A, lam, u)          # one pass for both
+        else:
+            gK = wqfd.wq_grad_K(A, lam, u) if want_K else None
+            gf = wqfd.wq_grad_f(A, lam) if need_f else None
         if gK is not None:
             gK = gK.view_as(K_q)
-        gf = wqfd.wq_grad_f(A, lam) if need_f else None
         ga = wqfd.wq_grad_alpha(A, lam, u) if (need_a and ctx.has_alpha) else None
         return gK, gf, ga, None, None, None, None
 

@@ -24,6 +24,9 @@ struct wq_op_s {
 struct fd_pc_s {
     wqfd::FdPc pc;
 };
+struct wq_eval_s {
+    wqfd::EvalOp E;
+};
 
 namespace {
 
@@ -475,9 +478,10 @@ extern "C" {
 const char* wq_last_error(void) { return g_err.c_str(); }
 const char* wq_version(void) { return "wqfd 0.1 (gfx950)"; }
 
-// wq_setup and wq_setup_gauss: the same operator set-up for the two quadrature rules
+// wq_setup, wq_setup_nurbs and wq_setup_gauss: the same operator set-up for the
+// two quadrature rules and for polynomial or rational (weights != null) maps
 static int setup_impl(int rule, int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
-                      int k_kind, const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed,
+                      const double* weights, int k_kind, const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed,
                       wq_stream_t s_, wq_op* out) {
     g_err.clear();
     hipStream_t s = reinterpret_cast<hipStream_t>(s_);
@@ -601,7 +605,7 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
 
     // geometry on the host
     std::vector<double> hdet(o.Nq), hjinv(9 * o.Nq), hF(3 * o.Nq);
-    rc = wqfd::geometry_at_quad(sp, ctrl, hdet.data(), hjinv.data(), hF.data(), err, nthreads());
+    rc = wqfd::geometry_at_quad(sp, ctrl, weights, hdet.data(), hjinv.data(), hF.data(), err, nthreads());
     if (rc) return fail(rc, err);
 
     char* base = static_cast<char*>(ws);
@@ -679,14 +683,23 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
 int wq_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
              const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s,
              wq_op* out) {
-    return setup_impl(wqfd::kRuleWQ, p, nknots, knots, ctrl, k_kind, K_q, prec_mask, ws, ws_bytes, ws_needed, s, out);
+    return setup_impl(wqfd::kRuleWQ, p, nknots, knots, ctrl, nullptr, k_kind, K_q, prec_mask, ws, ws_bytes, ws_needed,
+                      s, out);
+}
+
+int wq_setup_nurbs(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                   const double* weights, int k_kind, const double* K_q, int prec_mask, void* ws, size_t ws_bytes,
+                   size_t* ws_needed, wq_stream_t s, wq_op* out) {
+    if (!weights) return fail(WQ_EINVAL, "null weights");
+    return setup_impl(wqfd::kRuleWQ, p, nknots, knots, ctrl, weights, k_kind, K_q, prec_mask, ws, ws_bytes,
+                      ws_needed, s, out);
 }
 
 int wq_setup_gauss(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, int k_kind,
                    const double* K_q, int prec_mask, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s,
                    wq_op* out) {
-    return setup_impl(wqfd::kRuleGauss, p, nknots, knots, ctrl, k_kind, K_q, prec_mask, ws, ws_bytes, ws_needed, s,
-                      out);
+    return setup_impl(wqfd::kRuleGauss, p, nknots, knots, ctrl, nullptr, k_kind, K_q, prec_mask, ws, ws_bytes,
+                      ws_needed, s, out);
 }
 
 int wq_dims(wq_op A, int32_t n[3], int32_t nq[3]) {
@@ -800,6 +813,12 @@ int wq_grad_K(wq_op A, const double* lam, const double* u, double* gK, wq_stream
 int wq_grad_f(wq_op A, const double* lam, double* gf, wq_stream_t s) {
     if (!A || !lam || !gf) return fail(WQ_EINVAL, "null argument");
     HIP_TRY(wqfd::launch_grad_f(A->op, lam, gf, reinterpret_cast<hipStream_t>(s)), "wq_grad_f");
+    return WQ_OK;
+}
+
+int wq_grad_Kf(wq_op A, const double* lam, const double* u, double* gK, double* gf, wq_stream_t s) {
+    if (!A || !lam || !u || !gK || !gf) return fail(WQ_EINVAL, "null argument");
+    HIP_TRY(wqfd::launch_grad_Kf(A->op, lam, u, gK, gf, reinterpret_cast<hipStream_t>(s)), "wq_grad_Kf");
     return WQ_OK;
 }
 
@@ -1013,8 +1032,8 @@ int fd_eig_1d(int p, int nknots, const double* knots, double* lam, double* U) {
     return WQ_OK;
 }
 
-int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl, double* detJ,
-                     double* Jinv, double* F) {
+int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                     const double* weights, double* detJ, double* Jinv, double* F) {
     g_err.clear();
     int rc = check_knots_args(p, nknots, knots);
     if (rc) return rc;
@@ -1025,9 +1044,89 @@ int wq_geometry_host(int p, const int32_t nknots[3], const double* const knots[3
         rc = wqfd::build_space(p, nknots[l], knots[l], false, sp[l], err);
         if (rc) return fail(rc, err);
     }
-    rc = wqfd::geometry_at_quad(sp, ctrl, detJ, Jinv, F, err, nthreads());
+    rc = wqfd::geometry_at_quad(sp, ctrl, weights, detJ, Jinv, F, err, nthreads());
     return rc ? fail(rc, err) : WQ_OK;
 }
+
+// ------------------------------------------------------------------------ evaluation at Gauss points
+int wq_eval_setup(int p, const int32_t nknots[3], const double* const knots[3], const double* ctrl,
+                  const double* weights, int ng, void* ws, size_t ws_bytes, size_t* ws_needed, wq_stream_t s_,
+                  wq_eval* out) {
+    g_err.clear();
+    hipStream_t s = reinterpret_cast<hipStream_t>(s_);
+    int rc = check_knots_args(p, nknots, knots);
+    if (rc) return rc;
+    if (!ctrl) return fail(WQ_EINVAL, "null control points");
+    if (!ws && !ws_needed) return fail(WQ_EINVAL, "need ws or ws_needed");
+    if (ws && !out) return fail(WQ_EINVAL, "null output handle");
+    wqfd::GaussSpace1D G[3];
+    std::string err;
+    for (int l = 0; l < 3; ++l) {
+        rc = wqfd::gauss_space(p, nknots[l], knots[l], ng, G[l], err);
+        if (rc) return fail(rc, "direction " + std::to_string(l + 1) + ": " + err);
+    }
+    const size_t M = (size_t)G[0].m * G[1].m * G[2].m;
+    std::vector<double> hom(M * 4);
+    for (size_t k = 0; k < M; ++k) {
+        const double w = weights ? weights[k] : 1.0;
+        if (!(w > 0.0)) return fail(WQ_EINVAL, "every control weight must be positive");
+        for (int a = 0; a < 3; ++a) hom[4 * k + a] = w * ctrl[3 * k + a];
+        hom[4 * k + 3] = w;
+    }
+    Packer pk;
+    size_t o_first[3], o_B[3], o_D[3], o_w[3];
+    for (int l = 0; l < 3; ++l) {
+        o_first[l] = pk.add(G[l].first.data(), G[l].first.size() * sizeof(int));
+        o_B[l] = pk.add(G[l].B.data(), G[l].B.size() * 8);
+        o_D[l] = pk.add(G[l].D.data(), G[l].D.size() * 8);
+        o_w[l] = pk.add(G[l].w.data(), G[l].w.size() * 8);
+    }
+    const size_t o_ctrl = pk.add(hom.data(), hom.size() * 8);
+    if (ws_needed) *ws_needed = pk.buf.size();
+    if (!ws) return WQ_OK;
+    if (ws_bytes < pk.buf.size()) return fail(WQ_ENOMEM, "workspace too small for wq_eval_setup");
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(WQ_EINVAL, "workspace must be 256-byte aligned");
+    char* base = static_cast<char*>(ws);
+    HIP_TRY(hipMemcpyAsync(base, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, s), "upload eval tables");
+    auto h = std::make_unique<wq_eval_s>();
+    wqfd::EvalOp& E = h->E;
+    E.p = p;
+    E.ng = ng;
+    for (int l = 0; l < 3; ++l) {
+        E.ne[l] = G[l].n_el;
+        E.nq[l] = G[l].nq;
+        E.m[l] = G[l].m;
+        E.n[l] = G[l].m - 2;
+        E.first[l] = reinterpret_cast<const int*>(base + o_first[l]);
+        E.B[l] = reinterpret_cast<const double*>(base + o_B[l]);
+        E.D[l] = reinterpret_cast<const double*>(base + o_D[l]);
+        E.w[l] = reinterpret_cast<const double*>(base + o_w[l]);
+    }
+    E.ctrl = reinterpret_cast<const double*>(base + o_ctrl);
+    HIP_TRY(hipStreamSynchronize(s), "wq_eval_setup sync");
+    *out = h.release();
+    return WQ_OK;
+}
+
+int wq_eval_dims(wq_eval E, int32_t ne[3], int32_t nq[3]) {
+    if (!E) return fail(WQ_EINVAL, "null handle");
+    for (int l = 0; l < 3; ++l) {
+        if (ne) ne[l] = E->E.ne[l];
+        if (nq) nq[l] = E->E.nq[l];
+    }
+    return WQ_OK;
+}
+
+int wq_eval_slab(wq_eval E, const double* u, int e3_begin, int e3_end, double* X, double* wdet, double* uh,
+                 double* grad, wq_stream_t s) {
+    if (!E || !u || !X || !wdet || !uh || !grad) return fail(WQ_EINVAL, "null argument");
+    if (e3_begin < 0 || e3_end > E->E.ne[2] || e3_begin > e3_end) return fail(WQ_EINVAL, "element range outside [0, n_el3]");
+    HIP_TRY(wqfd::launch_eval_slab(E->E, u, e3_begin, e3_end, X, wdet, uh, grad, reinterpret_cast<hipStream_t>(s)),
+            "wq_eval_slab");
+    return WQ_OK;
+}
+
+void wq_eval_destroy(wq_eval E) { delete E; }
 
 // ------------------------------------------------------------------------ Krylov
 size_t krylov_ws_bytes(wq_op A) { return A ? wqfd::krylov_bytes(A->op.N, false) : 0; }

@@ -87,6 +87,20 @@ struct FdPc {
     void* scratch = nullptr;    // one N-sized buffer of the widest precision
 };
 
+// Evaluation tables of a discrete solution at tensor Gauss points (eval.hip):
+// per direction the first non-zero B-spline, values and derivatives [nq][p+1]
+// and scaled Gauss weights of each point; the homogeneous control net
+// [m3][m2][m1][4] = (w P, w) of the geometry map.
+struct EvalOp {
+    int p = 0, ng = 0;
+    int ne[3] = {0, 0, 0}, nq[3] = {0, 0, 0}, m[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+    const int* first[3] = {nullptr, nullptr, nullptr};
+    const double* B[3] = {nullptr, nullptr, nullptr};
+    const double* D[3] = {nullptr, nullptr, nullptr};
+    const double* w[3] = {nullptr, nullptr, nullptr};
+    const double* ctrl = nullptr;
+};
+
 // ---------------------------------------------------------------- launchers
 // MF-WQ operator (wq_kernels.hip)
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask);
@@ -97,10 +111,18 @@ hipError_t launch_apply(const WqOp& op, int prec, const void* v, void* w, bool t
 hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t s);
 hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s);
 hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s);
+// both in one pass over the quadrature points (fused operators), else one after the other
+hipError_t launch_grad_Kf(const WqOp& op, const double* lam, const double* u, double* gK, double* gf,
+                          hipStream_t s);
 // reaction term: Cm = alpha det J (both prepared precisions), w = M~ v, dJ/dalpha
 hipError_t launch_set_alpha(const WqOp& op, const double* alpha_q, hipStream_t s);
 hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, hipStream_t s);
 hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s);
+
+// u_h, grad u_h, F and w |det J| at the Gauss points of elements
+// [e3_begin, e3_end) along z (all elements in x and y); outputs [3][n], [n], [n], [3][n]
+hipError_t launch_eval_slab(const EvalOp& E, const double* u, int e3_begin, int e3_end, double* X, double* wdet,
+                            double* uh, double* grad, hipStream_t s);
 
 // FD preconditioner (fd_kernels.hip).  `scratch` holds the intermediate between
 // the passes: N values of the precision's type (at most N * 8 bytes).

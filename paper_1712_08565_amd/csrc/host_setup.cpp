@@ -388,14 +388,52 @@ int build_space(int p, int nknots, const double* knots, bool with_weights, Space
     return WQ_OK;
 }
 
-int geometry_at_quad(const Space1D* sp, const double* ctrl, double* detJ, double* Jinv, double* F,
-                     std::string& err, int nthreads) {
+int gauss_space(int p, int nknots, const double* knots, int ng, GaussSpace1D& G, std::string& err) {
+    if (ng < 1 || ng > 32) {
+        err = "Gauss points per element must be in 1..32";
+        return WQ_EINVAL;
+    }
+    Space1D S;
+    int rc = build_space(p, nknots, knots, false, S, err);
+    if (rc) return rc;
+    std::vector<double> gx, gw;
+    gauss_legendre(ng, gx, gw);
+    G.p = p;
+    G.m = S.m;
+    G.n_el = S.n_el;
+    G.ng = ng;
+    G.nq = S.n_el * ng;
+    G.first.resize(G.nq);
+    G.B.resize((size_t)G.nq * (p + 1));
+    G.D.resize((size_t)G.nq * (p + 1));
+    G.w.resize(G.nq);
+    for (int e = 0; e < S.n_el; ++e) {
+        const double a = S.breaks[e], b = S.breaks[e + 1];
+        for (int g = 0; g < ng; ++g) {
+            // ascending points inside the element (the rule's nodes run from +1 down)
+            const double t = gx[ng - 1 - g];
+            const int q = e * ng + g;
+            const double x = 0.5 * (a + b) + 0.5 * (b - a) * t;
+            const int mu = eval_nonzero(S.knots, p, S.m, x, &G.B[(size_t)q * (p + 1)], &G.D[(size_t)q * (p + 1)]);
+            G.first[q] = mu - p;
+            G.w[q] = 0.5 * (b - a) * gw[ng - 1 - g];
+        }
+    }
+    return WQ_OK;
+}
+
+namespace {
+
+// Sum factorization of a control net with NC components per point (x, y, z, and
+// for a rational map the weight last, the first three multiplied by it): value
+// and parametric gradient of every component at the quadrature points of plane
+// k3 range [k_begin, k_end) with stride, handed to `at(q, value[NC], grad[NC][3])`.
+template <int NC, typename At>
+void sum_factorize(const Space1D* sp, const double* ctrl, int tid, int nthreads, At&& at) {
     const Space1D &S1 = sp[0], &S2 = sp[1], &S3 = sp[2];
     const int p = S1.p;
     const int m1 = S1.m, m2 = S2.m;
     const int nq1 = S1.nq, nq2 = S2.nq, nq3 = S3.nq;
-    const size_t Nq = (size_t)nq1 * nq2 * nq3;
-    // non-zero basis values at the quadrature points, per direction
     struct Nz {
         std::vector<int> first;
         std::vector<double> v, d;
@@ -411,75 +449,120 @@ int geometry_at_quad(const Space1D* sp, const double* ctrl, double* detJ, double
             nz[l].first[q] = mu - p;
         }
     }
-    std::vector<int> bad(nthreads, 0);
-    auto work = [&](int tid) {
-        // per quad plane: z contraction, then y, then x
-        std::vector<double> Pz0((size_t)m2 * m1 * 3), Pz1((size_t)m2 * m1 * 3);
-        std::vector<double> Y00((size_t)m1 * 3), Y01((size_t)m1 * 3), Y10((size_t)m1 * 3);
-        for (int k = tid; k < nq3; k += nthreads) {
-            std::fill(Pz0.begin(), Pz0.end(), 0.0);
-            std::fill(Pz1.begin(), Pz1.end(), 0.0);
-            const int f3 = nz[2].first[k];
-            for (int r = 0; r <= p; ++r) {
-                const double bv = nz[2].v[(size_t)k * (p + 1) + r], bd = nz[2].d[(size_t)k * (p + 1) + r];
-                const double* P = ctrl + (size_t)(f3 + r) * m2 * m1 * 3;
-                for (size_t t = 0; t < (size_t)m2 * m1 * 3; ++t) {
-                    Pz0[t] += bv * P[t];
-                    Pz1[t] += bd * P[t];
-                }
-            }
-            for (int q2 = 0; q2 < nq2; ++q2) {
-                std::fill(Y00.begin(), Y00.end(), 0.0);
-                std::fill(Y01.begin(), Y01.end(), 0.0);
-                std::fill(Y10.begin(), Y10.end(), 0.0);
-                const int f2 = nz[1].first[q2];
-                for (int r = 0; r <= p; ++r) {
-                    const double bv = nz[1].v[(size_t)q2 * (p + 1) + r], bd = nz[1].d[(size_t)q2 * (p + 1) + r];
-                    const double* A0 = &Pz0[(size_t)(f2 + r) * m1 * 3];
-                    const double* A1 = &Pz1[(size_t)(f2 + r) * m1 * 3];
-                    for (int t = 0; t < m1 * 3; ++t) {
-                        Y00[t] += bv * A0[t];
-                        Y01[t] += bd * A0[t];
-                        Y10[t] += bv * A1[t];
-                    }
-                }
-                for (int q1 = 0; q1 < nq1; ++q1) {
-                    const int f1 = nz[0].first[q1];
-                    double Fv[3] = {0, 0, 0}, J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-                    for (int r = 0; r <= p; ++r) {
-                        const double bv = nz[0].v[(size_t)q1 * (p + 1) + r], bd = nz[0].d[(size_t)q1 * (p + 1) + r];
-                        const int j = f1 + r;
-                        for (int a = 0; a < 3; ++a) {
-                            Fv[a] += bv * Y00[j * 3 + a];
-                            J[a][0] += bd * Y00[j * 3 + a];
-                            J[a][1] += bv * Y01[j * 3 + a];
-                            J[a][2] += bv * Y10[j * 3 + a];
-                        }
-                    }
-                    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-                    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-                    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-                    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-                    const size_t q = ((size_t)k * nq2 + q2) * nq1 + q1;
-                    if (!(det > 0.0)) bad[tid] = 1;
-                    const double id = 1.0 / det;
-                    double Ji[3][3];
-                    Ji[0][0] = c00 * id;
-                    Ji[1][0] = c01 * id;
-                    Ji[2][0] = c02 * id;
-                    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-                    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-                    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-                    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-                    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-                    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-                    detJ[q] = det;
-                    for (int r = 0; r < 3; ++r)
-                        for (int c = 0; c < 3; ++c) Jinv[(size_t)(3 * r + c) * Nq + q] = Ji[r][c];
-                    for (int a = 0; a < 3; ++a) F[(size_t)a * Nq + q] = Fv[a];
-                }
+    // per quad plane: z contraction, then y, then x
+    std::vector<double> Pz0((size_t)m2 * m1 * NC), Pz1((size_t)m2 * m1 * NC);
+    std::vector<double> Y00((size_t)m1 * NC), Y01((size_t)m1 * NC), Y10((size_t)m1 * NC);
+    for (int k = tid; k < nq3; k += nthreads) {
+        std::fill(Pz0.begin(), Pz0.end(), 0.0);
+        std::fill(Pz1.begin(), Pz1.end(), 0.0);
+        const int f3 = nz[2].first[k];
+        for (int r = 0; r <= p; ++r) {
+            const double bv = nz[2].v[(size_t)k * (p + 1) + r], bd = nz[2].d[(size_t)k * (p + 1) + r];
+            const double* P = ctrl + (size_t)(f3 + r) * m2 * m1 * NC;
+            for (size_t t = 0; t < (size_t)m2 * m1 * NC; ++t) {
+                Pz0[t] += bv * P[t];
+                Pz1[t] += bd * P[t];
             }
         }
+        for (int q2 = 0; q2 < nq2; ++q2) {
+            std::fill(Y00.begin(), Y00.end(), 0.0);
+            std::fill(Y01.begin(), Y01.end(), 0.0);
+            std::fill(Y10.begin(), Y10.end(), 0.0);
+            const int f2 = nz[1].first[q2];
+            for (int r = 0; r <= p; ++r) {
+                const double bv = nz[1].v[(size_t)q2 * (p + 1) + r], bd = nz[1].d[(size_t)q2 * (p + 1) + r];
+                const double* A0 = &Pz0[(size_t)(f2 + r) * m1 * NC];
+                const double* A1 = &Pz1[(size_t)(f2 + r) * m1 * NC];
+                for (int t = 0; t < m1 * NC; ++t) {
+                    Y00[t] += bv * A0[t];
+                    Y01[t] += bd * A0[t];
+                    Y10[t] += bv * A1[t];
+                }
+            }
+            for (int q1 = 0; q1 < nq1; ++q1) {
+                const int f1 = nz[0].first[q1];
+                double Fv[NC], G[NC][3];
+                for (int a = 0; a < NC; ++a) Fv[a] = G[a][0] = G[a][1] = G[a][2] = 0.0;
+                for (int r = 0; r <= p; ++r) {
+                    const double bv = nz[0].v[(size_t)q1 * (p + 1) + r], bd = nz[0].d[(size_t)q1 * (p + 1) + r];
+                    const int j = f1 + r;
+                    for (int a = 0; a < NC; ++a) {
+                        Fv[a] += bv * Y00[j * NC + a];
+                        G[a][0] += bd * Y00[j * NC + a];
+                        G[a][1] += bv * Y01[j * NC + a];
+                        G[a][2] += bv * Y10[j * NC + a];
+                    }
+                }
+                at(((size_t)k * nq2 + q2) * nq1 + q1, Fv, G);
+            }
+        }
+    }
+}
+
+// det J, J^{-1} (plane 3 r + c) and F of one point; false if det J <= 0
+inline bool store_point(size_t q, size_t Nq, const double (&Fv)[3], const double (&J)[3][3], double* detJ,
+                        double* Jinv, double* F) {
+    const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+    const double id = 1.0 / det;
+    double Ji[3][3];
+    Ji[0][0] = c00 * id;
+    Ji[1][0] = c01 * id;
+    Ji[2][0] = c02 * id;
+    Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+    Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+    Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+    Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+    Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+    Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    detJ[q] = det;
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Jinv[(size_t)(3 * r + c) * Nq + q] = Ji[r][c];
+    for (int a = 0; a < 3; ++a) F[(size_t)a * Nq + q] = Fv[a];
+    return det > 0.0;
+}
+
+}  // namespace
+
+int geometry_at_quad(const Space1D* sp, const double* ctrl, const double* weights, double* detJ, double* Jinv,
+                     double* F, std::string& err, int nthreads) {
+    const size_t Nq = (size_t)sp[0].nq * sp[1].nq * sp[2].nq;
+    const size_t M = (size_t)sp[0].m * sp[1].m * sp[2].m;
+    std::vector<int> bad(nthreads, 0);
+    std::vector<double> hom;
+    if (weights) {
+        // homogeneous control net (w P, w): the rational map is the quotient of
+        // two polynomial splines, F = (sum w_k P_k b_k) / (sum w_k b_k)
+        for (size_t k = 0; k < M; ++k)
+            if (!(weights[k] > 0.0)) {
+                err = "rational map: every control weight must be positive";
+                return WQ_EINVAL;
+            }
+        hom.resize(M * 4);
+        for (size_t k = 0; k < M; ++k) {
+            for (int a = 0; a < 3; ++a) hom[4 * k + a] = weights[k] * ctrl[3 * k + a];
+            hom[4 * k + 3] = weights[k];
+        }
+    }
+    auto work = [&](int tid) {
+        if (!weights) {
+            sum_factorize<3>(sp, ctrl, tid, nthreads, [&](size_t q, const double (&Fv)[3], const double (&J)[3][3]) {
+                if (!store_point(q, Nq, Fv, J, detJ, Jinv, F)) bad[tid] = 1;
+            });
+            return;
+        }
+        // quotient rule: dF_a/dxi_b = (dP_a/dxi_b - F_a dW/dxi_b) / W
+        sum_factorize<4>(sp, hom.data(), tid, nthreads,
+                         [&](size_t q, const double (&Pv)[4], const double (&G)[4][3]) {
+                             const double iw = 1.0 / Pv[3];
+                             double Fv[3], J[3][3];
+                             for (int a = 0; a < 3; ++a) Fv[a] = Pv[a] * iw;
+                             for (int a = 0; a < 3; ++a)
+                                 for (int b = 0; b < 3; ++b) J[a][b] = (G[a][b] - Fv[a] * G[3][b]) * iw;
+                             if (!store_point(q, Nq, Fv, J, detJ, Jinv, F)) bad[tid] = 1;
+                         });
     };
     std::vector<std::thread> th;
     for (int t = 1; t < nthreads; ++t) th.emplace_back(work, t);

@@ -39,15 +39,29 @@ struct Space1D {
 int build_space(int p, int nknots, const double* knots, bool with_weights, Space1D& out,
                 std::string& err, int rule = kRuleWQ);
 
+// Tensor Gauss rule of ng points per element and direction, for evaluating a
+// discrete solution (the error measure of Section 4): per point the first of
+// the p+1 B-splines that are non-zero there, their values and derivatives, and
+// the Gauss weight scaled to the element.  Points ascend.
+struct GaussSpace1D {
+    int p = 0, m = 0, n_el = 0, ng = 0, nq = 0;   // nq = n_el ng
+    std::vector<int> first;                      // [nq]
+    std::vector<double> B, D;                    // [nq][p+1]
+    std::vector<double> w;                       // [nq]
+};
+int gauss_space(int p, int nknots, const double* knots, int ng, GaussSpace1D& out, std::string& err);
+
 // Values and first derivatives of the p+1 B-splines that are non-zero on the
 // knot span containing x (span index returned; x == 1 uses the last span).
 int eval_nonzero(const std::vector<double>& knots, int p, int m, double x, double* N, double* dN);
 
 // Geometry at the quadrature points: detJ [Nq] and J^{-1} [9][Nq] (row-major
 // 3x3 per point, entry (r, c) in plane 3 r + c) and F [3][Nq], from control
-// points ctrl[m3][m2][m1][3].  Returns 0, or WQ_EGEOM if det J <= 0 somewhere.
-int geometry_at_quad(const Space1D* sp, const double* ctrl, double* detJ, double* Jinv,
-                     double* F, std::string& err, int nthreads);
+// points ctrl[m3][m2][m1][3] and, for a rational (NURBS) map, positive weights
+// [m3][m2][m1] (null: polynomial map).  Returns 0, WQ_EINVAL for a weight
+// <= 0, or WQ_EGEOM if det J <= 0 somewhere.
+int geometry_at_quad(const Space1D* sp, const double* ctrl, const double* weights, double* detJ,
+                     double* Jinv, double* F, std::string& err, int nthreads);
 
 // Generalized symmetric eigenproblem K U = M U diag(lam), U^T M U = I by
 // Cholesky of M and cyclic Jacobi on L^{-1} K L^{-T}.  U row-major [n][n]

@@ -14,6 +14,7 @@
 // coalesced accesses along x.
 #include <hip/hip_runtime.h>
 
+#include "buffer.h"
 #include "device.h"
 
 namespace wqfd {
@@ -332,138 +333,233 @@ __global__ __launch_bounds__(kThreads) void grad_K_kernel(const double* __restri
     }
 }
 
-// Fused x/y stage of the gradient expansion (p <= 7, operators with the fused
-// tables).  With the z contractions done (Tl[v3] = W3^(v3)T lam and
-// Tu[b3] = B3^(b3) u, arrays [n_q3][n2][n1]), one workgroup per 16 x 16 tile of
-// quadrature columns and a range of quadrature planes forms, per plane and from
-// the tile's dense 16 x 16 factor blocks (the fused apply's tables), the nine
-// values (W^(ab)T lam)_q and the three values (B^(b) u)_q at its 256 points, as
-// 24 products of 16 x 16 blocks on the matrix cores (y first, then x, in place in
-// LDS), multiplies them to g_ab = -(W^(ab)T lam)_q (B^(b) u)_q and chains g to the
-// layout of K_q: no N_q-sized intermediate is written.
+// Fused gradient expansion (p <= 7, operators with the fused tables).  One
+// workgroup per 16 x 16 tile of quadrature columns and a range of quadrature
+// planes; each of its four waves takes whole planes on its own (no barrier after
+// the factor blocks are in LDS).  Per plane a wave
+//   * contracts z in registers: the rows of the tile's test window of
+//     W3^(v)T lam (v = 0..3, from the p + 2 planes of lam the plane's weights
+//     touch) and of the trial window of B3 u and B-dot3 u;
+//   * forms, as products of 16 x 16 blocks on the matrix cores, the y products
+//     transposed (C'[i1][q2]) and then the x products (out[q2][q1]): the y
+//     result, as it sits in the accumulator registers, is exactly the A operand
+//     of the x product, so nothing goes through LDS;
+//   * takes the nine values (W^(ab)T lam)_q, the three (B^(b) u)_q and, when
+//     dJ/df is wanted, (W^(00)T lam)_q at the lane's four points and writes
+//     g_ab = -(W^(ab)T lam)_q (B^(b) u)_q, summed over symmetric pairs and
+//     chained to the layout of K_q, and det J (W^(00)T lam)_q.
+// No N_q-sized or z-contracted intermediate is written.
 typedef double gd4 __attribute__((ext_vector_type(4)));
-constexpr int GLD = 17;
-constexpr int GBLK = 16 * GLD;
 
-// c += A B for 16 x 16 blocks in LDS: A[m][k] = At[m][k]; B[k][n] = Bt[k][n]
-// (BT = false) or Bt[n][k] (BT = true).  FP64 MFMA operand layout: lane l holds
-// A row l % 16 and B column l % 16 of the k-block l / 16; result row kb + 4 v.
-template <bool BT>
-__device__ inline gd4 gemm16_lds(const double* At, const double* Bt, gd4 c, int cl, int kb) {
-    double a[4], b[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        a[s] = At[cl * GLD + 4 * s + kb];
-        b[s] = BT ? Bt[cl * GLD + 4 * s + kb] : Bt[(4 * s + kb) * GLD + cl];
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
-    return c;
-}
-
-struct GradXYArgs {
+struct GradFusedArgs {
     const double* tilesX = nullptr;
     const double* tilesY = nullptr;
     const int* JX = nullptr;
     const int* IX = nullptr;
     const int* JY = nullptr;
     const int* IY = nullptr;
-    const double* Tl = nullptr;      // [4][nq3][n2][n1]
-    const double* Tu = nullptr;      // [2][nq3][n2][n1]
+    const int* bs3 = nullptr;
+    const int* wts3 = nullptr;
+    const double* cz = nullptr;     // [nq3][2(p+1) + 4(p+2)]: B3, B-dot3 rows, W3^(v) columns
+    const double* lam = nullptr;
+    const double* u = nullptr;
     const double* detJ = nullptr;
     const double* Jinv = nullptr;
-    double* out = nullptr;
+    double* gK = nullptr;           // dJ/dK (nullptr: not wanted)
+    double* gf = nullptr;           // dJ/df (nullptr: not wanted)
     int k_kind = 0;
-    int n1 = 0, n2 = 0, nq1 = 0, nq2 = 0, nq3 = 0, ntx = 0, nty = 0, zchunk = 0;
+    int n1 = 0, n2 = 0, n3 = 0, nq1 = 0, nq2 = 0, nq3 = 0, ntx = 0, nty = 0, zchunk = 0;
     size_t Nq = 0;
 };
 
-__global__ __launch_bounds__(256) void grad_xy_kernel(GradXYArgs a) {
-    // factor blocks: 0-3 W2^(v) as [q2][i2]; 4, 5 B2_d as [q2][j2]; 6-9 W1^(v) as [i1][q1];
-    // 10, 11 B1_d as [q1][j1] (v = 2 [test derivative] + [trial derivative])
-    __shared__ double sT[12][GBLK];
-    __shared__ double sD[6][GBLK];      // plane data: 0-3 Tl[v3] as [i2][i1], 4, 5 Tu[b3] as [j2][j1]
-    __shared__ double sY[12][GBLK];     // y products, then (in place) the values at the points
+// 16 x 16 x 16 product on the matrix cores: A per lane as a[s] = A[cl][4s + kb]
+// (FP64 operand layout: lane l holds row l % 16 of k-block l / 16), B from LDS
+// stored [k][n] (lane reads T[4s + kb][cl]); result c[v] = C[kb + 4v][cl].
+__device__ inline gd4 mm16(const double (&a)[4], const double* __restrict__ T, int cl, int kb) {
+    gd4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], T[(4 * s + kb) * 16 + cl], c, 0, 0, 0);
+    return c;
+}
+
+// y then x product of one field: D given as the lane's A operand of the y
+// product (D[i2 = 4s + kb][i1 = cl]); Ty [i2][q2] and Tx [i1][q1] in LDS.
+__device__ inline gd4 yx16(const double (&d)[4], const double* Ty, const double* Tx, int cl, int kb) {
+    // one scheduling region per product: measured faster than letting the
+    // compiler interleave products (102 vs 122 us on ring 64^3, p = 3)
+    asm volatile("" ::: "memory");
+    const gd4 y = mm16(d, Ty, cl, kb);                 // y[v] = C'[i1 = kb + 4v][q2 = cl]
+    const double ya[4] = {y[0], y[1], y[2], y[3]};     // = A[q2 = cl][i1 = 4s + kb] of the x product
+    return mm16(ya, Tx, cl, kb);                       // out[q2 = kb + 4v][q1 = cl]
+}
+
+// KK: coefficient kind of the output (0: the six C planes, else chained through
+// eq. C).  Memory goes through raw buffer accesses (buffer.h): array bases and
+// plane offsets in scalar registers, the lane's 32-bit byte offset in a vector
+// register (the launcher checks that N and N_q stay below 2^32 bytes per plane
+// set).
+template <int P, int KK>
+__global__ __launch_bounds__(256) void grad_fused_kernel(GradFusedArgs a) {
+    constexpr int RT = P + 1, RO = P + 2, CZ = 2 * RT + 4 * RO;
+    // factor blocks as [k][n]: 0-3 W2^(v) [i2][q2]; 4, 5 B2_d [j2][q2]; 6-9 W1^(v) [i1][q1];
+    // 10, 11 B1_d [j1][q1] (v = 2 [test derivative] + [trial derivative], d = trial derivative)
+    __shared__ double sT[12][256];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int cl = lane & 15, kb = lane >> 4;
-    const int tx = tid & 15, ty = tid >> 4;
     const int lin = blockIdx.x;
     const int t1 = lin % a.ntx, t2 = (lin / a.ntx) % a.nty, zc = lin / (a.ntx * a.nty);
     const int k0 = zc * a.zchunk, k1 = min(a.nq3, k0 + a.zchunk);
-    if (k0 >= k1) return;
-    const int I1 = a.IX[t1], J1 = a.JX[t1], I2 = a.IY[t2], J2 = a.JY[t2];
+    if (k0 >= k1) return;                              // uniform over the workgroup
     for (int e = tid; e < 12 * 256; e += 256) {
         const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
+        double val;
         if (b < 4)
-            sT[b][c * GLD + r] = a.tilesY[((size_t)t2 * 6 + 2 + b) * 256 + r * 16 + c];
+            val = a.tilesY[((size_t)t2 * 6 + 2 + b) * 256 + r * 16 + c];           // W_v[i = r][q = c]
         else if (b < 6)
-            sT[b][r * GLD + c] = a.tilesY[((size_t)t2 * 6 + (b - 4)) * 256 + r * 16 + c];
+            val = a.tilesY[((size_t)t2 * 6 + (b - 4)) * 256 + c * 16 + r];         // B_d[q = c][j = r]
         else if (b < 10)
-            sT[b][r * GLD + c] = a.tilesX[((size_t)t1 * 6 + 2 + (b - 6)) * 256 + r * 16 + c];
+            val = a.tilesX[((size_t)t1 * 6 + 2 + (b - 6)) * 256 + r * 16 + c];
         else
-            sT[b][r * GLD + c] = a.tilesX[((size_t)t1 * 6 + (b - 10)) * 256 + r * 16 + c];
+            val = a.tilesX[((size_t)t1 * 6 + (b - 10)) * 256 + c * 16 + r];
+        sT[b][r * 16 + c] = val;
     }
-    // products of this wave: pi = wave + 4 j, j = 0..2.  pi < 9: field f = pi with
-    // (v3, v2, v1) of f = 3 alpha + beta, v_l = 2 [l = alpha] + [l = beta]; pi = 9 + beta:
-    // (B^(beta) u) with (b3, b2, b1) = (beta = z, beta = y, beta = x)
-    const size_t zsz = (size_t)a.nq3 * a.n2 * a.n1;
-    const int q1 = 16 * t1 + tx, q2 = 16 * t2 + ty;
-    const bool in = q1 < a.nq1 && q2 < a.nq2;
-    for (int k = k0; k < k1; ++k) {
-        for (int e = tid; e < 6 * 256; e += 256) {
-            const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            double val = 0.0;
-            if (b < 4) {
-                const int i2 = I2 + r, i1 = I1 + c;
-                if (i2 < a.n2 && i1 < a.n1) val = a.Tl[b * zsz + ((size_t)k * a.n2 + i2) * a.n1 + i1];
-            } else {
-                const int j2 = J2 + r, j1 = J1 + c;
-                if (j2 < a.n2 && j1 < a.n1) val = a.Tu[(b - 4) * zsz + ((size_t)k * a.n2 + j2) * a.n1 + j1];
-            }
-            sD[b][r * GLD + c] = val;
-        }
-        __syncthreads();
+    __syncthreads();
+    // the lane's rows 4s + kb and column cl of the test (I) and trial (J) DOF
+    // windows (byte offsets in a plane), clamped into the arrays: the factor
+    // blocks are zero beyond n
+    const int I1 = a.IX[t1], J1 = a.JX[t1], I2 = a.IY[t2], J2 = a.JY[t2];
+    const int i1 = min(I1 + cl, a.n1 - 1), j1 = min(J1 + cl, a.n1 - 1);
+    unsigned offL[4], offU[4];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {                    // y products
-            const int pi = wave + 4 * j;
-            gd4 c = {0, 0, 0, 0};
-            if (pi < 9) {
-                const int al = pi / 3, be = pi % 3;
-                const int v2 = 2 * (al == 1) + (be == 1), v3 = 2 * (al == 2) + (be == 2);
-                c = gemm16_lds<false>(sT[v2], sD[v3], c, cl, kb);
-            } else {
-                const int be = pi - 9;
-                c = gemm16_lds<false>(sT[4 + (be == 1)], sD[4 + (be == 2)], c, cl, kb);
-            }
+    for (int s = 0; s < 4; ++s) {
+        offL[s] = 8u * (unsigned)(min(I2 + 4 * s + kb, a.n2 - 1) * a.n1 + i1);
+        offU[s] = 8u * (unsigned)(min(J2 + 4 * s + kb, a.n2 - 1) * a.n1 + j1);
+    }
+    const unsigned plb = 8u * (unsigned)(a.n2 * a.n1);                 // bytes of a DOF plane
+    const unsigned pqb = 8u * (unsigned)(a.nq2 * a.nq1);               // bytes of a quadrature plane
+    const __amdgpu_buffer_rsrc_t rl = buf_rsrc(a.lam), ru = buf_rsrc(a.u), rd = buf_rsrc(a.detJ);
+    const int q1 = 16 * t1 + cl;
+    const bool wantK = a.gK != nullptr, wantF = a.gf != nullptr;
+    for (int k = k0 + wave; k < k1; k += 4) {
+        // keeps the factor operands in LDS (read per product) instead of 96
+        // registers held across the loop
+        asm volatile("" ::: "memory");
+        const double* __restrict__ c = a.cz + (size_t)k * CZ;
+        const unsigned kq = (unsigned)k * pqb;
+        // trial side first: B3 u, B-dot3 u in z, then (B^(b) u) at the lane's points
+        gd4 Bu[3];
+        if (wantK) {
+            double Du[2][4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sY[pi][(kb + 4 * v) * GLD + cl] = c[v];
-        }
-        __syncthreads();
+            for (int s = 0; s < 4; ++s) Du[0][s] = Du[1][s] = 0.0;
+            const int bb = a.bs3[k];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {                    // x products (in place: operands read first)
-            const int pi = wave + 4 * j;
-            gd4 c = {0, 0, 0, 0};
-            if (pi < 9) {
-                const int al = pi / 3, be = pi % 3;
-                const int v1 = 2 * (al == 0) + (be == 0);
-                c = gemm16_lds<false>(sY[pi], sT[6 + v1], c, cl, kb);
-            } else {
-                const int be = pi - 9;
-                c = gemm16_lds<true>(sY[pi], sT[10 + (be == 0)], c, cl, kb);
+            for (int r = 0; r < RT; ++r) {
+                const unsigned so = (unsigned)min(bb + r, a.n3 - 1) * plb;
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const double x = buf_load<double>(ru, offU[s], so);
+                    Du[0][s] += c[r] * x;
+                    Du[1][s] += c[RT + r] * x;
+                }
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) sY[pi][(kb + 4 * v) * GLD + cl] = c[v];
+            for (int be = 0; be < 3; ++be) Bu[be] = yx16(Du[be == 2], sT[4 + (be == 1)], sT[10 + (be == 0)], cl, kb);
         }
-        __syncthreads();
-        if (in) {
-            double g[3][3];
-            for (int al = 0; al < 3; ++al)
-                for (int be = 0; be < 3; ++be)
-                    g[al][be] = -sY[3 * al + be][ty * GLD + tx] * sY[9 + be][ty * GLD + tx];
-            grad_chain(g, a.detJ, a.Jinv, a.k_kind, a.out, a.Nq, ((size_t)k * a.nq2 + q2) * a.nq1 + q1);
+        // test side: W3^(v)T lam in z (out-of-range planes have zero coefficients, clamped loads)
+        double Dl[4][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Dl[0][s] = Dl[1][s] = Dl[2][s] = Dl[3][s] = 0.0;
+        const int wb = a.wts3[k];
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const unsigned so = (unsigned)min(wb + r, a.n3 - 1) * plb;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double x = buf_load<double>(rl, offL[s], so);
+                if (wantK) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Dl[v][s] += c[2 * RT + v * RO + r] * x;
+                } else {
+                    Dl[0][s] += c[2 * RT + r] * x;
+                }
+            }
         }
-        __syncthreads();
+        if (wantF) {
+            const gd4 f = yx16(Dl[0], sT[0], sT[6], cl, kb);
+            const __amdgpu_buffer_rsrc_t rf = buf_rsrc(a.gf);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int q2 = 16 * t2 + kb + 4 * v;
+                if (q1 < a.nq1 && q2 < a.nq2) {
+                    const unsigned o = 8u * (unsigned)(q2 * a.nq1 + q1);
+                    buf_store<double>(buf_load<double>(rd, o, kq) * f[v], rf, o, kq);
+                }
+            }
+        }
+        if (!wantK) continue;
+        // symmetric accumulation acc[c][v], c in (11, 22, 33, 12, 13, 23): g_ab + g_ba off the diagonal
+        double acc[6][4];
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                const int v1 = 2 * (al == 0) + (be == 0), v2 = 2 * (al == 1) + (be == 1),
+                          v3 = 2 * (al == 2) + (be == 2);
+                const int pc = plane_of(al, be);
+                const bool first = al <= be;
+                const gd4 w = yx16(Dl[v3], sT[v2], sT[6 + v1], cl, kb);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double g = -w[v] * Bu[be][v];
+                    acc[pc][v] = first ? g : acc[pc][v] + g;
+                }
+            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int q2 = 16 * t2 + kb + 4 * v;
+            if (!(q1 < a.nq1 && q2 < a.nq2)) continue;
+            const unsigned o = 8u * (unsigned)(q2 * a.nq1 + q1);
+            if (KK == 0) {
+#pragma unroll
+                for (int pc = 0; pc < 6; ++pc) buf_store<double>(acc[pc][v], buf_rsrc(a.gK + pc * a.Nq), o, kq);
+                continue;
+            }
+            // chain: only the symmetric part M of g reaches dJ/dK (K and J^{-1} J^{-T} are symmetric)
+            const double M[3][3] = {{acc[0][v], 0.5 * acc[3][v], 0.5 * acc[4][v]},
+                                    {0.5 * acc[3][v], acc[1][v], 0.5 * acc[5][v]},
+                                    {0.5 * acc[4][v], 0.5 * acc[5][v], acc[2][v]}};
+            double Ji[3][3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int cc = 0; cc < 3; ++cc) Ji[r][cc] = buf_load<double>(buf_rsrc(a.Jinv + (3 * r + cc) * a.Nq), o, kq);
+            const double d = buf_load<double>(rd, o, kq);
+            if (KK == 1) {
+                double sum = 0.0;
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be)
+                        sum += M[al][be] * (Ji[al][0] * Ji[be][0] + Ji[al][1] * Ji[be][1] + Ji[al][2] * Ji[be][2]);
+                buf_store<double>(d * sum, buf_rsrc(a.gK), o, kq);
+            } else {
+                double T[3][3];   // T = M J^{-1}; H = det J J^{-T} T, H_rr and 2 H_rc stored
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc)
+                        T[al][cc] = M[al][0] * Ji[0][cc] + M[al][1] * Ji[1][cc] + M[al][2] * Ji[2][cc];
+                constexpr int R[6] = {0, 1, 2, 0, 0, 1}, Cc[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+                for (int pc = 0; pc < 6; ++pc) {
+                    const int r = R[pc], cc = Cc[pc];
+                    const double h = d * (Ji[0][r] * T[0][cc] + Ji[1][r] * T[1][cc] + Ji[2][r] * T[2][cc]);
+                    buf_store<double>(pc < 3 ? h : 2.0 * h, buf_rsrc(a.gK + pc * a.Nq), o, kq);
+                }
+            }
+        }
     }
 }
 
@@ -514,10 +610,11 @@ hipError_t apply_mass_staged(const WqOp& op, const OpTables<T>& tb, const T* Cm,
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask) {
     // staged apply in the widest precision; the staged gradient (operators
     // without the fused tables) also needs its fields (12 N_q FP64), the fused
-    // gradient only the staged layout's z-contraction arrays
+    // gradient (below 2^32 bytes per plane set) no scratch at all
     size_t e = Staged<double>::elems(op);
     size_t grad = 12 * op.Nq + 2 * (size_t)op.nq[2] * op.nq[1] * op.n[0] + 4 * (size_t)op.nq[2] * op.n[1] * op.n[0];
-    if (!op.fused && grad > e) e = grad;
+    const bool fused_grad = op.fused && op.N * 8 <= 0xffffffffull && op.Nq * 8 <= 0xffffffffull;
+    if (!fused_grad && grad > e) e = grad;
     (void)prec_mask;
     return e * sizeof(double);
 }
@@ -573,6 +670,75 @@ hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, h
     return apply_mass_staged<float>(op, op.t32, op.Cm32, static_cast<const float*>(v), static_cast<float*>(w), s);
 }
 
+// the fused gradient addresses a DOF vector and every quadrature plane set with
+// 32-bit byte offsets
+static bool grad_fused_ok(const WqOp& op) {
+    return op.fused && op.N * 8 <= 0xffffffffull && op.Nq * 8 <= 0xffffffffull;
+}
+
+static hipError_t launch_grad_fused(const WqOp& op, const double* lam, const double* u, double* gK, double* gf,
+                                    hipStream_t s) {
+    if (!grad_fused_ok(op)) return hipErrorInvalidValue;
+    const FusedArgs<double>& f = op.fz64;
+    GradFusedArgs g;
+    g.tilesX = f.tilesX;
+    g.tilesY = f.tilesY;
+    g.JX = f.JX;
+    g.IX = f.IX;
+    g.JY = f.JY;
+    g.IY = f.IY;
+    g.bs3 = f.bs3;
+    g.wts3 = f.wts3;
+    g.cz = f.cz;
+    g.lam = lam;
+    g.u = u;
+    g.detJ = op.detJ;
+    g.Jinv = op.Jinv;
+    g.gK = gK;
+    g.gf = gf;
+    g.k_kind = op.k_kind;
+    g.n1 = op.n[0];
+    g.n2 = op.n[1];
+    g.n3 = op.n[2];
+    g.nq1 = op.nq[0];
+    g.nq2 = op.nq[1];
+    g.nq3 = op.nq[2];
+    g.ntx = f.ntx;
+    g.nty = f.nty;
+    g.Nq = op.Nq;
+    // eight planes per workgroup (two per wave); 4, 12 and 16 measured no faster
+    g.zchunk = 8;
+    const int nz = (g.nq3 + g.zchunk - 1) / g.zchunk;
+    const dim3 grid(g.ntx * g.nty * nz), block(256);
+#define WQ_GRAD_LAUNCH(P)                                                                      \
+    do {                                                                                       \
+        if (g.k_kind == 0 || !gK)                                                              \
+            hipLaunchKernelGGL((grad_fused_kernel<P, 0>), grid, block, 0, s, g);               \
+        else if (g.k_kind == 1)                                                                \
+            hipLaunchKernelGGL((grad_fused_kernel<P, 1>), grid, block, 0, s, g);               \
+        else                                                                                   \
+            hipLaunchKernelGGL((grad_fused_kernel<P, 6>), grid, block, 0, s, g);               \
+    } while (0)
+    switch (op.p) {
+        case 2: WQ_GRAD_LAUNCH(2); break;
+        case 3: WQ_GRAD_LAUNCH(3); break;
+        case 4: WQ_GRAD_LAUNCH(4); break;
+        case 5: WQ_GRAD_LAUNCH(5); break;
+        case 6: WQ_GRAD_LAUNCH(6); break;
+        case 7: WQ_GRAD_LAUNCH(7); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef WQ_GRAD_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_Kf(const WqOp& op, const double* lam, const double* u, double* gK, double* gf,
+                          hipStream_t s) {
+    if (grad_fused_ok(op)) return launch_grad_fused(op, lam, u, gK, gf, s);
+    WQ_TRY(launch_grad_K(op, lam, u, gK, s));
+    return launch_grad_f(op, lam, gf, s);
+}
+
 hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s) {
     // g = det J W^(00)T lam (the chain of dJ/df), then g = -g .* (B u)
     WQ_TRY(launch_grad_f(op, lam, g, s));
@@ -599,6 +765,7 @@ hipError_t launch_rhs(const WqOp& op, const double* f_q, double* b, hipStream_t 
 }
 
 hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStream_t s) {
+    if (grad_fused_ok(op)) return launch_grad_fused(op, lam, nullptr, nullptr, gf, s);
     Staged<double> st(op, op.scratch);
     const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
     const int nq1 = op.nq[0], nq2 = op.nq[1], nq3 = op.nq[2];
@@ -611,48 +778,7 @@ hipError_t launch_grad_f(const WqOp& op, const double* lam, double* gf, hipStrea
 }
 
 hipError_t launch_grad_K(const WqOp& op, const double* lam, const double* u, double* gK, hipStream_t s) {
-    if (op.fused) {
-        // z contractions (four W3 variants of lam, B3 and B-dot3 of u) into the
-        // staged scratch, then the fused x/y stage and the chain rule
-        Staged<double> st(op, op.scratch);
-        const int n1 = op.n[0], n2 = op.n[1], n3 = op.n[2];
-        const Dir1D<double>& dz = op.t64.dir[2];
-        const size_t zsz = (size_t)op.nq[2] * n2 * n1;
-        double* Tl = st.Z[0];                           // Z[0..3] are consecutive [nq3][n2][n1] arrays
-        double* Tu = st.A;                              // A holds [nq3][nq2][n1] >= 2 [nq3][n2][n1] (nq2 > 2 n2)
-        for (int v = 0; v < 4; ++v) WQ_TRY(band<double>(2, dz.WT[v], lam, nullptr, Tl + v * zsz, n1, n2, n3, false, s));
-        WQ_TRY(band<double>(2, dz.B[0], u, nullptr, Tu, n1, n2, n3, false, s));
-        WQ_TRY(band<double>(2, dz.B[1], u, nullptr, Tu + zsz, n1, n2, n3, false, s));
-        GradXYArgs g;
-        const FusedArgs<double>& f = op.fz64;
-        g.tilesX = f.tilesX;
-        g.tilesY = f.tilesY;
-        g.JX = f.JX;
-        g.IX = f.IX;
-        g.JY = f.JY;
-        g.IY = f.IY;
-        g.Tl = Tl;
-        g.Tu = Tu;
-        g.detJ = op.detJ;
-        g.Jinv = op.Jinv;
-        g.out = gK;
-        g.k_kind = op.k_kind;
-        g.n1 = n1;
-        g.n2 = n2;
-        g.nq1 = op.nq[0];
-        g.nq2 = op.nq[1];
-        g.nq3 = op.nq[2];
-        g.ntx = f.ntx;
-        g.nty = f.nty;
-        g.Nq = op.Nq;
-        // z ranges of 8 planes: about five workgroups per CU at the benchmark sizes
-        g.zchunk = 8;
-        const int nz = (g.nq3 + g.zchunk - 1) / g.zchunk;
-        if (2 * n2 > op.nq[1] || st.Z[1] != st.Z[0] + zsz || st.Z[3] != st.Z[0] + 3 * zsz)
-            return hipErrorInvalidValue;                // scratch layout assumed above
-        hipLaunchKernelGGL(grad_xy_kernel, dim3(g.ntx * g.nty * nz), dim3(256), 0, s, g);
-        return hipGetLastError();
-    }
+    if (grad_fused_ok(op)) return launch_grad_fused(op, lam, u, gK, nullptr, s);
     // fields: wtl [9][Nq] = W^(ab)^T lam, gu [3][Nq] = B^(b) u
     double* base = reinterpret_cast<double*>(op.scratch);
     double* wtl = base;

@@ -39,7 +39,8 @@ def K_at(wl, Fq: torch.Tensor):
 
 def build(wl, prec_mask: int = WQ_F64, fd_prec_mask: int = WQ_F64, device="cuda", rule: str = "wq") -> DeviceProblem:
     knots = wl.knots()
-    A = wqfd.wq_setup(wl.p, knots, wl.ctrl(), WQ_K_IDENTITY, None, prec_mask, device, rule=rule)
+    A = wqfd.wq_setup(wl.p, knots, wl.ctrl(), WQ_K_IDENTITY, None, prec_mask, device, rule=rule,
+                      weights=wl.weights())
     _, Fq = wqfd.wq_quad_points(A)
     kind, K_q = K_at(wl, Fq)
     if kind != WQ_K_IDENTITY:

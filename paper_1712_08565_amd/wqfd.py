@@ -15,9 +15,9 @@ from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_FD_NOALLOC_BYTES, WQ_K_IDENTITY, 
                    check, lib)
 
 __all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
-           "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f",
+           "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f", "wq_grad_Kf",
            "wq_grad_alpha", "wq_alpha_mean", "fd_setup", "fd_apply", "fd_apply_noalloc", "fd_set_shift", "fd_factors",
-           "krylov_solve", "ir_solve", "ir_fallback_count", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
+           "krylov_solve", "ir_solve", "ir_fallback_count", "WqEval", "wq_eval_setup", "wq_eval_slab", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
            "WQ_K_SYM6", "WQError"]
 
 _DT = {WQ_F64: torch.float64, WQ_F32: torch.float32, WQ_BF16: torch.float32}
@@ -91,13 +91,75 @@ class FdPc:
             self.handle = None
 
 
+class WqEval:
+    """Gauss-point evaluator of discrete solutions (wq_eval_setup); owns its workspace tensor."""
+
+    def __init__(self, handle, ws, p, ng, device):
+        self.handle, self.ws, self.p, self.ng, self.device = handle, ws, p, ng, device
+        self._destroy = lib().wq_eval_destroy
+        ne = (C.c_int32 * 3)()
+        nq = (C.c_int32 * 3)()
+        check(lib().wq_eval_dims(handle, ne, nq), "wq_eval_dims")
+        self.ne, self.nq = tuple(ne), tuple(nq)
+        self.N = int(np.prod([e + p - 2 for e in self.ne]))   # interior B-splines (simple interior knots)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            self._destroy(h)
+            self.handle = None
+
+
+def wq_eval_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, ng: int,
+                  weights: Optional[np.ndarray] = None, device="cuda", stream=None) -> WqEval:
+    """Evaluator at ng Gauss points per element and direction on the map (ctrl, weights) of wq_setup."""
+    ks, nk, kp = _knots(knots)
+    ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
+    m = [len(k) - p - 1 for k in ks]
+    if p >= 1 and min(m) > 0 and ctrl.size != 3 * m[0] * m[1] * m[2]:
+        raise ValueError(f"ctrl: need {m[2]} x {m[1]} x {m[0]} control points of 3 coordinates, got {ctrl.size} values")
+    wp = C.c_void_p(0)
+    if weights is not None:
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        if weights.size != m[0] * m[1] * m[2]:
+            raise ValueError(f"weights: need {m[2]} x {m[1]} x {m[0]} values, got {weights.size}")
+        wp = C.c_void_p(weights.ctypes.data)
+    L = lib()
+    need = C.c_size_t(0)
+    h = C.c_void_p(0)
+    check(L.wq_eval_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), wp, ng, None, 0, C.byref(need), _stream(stream),
+                          C.byref(h)), "wq_eval_setup(size)")
+    ws = torch.empty(need.value, dtype=torch.uint8, device=device)
+    check(L.wq_eval_setup(p, nk, kp, C.c_void_p(ctrl.ctypes.data), wp, ng, _p(ws), need.value, None,
+                          _stream(stream), C.byref(h)), "wq_eval_setup")
+    return WqEval(h, ws, p, ng, device)
+
+
+def wq_eval_slab(E: WqEval, u: torch.Tensor, e3_begin: int, e3_end: int, out=None, stream=None):
+    """(X [3, n], wdet [n], uh [n], grad [3, n]) at the Gauss points of elements [e3_begin, e3_end) along z."""
+    n = E.nq[0] * E.nq[1] * (e3_end - e3_begin) * E.ng
+    if out is None:
+        out = tuple(torch.empty(k * n, dtype=torch.float64, device=E.device) for k in (3, 1, 1, 3))
+    X, wdet, uh, grad = out
+    for t, k, name in ((X, 3, "X"), (wdet, 1, "wdet"), (uh, 1, "uh"), (grad, 3, "grad")):
+        _need(t, torch.float64, k * n, name)
+    _need(u, torch.float64, E.N, "u")
+    if not (0 <= e3_begin <= e3_end <= E.ne[2]):
+        raise ValueError(f"element range [{e3_begin}, {e3_end}) outside [0, {E.ne[2]}]")
+    check(lib().wq_eval_slab(E.handle, _p(u), e3_begin, e3_end, _p(X), _p(wdet), _p(uh), _p(grad),
+                             _stream(stream)), "wq_eval_slab")
+    return X.view(3, n), wdet, uh, grad.view(3, n)
+
+
 def wq_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, k_kind: int = WQ_K_IDENTITY,
              K_q: Optional[torch.Tensor] = None, prec_mask: int = WQ_F64, device="cuda", stream=None,
-             rule: str = "wq") -> WqOp:
-    """rule "wq": weighted quadrature (wq_setup); "gauss": p + 1 Gauss points per element (wq_setup_gauss).
+             rule: str = "wq", weights: Optional[np.ndarray] = None) -> WqOp:
+    """rule "wq": weighted quadrature (wq_setup, or wq_setup_nurbs with control weights); "gauss": p + 1 Gauss
+    points per element (wq_setup_gauss).
 
-    ctrl holds the control points [m3][m2][m1][3] (m_l = len(knots[l]) - p - 1); a conductivity K_q is
-    installed with wq_set_coef once the operator exists, so that its size is checked against N_q."""
+    ctrl holds the control points [m3][m2][m1][3] (m_l = len(knots[l]) - p - 1), weights (optional) the
+    positive control weights [m3][m2][m1] of a rational map; a conductivity K_q is installed with wq_set_coef
+    once the operator exists, so that its size is checked against N_q."""
     ks, nk, kp = _knots(knots)
     ctrl = np.ascontiguousarray(ctrl, dtype=np.float64)
     m = [len(k) - p - 1 for k in ks]
@@ -107,10 +169,22 @@ def wq_setup(p: int, knots: Sequence[np.ndarray], ctrl: np.ndarray, k_kind: int 
         raise ValueError(f"unknown k_kind {k_kind}")
     if k_kind != WQ_K_IDENTITY and K_q is None:
         raise ValueError("K_q is required for this k_kind")
+    L = lib()
+    if weights is not None:
+        if rule != "wq":
+            raise ValueError("control weights are supported with rule 'wq'")
+        weights = np.ascontiguousarray(weights, dtype=np.float64)
+        if p >= 1 and min(m) > 0 and weights.size != m[0] * m[1] * m[2]:
+            raise ValueError(f"weights: need {m[2]} x {m[1]} x {m[0]} values, got {weights.size}")
+        wp = C.c_void_p(weights.ctypes.data)
+        name = "wq_setup_nurbs"
+
+        def fn(p_, nk_, kp_, c_, *rest):
+            return L.wq_setup_nurbs(p_, nk_, kp_, c_, wp, *rest)
+    else:
+        fn, name = {"wq": (L.wq_setup, "wq_setup"), "gauss": (L.wq_setup_gauss, "wq_setup_gauss")}[rule]
     need = C.c_size_t(0)
     h = C.c_void_p(0)
-    L = lib()
-    fn, name = {"wq": (L.wq_setup, "wq_setup"), "gauss": (L.wq_setup_gauss, "wq_setup_gauss")}[rule]
     check(fn(p, nk, kp, C.c_void_p(ctrl.ctypes.data), WQ_K_IDENTITY, C.c_void_p(0), prec_mask, None, 0,
              C.byref(need), _stream(stream), C.byref(h)), name + "(size)")
     ws = torch.empty(need.value, dtype=torch.uint8, device=device)
@@ -228,6 +302,20 @@ def wq_grad_f(op: WqOp, lam: torch.Tensor, gf: Optional[torch.Tensor] = None, st
     _need(gf, torch.float64, op.Nq, "gf")
     check(lib().wq_grad_f(op.handle, _p(lam), _p(gf), _stream(stream)), "wq_grad_f")
     return gf
+
+
+def wq_grad_Kf(op: WqOp, lam: torch.Tensor, u: torch.Tensor, gK: Optional[torch.Tensor] = None,
+               gf: Optional[torch.Tensor] = None, stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(dJ/dK, dJ/df) in one pass (wq_grad_Kf)."""
+    _need(lam, torch.float64, op.N, "lam")
+    _need(u, torch.float64, op.N, "u")
+    planes = {WQ_K_IDENTITY: 6, WQ_K_SCALAR: 1, WQ_K_SYM6: 6}[op.k_kind]
+    gK = torch.empty(planes * op.Nq, dtype=torch.float64, device=op.device) if gK is None else gK
+    gf = torch.empty(op.Nq, dtype=torch.float64, device=op.device) if gf is None else gf
+    _need(gK, torch.float64, planes * op.Nq, "gK")
+    _need(gf, torch.float64, op.Nq, "gf")
+    check(lib().wq_grad_Kf(op.handle, _p(lam), _p(u), _p(gK), _p(gf), _stream(stream)), "wq_grad_Kf")
+    return gK, gf
 
 
 def wq_grad_alpha(op: WqOp, lam: torch.Tensor, u: torch.Tensor, g: Optional[torch.Tensor] = None,

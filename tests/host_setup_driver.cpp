@@ -1,5 +1,5 @@
 // Drives the library's host set-up (spline spaces for both quadrature rules,
-// geometry at the quadrature points, 1D generalized eigenproblems) over
+// geometry at the quadrature points (polynomial and rational maps), 1D generalized eigenproblems) over
 // p = 2..10 on uniform and non-uniform knots.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_sanitizers.py; prints "ok".
 #include <cmath>
@@ -50,13 +50,24 @@ int main() {
                             }
                     const size_t Nq = (size_t)sp[0].nq * sp[1].nq * sp[2].nq;
                     std::vector<double> detJ(Nq), Jinv(9 * Nq), F(3 * Nq);
-                    if (wqfd::geometry_at_quad(sp, ctrl.data(), detJ.data(), Jinv.data(), F.data(), err, 2)) {
+                    if (wqfd::geometry_at_quad(sp, ctrl.data(), nullptr, detJ.data(), Jinv.data(), F.data(), err, 2)) {
                         std::printf("geometry p=%d: %s\n", p, err.c_str());
                         return 1;
                     }
                     for (double d : detJ)
                         if (std::fabs(d - 1.0) > 1e-10) {
                             std::printf("identity map with det J = %g at p=%d\n", d, p);
+                            return 1;
+                        }
+                    // the same net as a rational map with constant weights is the same map
+                    std::vector<double> w((size_t)m * m * m, 2.5);
+                    if (wqfd::geometry_at_quad(sp, ctrl.data(), w.data(), detJ.data(), Jinv.data(), F.data(), err, 2)) {
+                        std::printf("rational geometry p=%d: %s\n", p, err.c_str());
+                        return 1;
+                    }
+                    for (double d : detJ)
+                        if (std::fabs(d - 1.0) > 1e-10) {
+                            std::printf("rational identity map with det J = %g at p=%d\n", d, p);
                             return 1;
                         }
                     std::vector<double> lam, U;

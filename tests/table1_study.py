@@ -1,21 +1,21 @@
-"""Partial reproduction of the k-refinement study (Table 1 of the paper): the
-Dirichlet problem on the thick quarter ring with the oscillating manufactured
-solution of eq. (exact-solution), K = I, alpha = 0, solved by the library on the
-GPU (FP64 BiCGStab + FD to relative residual 1e-12, i.e. the Galerkin solution),
-and its relative H1 error integrated by the oracle (p + 3 Gauss points per
-element in physical coordinates).  Prints one row per (h, p) beside the paper's
-value.  Test infrastructure (not collected by pytest):
+"""Reproduction of the k-refinement study (Table 1 of the paper, tab:k_refinement,
+Section 4): the Dirichlet problem on the thick quarter ring with the oscillating
+manufactured solution of eq. (exact-solution), K = I, alpha = 0, solved by the
+library on the GPU (FD-preconditioned BiCGStab), and the relative H1-seminorm
+error of the solution.  Test infrastructure (not collected by pytest):
 
-    python tests/table1_study.py --cases 16:2,16:3,32:2,32:3          # GPU solves + errors
-    python tests/table1_study.py --cases 16:2 --solutions DIR         # errors of saved solutions only
+    python tests/table1_study.py --cases 16:2,32:3,256:7 --eta 0.1
 
---geometry ring_interp (default) interpolates the ring map at the Greville
-abscissae (order p + 1 in h); --geometry ring places the control points at the
-images of the Greville abscissae (order 2), which limits the error from p = 6 at
-32^3 elements.  The paper uses an exact NURBS ring.
---eta 0.1 also solves with the paper's error-matched stopping rule
-(eq. stopping_criterion: relative residual <= eta times the Galerkin solution's
-relative H1 error) and reports that solution's error and iteration count.
+Per case: the Galerkin solution (relative residual 1e-14), its relative H1
+error, and with --eta the solution stopped by the paper's error-matched rule
+(eq. stopping_criterion: |r|/|b| <= eta times the Galerkin solution's relative
+H1 error), its error and iterations.  The error integral uses p + 3 Gauss points
+per element and the exact gradient; --errors gpu (default) evaluates the
+solution with the library's Gauss-point evaluator (wq_eval_slab) in z-slabs and
+sums with torch, --errors oracle uses the oracle's integrator (CPU, coarse
+levels only).  --geometry ring_nurbs (default) is the exact ring as a rational
+map (the paper computes on NURBS); ring_interp interpolates the ring map by a
+polynomial spline of order p + 1.
 """
 import argparse
 import os
@@ -28,7 +28,6 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 import synth  # noqa: E402
-from oracle.errors import errors  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 
@@ -39,45 +38,95 @@ def paper_table():
     return {int(r[0]): list(r[1:]) for r in rows}
 
 
-def solve_on_gpu(ne, p, geometry, rtol=1e-12, dp=None):
+def paper_value(ne, p):
+    col = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}.get(ne)
+    t = paper_table()
+    return t[p][col] if (p in t and col is not None) else float("nan")
+
+
+def workload(ne, p, geometry="ring_nurbs"):
+    return synth.Workload(f"table1_{geometry}_{ne}_p{p}", ne, p, geometry, 0.0, "identity", "paper")
+
+
+def gpu_errors(wl, x, max_points=1 << 25):
+    """(relative L2, relative H1-seminorm) error of the coefficients x (device)
+    from the library's Gauss-point evaluator, p + 3 points per element, summed
+    over z-slabs in FP64 with torch."""
+    import torch
+    from paper_1712_08565_amd import wqfd
+    ng = wl.p + 3
+    E = wqfd.wq_eval_setup(wl.p, wl.knots(), wl.ctrl(), ng, weights=wl.weights())
+    per_el = E.nq[0] * E.nq[1] * ng
+    step = max(1, max_points // per_el)
+    s = torch.zeros(4, dtype=torch.float64, device=x.device)
+    for e0 in range(0, E.ne[2], step):
+        X, wdet, uh, grad = wqfd.wq_eval_slab(E, x, e0, min(E.ne[2], e0 + step))
+        P = X.t()
+        ue, ge = synth.u_paper(P), synth.grad_u_paper(P)
+        s += torch.stack([torch.sum(wdet * (uh - ue) ** 2), torch.sum(wdet * ue ** 2),
+                          torch.sum(wdet * torch.sum((grad.t() - ge) ** 2, 1)),
+                          torch.sum(wdet * torch.sum(ge ** 2, 1))])
+        del X, wdet, uh, grad, P, ue, ge
+    s = s.cpu().numpy()
+    return float(np.sqrt(s[0] / s[1])), float(np.sqrt(s[2] / s[3]))
+
+
+def oracle_errors(wl, x):
+    from oracle.errors import errors
+    return errors(wl.knots(), wl.p, wl.ctrl(), x.cpu().numpy(), synth.u_paper, synth.grad_u_paper,
+                  weights=wl.weights())
+
+
+def run_case(ne, p, geometry="ring_nurbs", eta=0.0, err_kind="gpu"):
     import torch
     from paper_1712_08565_amd import problem, wqfd
-    if dp is None:
-        wl = synth.Workload(f"ring{ne}_p{p}", ne, p, geometry, 0.0, "identity", "paper")
-        dp = problem.build(wl, wqfd.WQ_F64, wqfd.WQ_F64)
-    torch.cuda.synchronize()
+    wl = workload(ne, p, geometry)
     t0 = time.perf_counter()
-    x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=rtol, maxit=3000, raise_on_noconv=False)
+    dp = problem.build(wl, wqfd.WQ_F64, wqfd.WQ_F64)
     torch.cuda.synchronize()
-    return x.cpu().numpy(), it, res, time.perf_counter() - t0, dp
+    t_setup = time.perf_counter() - t0
+    err = gpu_errors if err_kind == "gpu" else oracle_errors
+
+    def solve(rtol):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=rtol, maxit=3000, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        return x, it, res, time.perf_counter() - t
+
+    xg, it_g, res_g, t_g = solve(1e-14)
+    t0 = time.perf_counter()
+    h1_g = err(wl, xg)[1]
+    t_err = time.perf_counter() - t0
+    out = dict(ne=ne, p=p, N=dp.A.N, h1=h1_g, it=it_g, res=res_g, solve_s=t_g, setup_s=t_setup, err_s=t_err,
+               paper=paper_value(ne, p))
+    if eta > 0:
+        xe, it_e, res_e, t_e = solve(eta * h1_g)
+        out.update(eta=eta, h1_eta=err(wl, xe)[1], it_eta=it_e, res_eta=res_e, solve_eta_s=t_e)
+    del dp
+    torch.cuda.empty_cache()
+    return out
+
+
+def fmt(r):
+    s = (f"2^-{int(np.log2(r['ne']))} {r['p']:2d} {r['N']:>10d} {r['h1']:10.3e} {r['paper']:8.1e} "
+         f"{r['h1'] / r['paper']:6.3f}  Galerkin: {r['it']:3d} it {1e3 * r['solve_s']:8.1f} ms")
+    if "eta" in r:
+        s += (f"  stopping rule: {r['it_eta']:3d} it {1e3 * r['solve_eta_s']:8.1f} ms error {r['h1_eta']:10.3e} "
+              f"({r['h1_eta'] / r['paper']:5.3f} of paper)")
+    return s + f"  [setup {r['setup_s']:.1f} s, error integral {r['err_s']:.1f} s]"
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--cases", default="16:2,16:3,16:4,32:2,32:3,32:4", help="n_el:p pairs")
-    ap.add_argument("--solutions", default="", help="directory of saved x_ne{n_el}_p{p}.npy (skip the GPU)")
-    ap.add_argument("--geometry", default="ring_interp", choices=("ring_interp", "ring"))
+    ap.add_argument("--cases", default="16:2,16:3,32:2,32:3", help="n_el:p pairs")
+    ap.add_argument("--geometry", default="ring_nurbs", choices=("ring_nurbs", "ring_interp", "ring"))
     ap.add_argument("--eta", type=float, default=0.0, help="also solve with the error-matched stopping rule")
+    ap.add_argument("--errors", default="gpu", choices=("gpu", "oracle"))
     args = ap.parse_args()
-    paper = paper_table()
-    print(f"{'h':>6} {'p':>2} {'rel H1 error':>12} {'paper':>8}  solve")
+    print(f"{'h':>5} {'p':>2} {'N':>10} {'H1 error':>10} {'paper':>8} {'ratio':>6}", flush=True)
     for ne, p in ((int(a), int(b)) for a, b in (c.split(":") for c in args.cases.split(","))):
-        if args.solutions:
-            x, info = np.load(os.path.join(args.solutions, f"x_ne{ne}_p{p}.npy")), "saved"
-        else:
-            x, it, res, t, dp = solve_on_gpu(ne, p, args.geometry)
-            info = f"{it} it, relres {res:.1e}, {1e3 * t:.1f} ms"
-        k = synth.uniform_knots(ne, p)
-        kn = (k, k, k)
-        ctrl = synth.control_net(args.geometry, kn, p, 0.0, 0)
-        h1 = errors(kn, p, ctrl, x, synth.u_paper, synth.grad_u_paper)[1]
-        if args.eta > 0 and not args.solutions:
-            xe, ite, rese, te, _ = solve_on_gpu(ne, p, args.geometry, rtol=args.eta * h1, dp=dp)
-            he = errors(kn, p, ctrl, xe, synth.u_paper, synth.grad_u_paper)[1]
-            info += f"; stopping rule (eta {args.eta}): {ite} it, {1e3 * te:.1f} ms, error {he:.2e}"
-        col = {16: 0, 32: 1, 64: 2, 128: 3, 256: 4}.get(ne)
-        ref = paper[p][col] if (p in paper and col is not None) else float("nan")
-        print(f"2^-{int(np.log2(ne)):d} {p:2d} {h1:12.2e} {ref:8.1e}  {info}", flush=True)
+        print(fmt(run_case(ne, p, args.geometry, args.eta, args.errors)), flush=True)
 
 
 if __name__ == "__main__":

@@ -32,7 +32,7 @@ def setup(name):
     wl = synth.workload(name)
     print(f"[adjoint] setup {name} (p={wl.p}, n_el={wl.n_el}, K {wl.k_kind})", flush=True)
     dp = problem.build(wl, WQ_F64, WQ_F64)
-    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field(), weights=wl.weights())
     torch.cuda.synchronize()
     _cache[name] = (wl, dp, pr)
     return _cache[name]
@@ -60,7 +60,8 @@ def oracle_grad_K(wl, pr, lam, u):
     return np.stack([g[0, 0], g[1, 1], g[2, 2], g[0, 1] + g[1, 0], g[0, 2] + g[2, 0], g[1, 2] + g[2, 1]]).ravel()
 
 
-@pytest.mark.parametrize("name", CASES + ["ring20_p6", "twist6_p6", "ring8nu_p5", "ring6_p8"])
+@pytest.mark.parametrize("name", CASES + ["ring20_p6", "twist6_p6", "ring8nu_p5", "ring6_p8", "nurbs6nu_p4",
+                                          "ring18_p7"])
 def test_gradient_kernels_parity(name):
     from paper_1712_08565_amd import wqfd
     wl, dp, pr = setup(name)
@@ -70,6 +71,19 @@ def test_gradient_kernels_parity(name):
     ef = max_rel(host(wqfd.wq_grad_f(dp.A, dev(lam))), adjoint.grad_f(pr, lam))
     print(f"[grad kernels] {name}: dJ/dK {eK:.2e}, dJ/df {ef:.2e}")
     assert eK <= 1e-12 and ef <= 1e-12, (f"{eK:.3e}", f"{ef:.3e}")
+
+
+@pytest.mark.parametrize("name", ["ring7_p4_kappa", "twist5_p4", "cube5_p2", "ring6_p8"])
+def test_grad_Kf_equals_the_two_calls(name):
+    """wq_grad_Kf (one pass on the fused kernels, the two calls on the staged
+    ones) gives bit for bit what wq_grad_K and wq_grad_f give."""
+    import torch
+    from paper_1712_08565_amd import wqfd
+    wl, dp, pr = setup(name)
+    lam = dev(synth.random_vector(pr.N, 45))
+    u = dev(synth.random_vector(pr.N, 46))
+    gK, gf = wqfd.wq_grad_Kf(dp.A, lam, u)
+    assert torch.equal(gK, wqfd.wq_grad_K(dp.A, lam, u)) and torch.equal(gf, wqfd.wq_grad_f(dp.A, lam))
 
 
 @pytest.mark.parametrize("name", CASES)

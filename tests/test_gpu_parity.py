@@ -10,8 +10,8 @@ the same seeded inputs.  Gates (element by element, see parity_gates.py):
      cond(K~) ~ 1e7 (twist6_p6) and FP64 residuals alone are not.
   FP32 / BF16 results: error stated (bounds are about ten times the observed error).
 Non-uniform knots (element lengths within a factor 4, different per direction)
-run through the same cases: the fused kernels (p <= 7, one and several tiles)
-and the staged ones (p = 8).
+and the exact ring as a rational (NURBS) map run through the same cases: the
+fused kernels (p <= 7, one and several tiles) and the staged ones (p = 8).
 """
 import numpy as np
 import pytest
@@ -27,7 +27,7 @@ pytestmark = pytest.mark.gpu
 APPLY_CASES = ["cube12_p3", "ring8_p2", "ring8_p3", "ring8_p4", "ring8_p5", "ring8_p6", "ring7_p4_kappa",
                "twist6_p6", "shear6_p3", "ring6_p8", "ring20_p6", "ring6_p7", "ring18_p7", "ring5_p10",
                "ring8nu_p2", "ring8nu_p3", "ring8nu_p4", "ring8nu_p5", "ring8nu_p6", "ring20nu_p6", "ring6nu_p8",
-               "twist6nu_p5"]
+               "twist6nu_p5", "nurbs8_p2", "nurbs8_p3", "nurbs8_p6", "nurbs20_p5", "nurbs6nu_p4", "nurbs6_p8"]
 
 _cache = {}
 
@@ -41,7 +41,7 @@ def setup(name):
     wl = synth.workload(name)
     print(f"[parity] setup {name} (p={wl.p}, n_el={wl.n_el})", flush=True)
     dp = problem.build(wl, WQ_F64 | WQ_F32, WQ_F64 | WQ_F32 | WQ_BF16)
-    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field())
+    pr = Problem(wl.knots(), wl.p, wl.ctrl(), wl.K_field(), weights=wl.weights())
     torch.cuda.synchronize()
     _cache[name] = (wl, dp, pr)
     return _cache[name]
@@ -229,7 +229,8 @@ def _solve_check(pr, A, b, x, xref, res, label, transpose=False):
 
 
 @pytest.mark.parametrize("name", ["ring8_p2", "ring8_p4", "ring8_p6", "ring7_p4_kappa", "twist5_p4", "twist6_p6",
-                                  "ring8nu_p3", "ring8nu_p6", "twist6nu_p5", "ring6nu_p8"])
+                                  "ring8nu_p3", "ring8nu_p6", "twist6nu_p5", "ring6nu_p8", "nurbs8_p3",
+                                  "nurbs6nu_p4"])
 def test_solve_parity(name):
     from paper_1712_08565_amd import wqfd
     wl, dp, pr = setup(name)

@@ -122,7 +122,7 @@ def test_geometry_matches_oracle(name):
     nk = (C.c_int32 * 3)(*[len(k) for k in ks])
     kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
     det, Ji, F = np.empty(Nq), np.empty((9, Nq)), np.empty((3, Nq))
-    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(det.ctypes.data),
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), None, C.c_void_p(det.ctypes.data),
                               C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
     assert rc == 0
     assert np.abs(F - F_ref.reshape(Nq, 3).T).max() < 1e-13
@@ -141,6 +141,33 @@ def test_inverted_geometry_is_reported():
     Nq = 15 ** 3
     det, Ji, F = np.empty(Nq), np.empty((9, Nq)), np.empty((3, Nq))
     from paper_1712_08565_amd import _lib
-    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(det.ctypes.data),
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), None, C.c_void_p(det.ctypes.data),
                               C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
     assert rc == _lib.WQ_EGEOM
+
+
+@pytest.mark.parametrize("name", ["nurbs8_p3", "nurbs6nu_p4"])
+def test_rational_geometry_matches_oracle(name):
+    """wq_geometry_host with control weights (the NURBS ring) against the oracle's
+    rational map; a non-positive weight is rejected."""
+    wl = synth.workload(name)
+    kn, ctrl, w = wl.knots(), wl.ctrl(), wl.weights()
+    F_ref, J_ref = map_and_jacobian([owq.Space1D(k, wl.p) for k in kn], ctrl, w)
+    Nq = F_ref[..., 0].size
+    ks = [np.ascontiguousarray(k) for k in kn]
+    nk = (C.c_int32 * 3)(*[len(k) for k in ks])
+    kp = (C.c_void_p * 3)(*[k.ctypes.data for k in ks])
+    det, Ji, F = np.empty(Nq), np.empty((9, Nq)), np.empty((3, Nq))
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(w.ctypes.data),
+                              C.c_void_p(det.ctypes.data), C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
+    assert rc == 0
+    assert np.abs(F - F_ref.reshape(Nq, 3).T).max() < 1e-13
+    assert np.abs(det - np.linalg.det(J_ref).ravel()).max() < 1e-12 * np.abs(det).max()
+    Ji_ref = np.linalg.inv(J_ref).reshape(Nq, 9).T
+    assert np.abs(Ji - Ji_ref).max() < 1e-12 * np.abs(Ji_ref).max()
+    bad = w.copy()
+    bad.flat[17] = 0.0
+    from paper_1712_08565_amd import _lib
+    rc = L().wq_geometry_host(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(bad.ctypes.data),
+                              C.c_void_p(det.ctypes.data), C.c_void_p(Ji.ctypes.data), C.c_void_p(F.ctypes.data))
+    assert rc == _lib.WQ_EINVAL
