@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwqfd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["host_setup.cpp", "wq_kernels.hip", "wq_fused.hip", "fd_kernels.hip", "fd_gemm.hip", "krylov.hip", "eval.hip", "capi.hip"]
+SOURCES = ["host_setup.cpp", "wq_kernels.hip", "wq_fused.hip", "fd_kernels.hip", "fd_gemm.hip", "krylov.hip", "eval.hip", "geom.hip", "capi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -567,6 +567,19 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
         f_schedT = pk.add(fh.schedT.data(), fh.schedT.size() * sizeof(int));
         f_soffT = pk.add(fh.schedT_off.data(), fh.schedT_off.size() * sizeof(int));
     }
+    // per-direction non-zero B-splines at the quadrature points (device geometry)
+    size_t g_first[3], g_B[3], g_D[3];
+    for (int l = 0; l < 3; ++l) {
+        const wqfd::Space1D& S = sp[l];
+        std::vector<int> first(S.nq);
+        std::vector<double> gb((size_t)S.nq * (p + 1)), gd((size_t)S.nq * (p + 1));
+        for (int q = 0; q < S.nq; ++q)
+            first[q] = wqfd::eval_nonzero(S.knots, p, S.m, S.xq[q], &gb[(size_t)q * (p + 1)],
+                                          &gd[(size_t)q * (p + 1)]) - p;
+        g_first[l] = pk.add(first.data(), first.size() * sizeof(int));
+        g_B[l] = pk.add(gb.data(), gb.size() * 8);
+        g_D[l] = pk.add(gd.data(), gd.size() * 8);
+    }
     // workspace layout
     size_t off = 0;
     const size_t o_tab = off;
@@ -603,10 +616,30 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
     if (ws_bytes < off) return fail(WQ_ENOMEM, "workspace too small for wq_setup");
     if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(WQ_EINVAL, "workspace must be 256-byte aligned");
 
-    // geometry on the host
-    std::vector<double> hdet(o.Nq), hjinv(9 * o.Nq), hF(3 * o.Nq);
-    rc = wqfd::geometry_at_quad(sp, ctrl, weights, hdet.data(), hjinv.data(), hF.data(), err, nthreads());
-    if (rc) return fail(rc, err);
+    // geometry: on the device when its intermediates fit the operator's own memory
+    // (Z and the control net in the scratch region, Y in the FP64 coefficient
+    // planes, which set_coef fills afterwards), else on the host
+    const int mm[3] = {sp[0].m, sp[1].m, sp[2].m};
+    const size_t M = (size_t)mm[0] * mm[1] * mm[2];
+    const size_t zb = (size_t)o.nq[2] * mm[1] * mm[0] * 8 * 8, yb = (size_t)o.nq[2] * o.nq[1] * mm[0] * 12 * 8;
+    const bool dev_geom = !std::getenv("WQFD_HOST_GEOMETRY") && al256(zb) + al256(M * 32) + 256 <= o.scratch_bytes &&
+                          yb <= 6 * o.Nq * 8;
+    std::vector<double> hdet, hjinv, hF, hom;
+    if (dev_geom) {
+        hom.resize(M * 4);
+        for (size_t k = 0; k < M; ++k) {
+            const double w = weights ? weights[k] : 1.0;
+            if (!(w > 0.0)) return fail(WQ_EINVAL, "rational map: every control weight must be positive");
+            for (int a = 0; a < 3; ++a) hom[4 * k + a] = w * ctrl[3 * k + a];
+            hom[4 * k + 3] = w;
+        }
+    } else {
+        hdet.resize(o.Nq);
+        hjinv.resize(9 * o.Nq);
+        hF.resize(3 * o.Nq);
+        rc = wqfd::geometry_at_quad(sp, ctrl, weights, hdet.data(), hjinv.data(), hF.data(), err, nthreads());
+        if (rc) return fail(rc, err);
+    }
 
     char* base = static_cast<char*>(ws);
     HIP_TRY(hipMemcpyAsync(base + o_tab, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice, s), "upload tables");
@@ -619,9 +652,38 @@ static int setup_impl(int rule, int p, const int32_t nknots[3], const double* co
     o.Cm32 = (prec_mask & WQ_F32) ? reinterpret_cast<float*>(base + o_cm32) : nullptr;
     o.scratch = base + o_scr;
     o.red = base + o_red;
-    HIP_TRY(hipMemcpyAsync(o.detJ, hdet.data(), o.Nq * 8, hipMemcpyHostToDevice, s), "upload detJ");
-    HIP_TRY(hipMemcpyAsync(o.Jinv, hjinv.data(), 9 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload Jinv");
-    HIP_TRY(hipMemcpyAsync(o.F, hF.data(), 3 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload F");
+    if (dev_geom) {
+        wqfd::GeomArgs g;
+        g.p = p;
+        for (int l = 0; l < 3; ++l) {
+            g.m[l] = mm[l];
+            g.nq[l] = o.nq[l];
+            g.first[l] = reinterpret_cast<const int*>(base + o_tab + g_first[l]);
+            g.B[l] = reinterpret_cast<const double*>(base + o_tab + g_B[l]);
+            g.D[l] = reinterpret_cast<const double*>(base + o_tab + g_D[l]);
+        }
+        g.Nq = o.Nq;
+        char* scr = static_cast<char*>(o.scratch);
+        g.Z = reinterpret_cast<double*>(scr);
+        double* dctrl = reinterpret_cast<double*>(scr + al256(zb));
+        g.ctrl = dctrl;
+        g.bad = reinterpret_cast<int*>(scr + al256(zb) + al256(M * 32));
+        g.Y = o.C64;
+        g.detJ = o.detJ;
+        g.Jinv = o.Jinv;
+        g.F = o.F;
+        int zero = 0, bad = 0;
+        HIP_TRY(hipMemcpyAsync(dctrl, hom.data(), M * 32, hipMemcpyHostToDevice, s), "upload control net");
+        HIP_TRY(hipMemcpyAsync(g.bad, &zero, sizeof(int), hipMemcpyHostToDevice, s), "clear flag");
+        HIP_TRY(wqfd::launch_geometry(g, s), "geometry");
+        HIP_TRY(hipMemcpyAsync(&bad, g.bad, sizeof(int), hipMemcpyDeviceToHost, s), "read flag");
+        HIP_TRY(hipStreamSynchronize(s), "geometry sync");
+        if (bad) return fail(WQ_EGEOM, "geometry map is not orientation preserving: det J <= 0 at a quadrature point");
+    } else {
+        HIP_TRY(hipMemcpyAsync(o.detJ, hdet.data(), o.Nq * 8, hipMemcpyHostToDevice, s), "upload detJ");
+        HIP_TRY(hipMemcpyAsync(o.Jinv, hjinv.data(), 9 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload Jinv");
+        HIP_TRY(hipMemcpyAsync(o.F, hF.data(), 3 * o.Nq * 8, hipMemcpyHostToDevice, s), "upload F");
+    }
     const char* tb = base + o_tab;
     for (int l = 0; l < 3; ++l) {
         auto& d64 = o.t64.dir[l];

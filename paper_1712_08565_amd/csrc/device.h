@@ -101,6 +101,27 @@ struct EvalOp {
     const double* ctrl = nullptr;
 };
 
+// Geometry at the quadrature points on the device (geom.hip): per direction the
+// first non-zero B-spline and the p + 1 values and derivatives at each of the
+// nq points, the homogeneous control net [m3][m2][m1][4], intermediates Z
+// ([nq3][m2][m1][8]) and Y ([nq3][nq2][m1][12]) in caller memory, outputs det J
+// [Nq], J^{-1} [9][Nq], F [3][Nq]; *bad is or-ed with 1 where det J <= 0.
+struct GeomArgs {
+    int p = 0;
+    int m[3] = {0, 0, 0}, nq[3] = {0, 0, 0};
+    size_t Nq = 0;
+    const int* first[3] = {nullptr, nullptr, nullptr};
+    const double* B[3] = {nullptr, nullptr, nullptr};
+    const double* D[3] = {nullptr, nullptr, nullptr};
+    const double* ctrl = nullptr;
+    double* Z = nullptr;
+    double* Y = nullptr;
+    double* detJ = nullptr;
+    double* Jinv = nullptr;
+    double* F = nullptr;
+    int* bad = nullptr;
+};
+
 // ---------------------------------------------------------------- launchers
 // MF-WQ operator (wq_kernels.hip)
 size_t wq_scratch_bytes(const WqOp& op, int prec_mask);
@@ -118,6 +139,10 @@ hipError_t launch_grad_Kf(const WqOp& op, const double* lam, const double* u, do
 hipError_t launch_set_alpha(const WqOp& op, const double* alpha_q, hipStream_t s);
 hipError_t launch_apply_mass(const WqOp& op, int prec, const void* v, void* w, hipStream_t s);
 hipError_t launch_grad_alpha(const WqOp& op, const double* lam, const double* u, double* g, hipStream_t s);
+
+// geometry set-up (geom.hip): bytes of the Z and Y intermediates, and the three passes
+size_t geometry_scratch_bytes(const int m[3], const int nq[3]);
+hipError_t launch_geometry(const GeomArgs& a, hipStream_t s);
 
 // u_h, grad u_h, F and w |det J| at the Gauss points of elements
 // [e3_begin, e3_end) along z (all elements in x and y); outputs [3][n], [n], [n], [3][n]

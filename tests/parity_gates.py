@@ -58,11 +58,23 @@ def reference_solve(pr, b, transpose=False, shift=0.0):
 def oracle_fp64_solve_error(pr, b, xref, transpose=False, shift=0.0, tol=1e-14):
     """Relative error of the oracle's own FP64 BiCGStab (to relative residual
     ``tol``) against the refined reference: the floor FP64 arithmetic leaves on
-    this system.  A GPU solve at the same tolerance is held to 1e-10 or, where
-    that floor is higher (cond(K~) ~ 1e7 and more), to three times the floor."""
+    this system.  A GPU solve at the same tolerance is held to 1e-10, or to
+    three times this floor, or to the normwise bound kappa_2 times its own
+    oracle residual (forward_error_bound), whichever is largest."""
     from oracle.fd import FD
     from oracle.krylov import bicgstab
     fd = FD(pr.spaces, shift=shift)
     A = pr.apply_T if transpose else pr.apply
     x = bicgstab(A, b, fd.apply, tol=tol, maxit=500)[0]
     return norm_rel(x, xref)
+
+
+def forward_error_bound(pr, rel_residual, max_n=4000) -> float:
+    """kappa_2(K~) times a relative residual: the normwise bound on the relative
+    error of any solution with that residual (K~ assembled by the oracle, dense
+    condition number; 0 when N > max_n, where it is not computed).  An FP64
+    solve of a system with kappa ~ 1e7 fixes the solution only to about this
+    level, whatever its arithmetic order (reading R10)."""
+    if pr.N > max_n:
+        return 0.0
+    return float(np.linalg.cond(pr.assemble().toarray())) * rel_residual
