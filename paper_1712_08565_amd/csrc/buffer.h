@@ -1,4 +1,4 @@
-// Raw buffer loads and stores for gfx950 (internal): the base address and a per-plane
+// Raw buffer loads for gfx950 (internal): the base address and a per-plane
 // byte offset live in scalar registers, the lane's byte offset in a vector
 // register, so streaming loads need no 64-bit vector address arithmetic.
 // Offsets are unsigned 32-bit bytes and every caller keeps base + scalar offset
@@ -23,17 +23,6 @@ __device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned s
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
     else
         return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-
-template <typename T>
-__device__ inline void buf_store(T v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    if constexpr (sizeof(T) == 8) {
-        using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
-    } else {
-        using V = decltype(__builtin_amdgcn_raw_buffer_load_b32(r, 0, 0, 0));
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(V, v), r, (int)voff, (int)soff, 0);
-    }
 }
 
 }  // namespace wqfd

@@ -14,7 +14,7 @@
 // coalesced accesses along x.
 #include <hip/hip_runtime.h>
 
-#include "buffer.h"
+#include "buffer_store.h"
 #include "device.h"
 
 namespace wqfd {
@@ -447,7 +447,17 @@ __global__ __launch_bounds__(256) void grad_fused_kernel(GradFusedArgs a) {
         asm volatile("" ::: "memory");
         const double* __restrict__ c = a.cz + (size_t)k * CZ;
         const unsigned kq = (unsigned)k * pqb;
-        // trial side first: B3 u, B-dot3 u in z, then (B^(b) u) at the lane's points
+        // the test window's values of lam are loaded first, so that their latency
+        // overlaps the trial side's loads and products
+        double xl[RO][4];
+        const int wb = a.wts3[k];
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+            const unsigned so = (unsigned)min(wb + r, a.n3 - 1) * plb;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xl[r][s] = buf_load<double>(rl, offL[s], so);
+        }
+        // trial side: B3 u, B-dot3 u in z, then (B^(b) u) at the lane's points
         gd4 Bu[3];
         if (wantK) {
             double Du[2][4];
@@ -471,13 +481,11 @@ __global__ __launch_bounds__(256) void grad_fused_kernel(GradFusedArgs a) {
         double Dl[4][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) Dl[0][s] = Dl[1][s] = Dl[2][s] = Dl[3][s] = 0.0;
-        const int wb = a.wts3[k];
 #pragma unroll
         for (int r = 0; r < RO; ++r) {
-            const unsigned so = (unsigned)min(wb + r, a.n3 - 1) * plb;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
-                const double x = buf_load<double>(rl, offL[s], so);
+                const double x = xl[r][s];
                 if (wantK) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) Dl[v][s] += c[2 * RT + v * RO + r] * x;
