@@ -59,7 +59,11 @@ def gpu_errors(wl, x, max_points=1 << 25):
     per_el = E.nq[0] * E.nq[1] * ng
     step = max(1, max_points // per_el)
     s = torch.zeros(4, dtype=torch.float64, device=x.device)
+    t_last = time.perf_counter()
     for e0 in range(0, E.ne[2], step):
+        if time.perf_counter() - t_last > 20.0:           # progress on long integrals
+            print(f"  error integral: element layer {e0} of {E.ne[2]}", file=sys.stderr, flush=True)
+            t_last = time.perf_counter()
         X, wdet, uh, grad = wqfd.wq_eval_slab(E, x, e0, min(E.ne[2], e0 + step))
         P = X.t()
         ue, ge = synth.u_paper(P), synth.grad_u_paper(P)
