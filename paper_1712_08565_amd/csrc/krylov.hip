@@ -10,6 +10,7 @@
 // accumulated in FP64.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -224,13 +225,21 @@ __global__ __launch_bounds__(kT) void axpy_kernel(const D* __restrict__ d, doubl
         x[i] += scale * (double)d[i];
 }
 
-// thread-local pinned host block for the per-iteration scalar read-back
+// thread-local pinned host block for the scalar read-back: slots 0-15 and
+// 16-31 alternate between iterations, 32-47 the confirmation, 48 the restart value
 double* host_scalars() {
     static thread_local double* h = nullptr;
     if (!h) {
         if (hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) h = nullptr;
     }
     return h;
+}
+
+// thread-local event marking the end of an iteration's scalar read-back
+hipEvent_t iteration_event() {
+    static thread_local hipEvent_t ev = nullptr;
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
+    return ev;
 }
 
 #define KR_TRY(x)                                   \
@@ -350,53 +359,93 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
         *relres = std::sqrt(rr0) / nbn;
         return 0;
     }
-    for (int it = 1; it <= maxit; ++it) {
-        hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, it == 1 ? 1 : 0, clear);
-        KR_TRY(M(V.p, V.ph, s));
-        KR_TRY(Aa(V.ph, V.v, s));
+    // Each iteration is enqueued in two halves.  The first (p, p^ = M p, v = A p^,
+    // alpha, s, s^ = M s, t = A s^, the partials of omega) touches neither x nor r;
+    // the second (omega, x and r, rho) ends with the scalars' copy to the host.
+    // The next iteration's first half is enqueued before the host waits for the
+    // current scalars (when the residual trend predicts that the current one does
+    // not converge), so the device keeps working through the read-back.  If
+    // the current iteration converged the speculative half is simply not
+    // continued (x is the current iterate); if its true residual then fails the
+    // confirmation, the recurrence restarts from the true residual (p = r).
+    hipEvent_t ev = iteration_event();
+    if (!ev) {
+        err = "could not create the iteration event";
+        return WQ_EHIP_CODE;
+    }
+    auto first_half = [&](int first) -> hipError_t {
+        hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, first, clear);
+        hipError_t e = M(V.p, V.ph, s);
+        if (e == hipSuccess) e = Aa(V.ph, V.v, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((dot_partial<T, 1>), g, blk, 0, s, V.rh, V.v, (const T*)nullptr, (const T*)nullptr,
                            (const T*)nullptr, (const T*)nullptr, N, V.part);
         hipLaunchKernelGGL(upd_s<T>, g, blk, 0, s, V.s, V.r, V.v, V.t, V.sc, V.part, nb, N, clear);
-        KR_TRY(M(V.s, V.sh, s));
-        KR_TRY(Aa(V.sh, V.t, s));
+        e = M(V.s, V.sh, s);
+        if (e == hipSuccess) e = Aa(V.sh, V.t, s);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.s, V.t, V.t, (const T*)nullptr,
                            (const T*)nullptr, N, V.part);
+        return hipGetLastError();
+    };
+    if (maxit >= 1) KR_TRY(first_half(1));
+    // residual history for the speculation decision: the next half is enqueued
+    // ahead only while this iteration is predicted (geometric trend of the last
+    // two residuals, with a factor 4 margin) not to reach the tolerance, so that a
+    // solve normally ends without a discarded half
+    double rel1 = std::sqrt(rr0) / nbn, rel2 = 0.0;
+    for (int it = 1; it <= maxit; ++it) {
+        double* hb = h + 16 * (it & 1);             // the scalars of this iteration (two host slots)
         hipLaunchKernelGGL(upd_xr<T>, g, blk, 0, s, x, V.r, V.ph, V.sh, V.s, V.t, V.rh, V.sc, V.part, nb, N, V.part2);
         hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part2, nb, V.sc, 0, (int)F_RHO_RR);
         KR_TRY(hipGetLastError());
-        KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
-        KR_TRY(hipStreamSynchronize(s));
+        KR_TRY(hipMemcpyAsync(hb, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+        KR_TRY(hipEventRecord(ev, s));
+        const double q = rel2 > 0.0 ? std::min(1.0, rel1 / rel2) : 1.0;
+        const bool spec = it < maxit && rel1 * q > 4.0 * tol;
+        if (spec) KR_TRY(first_half(0));            // speculative: the next iteration's first half
+        KR_TRY(hipEventSynchronize(ev));
         *iters = it;
-        const double rel = std::sqrt(h[S_RR]) / nbn;
+        const double rel = std::sqrt(hb[S_RR]) / nbn;
         *relres = rel;
-        if (!std::isfinite(rel) || !std::isfinite(h[S_ALPHA]) || !std::isfinite(h[S_OMEGA])) {
+        rel2 = rel1;
+        rel1 = rel;
+        if (!std::isfinite(rel) || !std::isfinite(hb[S_ALPHA]) || !std::isfinite(hb[S_OMEGA])) {
+            KR_TRY(hipStreamSynchronize(s));
             err = "non-finite value in the BiCGStab recurrence";
             return -8;
         }
         if (rel <= tol) {
-            // confirm with the true residual r = b - A x
+            // confirm with the true residual r = b - A x (after the speculative half, in stream order)
             KR_TRY(A(x, V.t, s));
             hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.t, N);
             hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.t, V.rh, V.t, (const T*)nullptr,
                                (const T*)nullptr, N, V.part);
             hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_AUX, (int)F_STORE);
-            KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+            double* hc = h + 32;
+            KR_TRY(hipMemcpyAsync(hc, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
             KR_TRY(hipStreamSynchronize(s));
-            const double tr = std::sqrt(h[S_AUX]) / nbn;
+            const double tr = std::sqrt(hc[S_AUX]) / nbn;
             *relres = tr;
             if (tr <= tol) return 0;
-            // continue from the true residual: r = r_true, rho = (r^, r_true)
+            if (it == maxit) break;
+            // restart from the true residual: r = r_true, rho = (r^, r_true), p = r
             hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.t, V.r, (T*)nullptr, N);
-            h[0] = h[S_AUX2];
-            KR_TRY(hipMemcpyAsync(V.sc + S_RHO, &h[0], sizeof(double), hipMemcpyHostToDevice, s));
-            KR_TRY(hipStreamSynchronize(s));
+            double* hr = h + 48;                        // (pinned: read by the copy below)
+            *hr = hc[S_AUX2];
+            KR_TRY(hipMemcpyAsync(V.sc + S_RHO, hr, sizeof(double), hipMemcpyHostToDevice, s));
+            KR_TRY(first_half(1));
+            rel2 = 0.0;
             continue;
         }
-        if (h[S_RHO] == 0.0 || h[S_OMEGA] == 0.0 || h[S_RV] == 0.0) {
+        if (hb[S_RHO] == 0.0 || hb[S_OMEGA] == 0.0 || hb[S_RV] == 0.0) {
+            KR_TRY(hipStreamSynchronize(s));
             err = "BiCGStab breakdown (rho, (r^, v) or omega vanished)";
             return -7;
         }
+        if (!spec && it < maxit) KR_TRY(first_half(0));
     }
+    KR_TRY(hipStreamSynchronize(s));
     err = "BiCGStab reached the iteration limit";
     return -6;
 }
