@@ -121,3 +121,24 @@ def test_ir_stagnation_switches_to_fp64_inner_solves():
     print(f"[ir fallback] outer {outer_s}, inner {inner_s}, relres {res_s:.2e}, error vs reference {e:.2e}")
     assert wqfd.ir_fallback_count() == c0 + 1
     assert outer_s >= 2 and res_s <= 1e-12 and e <= 1e-10, (outer_s, res_s, e)
+
+
+@pytest.mark.parametrize("host_geom", [False, True])
+def test_inverted_map_and_bad_weights_are_reported(host_geom, monkeypatch):
+    """wq_setup on a map with det J < 0 (x and z of the control net swapped)
+    reports WQ_EGEOM, on the device geometry path and on the host one; a
+    non-positive control weight of a rational map reports WQ_EINVAL."""
+    from paper_1712_08565_amd import _lib, wqfd
+    if host_geom:
+        monkeypatch.setenv("WQFD_HOST_GEOMETRY", "1")
+    wl = synth.workload("cube5_p2")
+    bad = np.ascontiguousarray(wl.ctrl()[..., ::-1])
+    with pytest.raises(wqfd.WQError) as ei:
+        wqfd.wq_setup(wl.p, wl.knots(), bad)
+    assert ei.value.code == _lib.WQ_EGEOM, ei.value
+    nw = synth.workload("nurbs8_p2")
+    w = nw.weights().copy()
+    w.flat[5] = -1.0
+    with pytest.raises(wqfd.WQError) as ei:
+        wqfd.wq_setup(nw.p, nw.knots(), nw.ctrl(), weights=w)
+    assert ei.value.code == _lib.WQ_EINVAL, ei.value
