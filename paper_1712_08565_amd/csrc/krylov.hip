@@ -12,7 +12,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstring>
 
 #include "device.h"
 #include "krylov.h"
@@ -193,6 +192,19 @@ __global__ __launch_bounds__(kT) void upd_xr(T* __restrict__ x, T* __restrict__ 
     if (threadIdx.x == 0) part[gridDim.x + blockIdx.x] = v;
 }
 
+// Initial scalars of the recurrence from the first reduction (rho = (r^, r) in
+// S_RHO, (r, r) in S_RHO_OLD, (b, b) in S_ALPHA): rho_old = alpha = omega = 1.
+__global__ void init_scalars(double* sc) {
+    const double rr = sc[S_RHO_OLD], bb = sc[S_ALPHA];
+    for (int k = 0; k < kSlots; ++k)
+        if (k != S_RHO) sc[k] = 0.0;
+    sc[S_RHO_OLD] = 1.0;
+    sc[S_ALPHA] = 1.0;
+    sc[S_OMEGA] = 1.0;
+    sc[S_RR] = rr;
+    sc[S_BB] = bb;
+}
+
 // y = b - y (true residual) ; copy
 template <typename T>
 __global__ __launch_bounds__(kT) void resid(const T* __restrict__ b, T* __restrict__ y, size_t n) {
@@ -330,10 +342,12 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     }
     hipLaunchKernelGGL((dot_partial<T, 3>), g, blk, 0, s, V.rh, V.r, V.r, V.r, b, b, N, V.part);
     hipLaunchKernelGGL((dot_final<3>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_RHO, (int)F_STORE);
-    // S_RHO = (r^, r), S_RHO_OLD = (r, r) (overwritten below), S_ALPHA = (b, b): fix up on the host
+    // S_RHO = (r^, r), S_RHO_OLD = (r, r), S_ALPHA = (b, b): moved to their slots and the
+    // recurrence's initial scalars set on the device, then one read-back
+    hipLaunchKernelGGL(init_scalars, dim3(1), dim3(1), 0, s, V.sc);
     KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
     KR_TRY(hipStreamSynchronize(s));
-    const double bb = h[S_ALPHA], rr0 = h[S_RHO_OLD], rho0 = h[S_RHO];
+    const double bb = h[S_BB], rr0 = h[S_RR];
     if (!std::isfinite(bb) || !std::isfinite(rr0)) {
         err = "non-finite value in the right-hand side or initial residual";
         return -8;
@@ -343,18 +357,6 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
         return 0;
     }
     const double nbn = std::sqrt(bb);
-    {
-        double init[kSlots] = {0};
-        init[S_RHO] = rho0;
-        init[S_RHO_OLD] = 1.0;
-        init[S_ALPHA] = 1.0;
-        init[S_OMEGA] = 1.0;
-        init[S_RR] = rr0;
-        init[S_BB] = bb;
-        std::memcpy(h, init, sizeof init);
-        KR_TRY(hipMemcpyAsync(V.sc, h, kSlots * sizeof(double), hipMemcpyHostToDevice, s));
-        KR_TRY(hipStreamSynchronize(s));
-    }
     if (std::sqrt(rr0) / nbn <= tol) {
         *relres = std::sqrt(rr0) / nbn;
         return 0;
