@@ -187,3 +187,32 @@ def test_binding_checks_sizes_before_any_device_work():
         wqfd.wq_set_coef(op, wqfd.WQ_K_SYM6, None)
     with pytest.raises(ValueError, match="ws"):
         wqfd._ws_bytes(torch.zeros(64, dtype=torch.uint8), 16, "ws")
+
+
+def test_new_entries_check_arguments_on_the_host():
+    """wq_setup_nurbs, wq_grad_Kf and the Gauss-point evaluator refuse null and
+    out-of-range arguments before any device work; the evaluator's size query
+    needs no device and grows with the control net (32 bytes per point) and the
+    Gauss tables."""
+    from paper_1712_08565_amd import _lib
+    L = _lib.lib()
+    wl = synth.workload("nurbs8_p3")
+    ks, nk, kp = _setup_args(wl.p, wl.knots())
+    ctrl, w = wl.ctrl(), wl.weights()
+    need = C.c_size_t(0)
+    assert L.wq_setup_nurbs(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), None, 0, None, 1, None, 0,
+                            C.byref(need), None, None) == _lib.WQ_EINVAL
+    assert L.wq_setup_nurbs(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(w.ctypes.data), 0, None, 1,
+                            None, 0, C.byref(need), None, None) == 0 and need.value > 0
+    assert L.wq_grad_Kf(None, None, None, None, None, None) == _lib.WQ_EINVAL
+    for ng in (0, 33):
+        assert L.wq_eval_setup(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), None, ng, None, 0, C.byref(need), None,
+                               None) == _lib.WQ_EINVAL
+    sizes = []
+    for ng in (4, 6):
+        assert L.wq_eval_setup(wl.p, nk, kp, C.c_void_p(ctrl.ctypes.data), C.c_void_p(w.ctypes.data), ng, None, 0,
+                               C.byref(need), None, None) == 0
+        sizes.append(need.value)
+    assert sizes[0] >= ctrl[..., 0].size * 32 and sizes[1] > sizes[0]
+    assert L.wq_eval_slab(None, None, 0, 1, None, None, None, None, None) == _lib.WQ_EINVAL
+    assert L.wq_eval_dims(None, None, None) == _lib.WQ_EINVAL
