@@ -21,6 +21,7 @@ namespace wqfd {
 namespace {
 
 constexpr int kT = 256;
+constexpr int kU = 4;            // elements of a thread per chunk of kT * kU
 constexpr int kMaxBlocks = 1024;
 
 enum Slot {
@@ -30,7 +31,7 @@ enum Slot {
 enum FinalOp { F_STORE = 0, F_ALPHA, F_OMEGA, F_RHO_RR };
 
 inline int nblocks(size_t n) {
-    size_t b = (n + (size_t)kT * 4 - 1) / ((size_t)kT * 4);
+    size_t b = (n + (size_t)kT * kU - 1) / ((size_t)kT * kU);
     if (b > kMaxBlocks) b = kMaxBlocks;
     if (b < 1) b = 1;
     return (int)b;
@@ -48,6 +49,18 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
+// The vector kernels walk the vector in chunks of kT * kU elements, chunks
+// assigned to blocks round-robin; a thread's elements of a chunk are kT apart,
+// and all their loads are issued before the first use, so a thread waits for
+// memory once per chunk instead of once per element.  The kernels are bound by
+// that latency, not by bandwidth: a pass over a vector of a few MB at 8 TB/s
+// takes well under a microsecond.
+template <typename F>
+__device__ inline void for_chunks(size_t n, F&& body) {
+    for (size_t c = (size_t)blockIdx.x * (kT * kU) + threadIdx.x; c < n; c += (size_t)gridDim.x * (kT * kU))
+        body(c);
+}
+
 // partial sums of up to three dot products (x_k, y_k)
 template <typename T, int K>
 __global__ __launch_bounds__(kT) void dot_partial(const T* __restrict__ x0, const T* __restrict__ y0,
@@ -56,11 +69,24 @@ __global__ __launch_bounds__(kT) void dot_partial(const T* __restrict__ x0, cons
                                                   double* __restrict__ part) {
     __shared__ double sh[kT / 64];
     double a0 = 0, a1 = 0, a2 = 0;
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-        a0 += (double)x0[i] * (double)y0[i];
-        if (K > 1) a1 += (double)x1[i] * (double)y1[i];
-        if (K > 2) a2 += (double)x2[i] * (double)y2[i];
-    }
+    for_chunks(n, [&](size_t c) {
+        T u0[kU], v0[kU], u1[kU], v1[kU], u2[kU], v2[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            const bool in = i < n;
+            u0[u] = in ? x0[i] : T(0);
+            v0[u] = in ? y0[i] : T(0);
+            if (K > 1) u1[u] = in ? x1[i] : T(0), v1[u] = in ? y1[i] : T(0);
+            if (K > 2) u2[u] = in ? x2[i] : T(0), v2[u] = in ? y2[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            a0 += (double)u0[u] * (double)v0[u];
+            if (K > 1) a1 += (double)u1[u] * (double)v1[u];
+            if (K > 2) a2 += (double)u2[u] * (double)v2[u];
+        }
+    });
     double r = block_sum(a0, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = r;
     if (K > 1) {
@@ -135,10 +161,25 @@ __global__ __launch_bounds__(kT) void upd_p(T* __restrict__ p, const T* __restri
                                             const double* __restrict__ sc, size_t n, int first, int clear_v) {
     const double beta = first ? 0.0 : (sc[S_RHO] / sc[S_RHO_OLD]) * (sc[S_ALPHA] / sc[S_OMEGA]);
     const double om = sc[S_OMEGA];
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-        p[i] = first ? r[i] : (T)((double)r[i] + beta * ((double)p[i] - om * (double)v[i]));
-        if (clear_v) v[i] = T(0);
-    }
+    for_chunks(n, [&](size_t c) {
+        T rr[kU], pp[kU], vv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            const bool in = i < n;
+            rr[u] = in ? r[i] : T(0);
+            pp[u] = in && !first ? p[i] : T(0);
+            vv[u] = in && !first ? v[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            if (i < n) {
+                p[i] = first ? rr[u] : (T)((double)rr[u] + beta * ((double)pp[u] - om * (double)vv[u]));
+                if (clear_v) v[i] = T(0);
+            }
+        }
+    });
 }
 
 // alpha = rho / (r^, v) from the partials of (r^, v);  s = r - alpha v;
@@ -154,10 +195,23 @@ __global__ __launch_bounds__(kT) void upd_s(T* __restrict__ s, const T* __restri
         sc[S_RV] = rv;
         sc[S_ALPHA] = al;
     }
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-        s[i] = (T)((double)r[i] - al * (double)v[i]);
-        if (clear_t) t[i] = T(0);
-    }
+    for_chunks(n, [&](size_t c) {
+        T rr[kU], vv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            rr[u] = i < n ? r[i] : T(0);
+            vv[u] = i < n ? v[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            if (i < n) {
+                s[i] = (T)((double)rr[u] - al * (double)vv[u]);
+                if (clear_t) t[i] = T(0);
+            }
+        }
+    });
 }
 
 // omega = (t, s) / (t, t) from their partials;  x += alpha p^ + omega s^ ;
@@ -179,13 +233,31 @@ __global__ __launch_bounds__(kT) void upd_xr(T* __restrict__ x, T* __restrict__ 
     }
     const double al = sc[S_ALPHA];
     double a0 = 0, a1 = 0;
-    for (size_t i = (size_t)blockIdx.x * kT + threadIdx.x; i < n; i += (size_t)gridDim.x * kT) {
-        x[i] = (T)((double)x[i] + al * (double)ph[i] + om * (double)sh_[i]);
-        const T rn = (T)((double)s[i] - om * (double)t[i]);
-        r[i] = rn;
-        a0 += (double)rh[i] * (double)rn;
-        a1 += (double)rn * (double)rn;
-    }
+    for_chunks(n, [&](size_t c) {
+        T xx[kU], pp[kU], ss_[kU], ss[kU], tt_[kU], rr[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            const bool in = i < n;
+            xx[u] = in ? x[i] : T(0);
+            pp[u] = in ? ph[i] : T(0);
+            ss_[u] = in ? sh_[i] : T(0);
+            ss[u] = in ? s[i] : T(0);
+            tt_[u] = in ? t[i] : T(0);
+            rr[u] = in ? rh[i] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const size_t i = c + (size_t)u * kT;
+            const T rn = (T)((double)ss[u] - om * (double)tt_[u]);
+            if (i < n) {
+                x[i] = (T)((double)xx[u] + al * (double)pp[u] + om * (double)ss_[u]);
+                r[i] = rn;
+            }
+            a0 += (double)rr[u] * (double)rn;
+            a1 += (double)rn * (double)rn;
+        }
+    });
     double v = block_sum(a0, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = v;
     v = block_sum(a1, sh);
