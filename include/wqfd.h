@@ -290,8 +290,10 @@ int krylov_solve(wq_op A, fd_pc P, int transpose, const double* b, double* x,
  * r = b - K~ x and FP64 update x += d; inner right-preconditioned BiCGStab in
  * FP32 (FP32 apply, FD in `fd_prec` = WQ_F32 or WQ_BF16) on the scaled residual
  * to relative tolerance max(tau_inner, rtol |b|_2 / (2 |r|_2)) (the last inner
- * solve reduces the residual only as far as the outer target needs).  Stops
- * when the FP64 residual satisfies |r|_2/|b|_2 <= rtol.  x: FP64 in/out.
+ * solve reduces the residual only as far as the outer target needs; an inner
+ * solve stops on its recurrence residual, the outer FP64 residual being the
+ * check).  Stops when the FP64 residual satisfies |r|_2/|b|_2 <= rtol.
+ * x: FP64 in/out.
  * ws: device, at least
  * ir_ws_bytes(A).  *outer, *inner_total, *relres: host outputs.
  * Errors: as krylov_solve.

@@ -1292,9 +1292,8 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
         return WQ_OK;
     }
     auto residual = [&]() -> int {
-        hipError_t e = wqfd::launch_apply(*op, WQ_F64, x, t64, false, s);
+        hipError_t e = wqfd::launch_apply(*op, WQ_F64, x, r64, false, s);
         if (e != hipSuccess) return hip_fail(e, "ir residual apply");
-        HIP_TRY(hipMemcpyAsync(r64, t64, N * 8, hipMemcpyDeviceToDevice, s), "ir copy");
         HIP_TRY(wqfd::launch_resid(b, r64, N, s), "ir resid");
         int r2 = wqfd::norm2(r64, N, nws, &nr, err, s);
         return r2 ? fail(r2, err) : WQ_OK;
@@ -1313,7 +1312,7 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
             HIP_TRY(wqfd::launch_cast_f64_to_f32(r64, b32, N, 1.0 / nr, s), "ir cast");
             const double tol = std::max(tau_inner, 0.5 * rtol * nb / nr);
             rc = wqfd::bicgstab<float>(A32, M32, N, b32, d32, true, tol, maxit_inner, kws, &it, &rel, err, s,
-                                       op->fused ? &A32acc : nullptr);
+                                       op->fused ? &A32acc : nullptr, false);
             *inner_total += it;
             if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
             HIP_TRY(wqfd::launch_axpy_f32_to_f64(d32, x, N, nr, s), "ir update");
@@ -1322,7 +1321,7 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
             HIP_TRY(hipMemcpyAsync(t64, r64, N * 8, hipMemcpyDeviceToDevice, s), "ir copy");
             const double tol = std::max(0.5 * rtol * nb / nr, 1e-14);
             rc = wqfd::bicgstab<double>(A64, M64, N, t64, d64, true, tol, maxit_inner, kws, &it, &rel, err, s,
-                                        op->fused ? &A64acc : nullptr);
+                                        op->fused ? &A64acc : nullptr, false);
             *inner_total += it;
             if (rc && rc != WQ_ENOCONV && rc != WQ_EBREAKDOWN) return fail(rc, err);
             HIP_TRY(wqfd::launch_axpy_f64(d64, x, N, 1.0, s), "ir update");

@@ -16,11 +16,15 @@ size_t krylov_bytes(size_t N, bool fp32);
 
 // Right-preconditioned BiCGStab: A x = b with x = M y.  Returns 0 or a
 // negative wqfd error code (message in err).  Synchronises once per iteration.
-template <typename T>
 // A_acc (optional): the operator adding its product into a zeroed output; the
 // iteration then clears the two product outputs inside its vector updates.
+// confirm: check a converged recurrence residual against the true residual
+// b - A x before returning (the inner solves of iterative refinement skip it:
+// the outer loop forms the true residual in FP64 anyway).
+template <typename T>
 int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0_zero, double tol, int maxit,
-             void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc = nullptr);
+             void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc = nullptr,
+             bool confirm = true);
 
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s);
 size_t norm2_ws_bytes();

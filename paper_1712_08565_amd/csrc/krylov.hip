@@ -387,7 +387,8 @@ hipError_t launch_axpy_f64(const double* d, double* x, size_t n, double scale, h
 
 template <typename T>
 int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0_zero, double tol, int maxit,
-             void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc) {
+             void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc,
+             bool confirm) {
     // A_acc: the same operator adding into a cleared output (the update kernels
     // clear v and t just before the products that fill them)
     const LinOp& Aa = A_acc ? *A_acc : A;
@@ -418,21 +419,6 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     // recurrence's initial scalars set on the device, then one read-back
     hipLaunchKernelGGL(init_scalars, dim3(1), dim3(1), 0, s, V.sc);
     KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
-    KR_TRY(hipStreamSynchronize(s));
-    const double bb = h[S_BB], rr0 = h[S_RR];
-    if (!std::isfinite(bb) || !std::isfinite(rr0)) {
-        err = "non-finite value in the right-hand side or initial residual";
-        return -8;
-    }
-    if (bb == 0.0) {
-        hipLaunchKernelGGL(fill0<T>, g, blk, 0, s, x, N);
-        return 0;
-    }
-    const double nbn = std::sqrt(bb);
-    if (std::sqrt(rr0) / nbn <= tol) {
-        *relres = std::sqrt(rr0) / nbn;
-        return 0;
-    }
     // Each iteration is enqueued in two halves.  The first (p, p^ = M p, v = A p^,
     // alpha, s, s^ = M s, t = A s^, the partials of omega) touches neither x nor r;
     // the second (omega, x and r, rho) ends with the scalars' copy to the host.
@@ -442,11 +428,6 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     // the current iteration converged the speculative half is simply not
     // continued (x is the current iterate); if its true residual then fails the
     // confirmation, the recurrence restarts from the true residual (p = r).
-    hipEvent_t ev = iteration_event();
-    if (!ev) {
-        err = "could not create the iteration event";
-        return WQ_EHIP_CODE;
-    }
     auto first_half = [&](int first) -> hipError_t {
         hipLaunchKernelGGL(upd_p<T>, g, blk, 0, s, V.p, V.r, V.v, V.sc, N, first, clear);
         hipError_t e = M(V.p, V.ph, s);
@@ -462,7 +443,31 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
                            (const T*)nullptr, N, V.part);
         return hipGetLastError();
     };
+    // the first iteration's first half is enqueued before the host waits for the
+    // initial scalars (it touches neither x nor r, so an early return leaves them as
+    // they are)
+    hipEvent_t ev = iteration_event();
+    if (!ev) {
+        err = "could not create the iteration event";
+        return WQ_EHIP_CODE;
+    }
+    KR_TRY(hipEventRecord(ev, s));
     if (maxit >= 1) KR_TRY(first_half(1));
+    KR_TRY(hipEventSynchronize(ev));
+    const double bb = h[S_BB], rr0 = h[S_RR];
+    if (!std::isfinite(bb) || !std::isfinite(rr0)) {
+        err = "non-finite value in the right-hand side or initial residual";
+        return -8;
+    }
+    if (bb == 0.0) {
+        hipLaunchKernelGGL(fill0<T>, g, blk, 0, s, x, N);
+        return 0;
+    }
+    const double nbn = std::sqrt(bb);
+    if (std::sqrt(rr0) / nbn <= tol) {
+        *relres = std::sqrt(rr0) / nbn;
+        return 0;
+    }
     // residual history for the speculation decision: the next half is enqueued
     // ahead only while this iteration is predicted (geometric trend of the last
     // two residuals, with a factor 4 margin) not to reach the tolerance, so that a
@@ -490,6 +495,7 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
             return -8;
         }
         if (rel <= tol) {
+            if (!confirm) return 0;
             // confirm with the true residual r = b - A x (after the speculative half, in stream order)
             KR_TRY(A(x, V.t, s));
             hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.t, N);
@@ -525,9 +531,9 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
 }
 
 template int bicgstab<double>(const LinOp&, const LinOp&, size_t, const double*, double*, bool, double, int,
-                              void*, int*, double*, std::string&, hipStream_t, const LinOp*);
+                              void*, int*, double*, std::string&, hipStream_t, const LinOp*, bool);
 template int bicgstab<float>(const LinOp&, const LinOp&, size_t, const float*, float*, bool, double, int, void*,
-                             int*, double*, std::string&, hipStream_t, const LinOp*);
+                             int*, double*, std::string&, hipStream_t, const LinOp*, bool);
 
 // FP64 norm of a vector (two-pass), synchronising.
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s) {
