@@ -24,8 +24,23 @@ _DT = {WQ_F64: torch.float64, WQ_F32: torch.float32, WQ_BF16: torch.float32}
 
 
 def _stream(stream=None):
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return C.c_void_p(s.cuda_stream)
+    """The stream a call is enqueued on: torch's current stream by default.  A
+    torch stream other than the current one first waits for the work already
+    queued on the current stream (where the tensors passed in were produced)."""
+    cur = torch.cuda.current_stream()
+    if stream is None:
+        return C.c_void_p(cur.cuda_stream)
+    if isinstance(stream, torch.cuda.Stream) and stream != cur:
+        stream.wait_stream(cur)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _keep_for(t: torch.Tensor, stream):
+    """A tensor allocated here and used on another stream: its memory is not
+    reused before that stream's queued work (a solve may return with work of its
+    own still queued) has finished."""
+    if isinstance(stream, torch.cuda.Stream):
+        t.record_stream(stream)
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -381,7 +396,9 @@ def krylov_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = 
     x = torch.zeros_like(b) if x is None else x
     _need(x, torch.float64, A.N, "x")
     nb = lib().krylov_ws_bytes(A.handle)
-    ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    if ws is None:
+        ws = torch.empty(nb, dtype=torch.uint8, device=A.device)
+        _keep_for(ws, stream)
     wsb = _ws_bytes(ws, nb, "ws")
     it, rel = C.c_int(0), C.c_double(0)
     rc = lib().krylov_solve(A.handle, P.handle, int(transpose), _p(b), _p(x), rtol, maxit, _p(ws), wsb,
@@ -399,7 +416,9 @@ def ir_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None
     x = torch.zeros_like(b) if x is None else x
     _need(x, torch.float64, A.N, "x")
     nb = lib().ir_ws_bytes(A.handle)
-    ws = torch.empty(nb, dtype=torch.uint8, device=A.device) if ws is None else ws
+    if ws is None:
+        ws = torch.empty(nb, dtype=torch.uint8, device=A.device)
+        _keep_for(ws, stream)
     wsb = _ws_bytes(ws, nb, "ws")
     outer, inner, rel = C.c_int(0), C.c_int(0), C.c_double(0)
     check(lib().ir_solve(A.handle, P.handle, fd_prec, _p(b), _p(x), rtol, tau_inner, max_outer, maxit_inner, _p(ws),
