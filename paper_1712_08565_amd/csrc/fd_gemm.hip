@@ -163,12 +163,14 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
 // load needs a bounds check.  Data loads are unconditional too: rows and columns
 // past the extents are clamped to the last one (finite values that meet the
 // zero padding of the matrix, or land in outputs that are not stored).  All
-// loads are raw buffer loads with the step offset in a scalar register.
+// loads are raw buffer loads with the step offset in a scalar register, issued
+// a fixed number of steps ahead of the first product (software pipelined).
 // One wave per 16-wide block (KB = ceil(n / 16) waves); NP planes (xy) or
-// column blocks (z) per workgroup share the matrices, which are loaded once
-// (double-buffered LDS block, one barrier per item).  FP64 with KB > 6 loads
-// the second matrix after the first product, into the first one's registers.
-// Contraction steps past the true length are skipped.
+// column blocks (z) per workgroup share the matrices, which are loaded once:
+// the first products of all NP items run in the pipelined load loop, and the
+// second matrix takes the first one's registers step by step as they are used
+// (one barrier per workgroup).  Contraction steps past the true length are
+// skipped.
 constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
 
 template <int PREC>
@@ -191,9 +193,8 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;                         // padded matrix row
     constexpr int LDQ = 16 * KB + 1;                     // odd row length of the Q block
-    constexpr bool PRE = PREC != 1 || KB <= 6;           // both matrices in registers from the start
-    static_assert(NP == 1 || PRE, "several planes per block keep both matrices in registers");
-    __shared__ T sQ[NP > 1 ? 2 : 1][16 * LDQ];
+    constexpr int DL = 60 / (NP + 2) - 1;                // load lead in steps
+    __shared__ T sQ[NP][16 * LDQ];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
     const int r0 = blockIdx.x * 16;                      // first i2 of this block
@@ -206,51 +207,58 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     const unsigned vo = (unsigned)((kb * n1 + jcc) * sizeof(T));
     const unsigned va = (unsigned)((kb * LDP + i2a) * sizeof(T)), vc = (unsigned)((kb * LDP + jc) * sizeof(T));
     constexpr unsigned kstep = 4 * LDP * sizeof(T);      // bytes between contraction steps of a matrix
-    T a[NKS], c[PRE ? NKS : 1], b[NP][NKS];
+    T a[NKS], b[NP][NKS];
+    Acc q[NP];
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {
-        a[s] = buf_load<T>(r2, va, s * kstep);
-        if constexpr (PRE) c[s] = buf_load<T>(r1, vc, s * kstep);
-    }
+    for (int p = 0; p < NP; ++p) q[p] = Acc{0, 0, 0, 0};
+    // Q = T2 X for every plane of the block: the loads of step s (T2 and the data)
+    // are issued DL steps ahead of the products of step s, in an order pinned by
+    // scheduling barriers, so the loads in flight stay under the 6-bit load
+    // counter and a product waits for its own step only; once step s of T2 is
+    // used, its register takes step s of T1 for the second product.
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int zp = min(z0 + p, n3 - 1);             // (a plane past the end is not used)
+    for (int s = 0; s < NKS + DL; ++s) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < NKS) {
+            a[s] = buf_load<T>(r2, va, s * kstep);
 #pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            if (4 * s + 3 < n2)                          // whole step inside the plane
-                b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
-            else if (s < ks2)                            // last step: rows clamped
-                b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
-                                      (unsigned)(zp * psz * sizeof(T)));
-            else
-                b[p][s] = T(0);                          // step skipped
+            for (int p = 0; p < NP; ++p) {
+                const int zp = min(z0 + p, n3 - 1);     // (a plane past the end is not stored)
+                if (4 * s + 3 < n2)                      // whole step inside the plane
+                    b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
+                else if (s < ks2)                        // last step: rows clamped
+                    b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
+                                          (unsigned)(zp * psz * sizeof(T)));
+                else
+                    b[p][s] = T(0);                      // step skipped
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (s >= DL) {
+            const int m = s - DL;
+            if (m < ks2) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) q[p] = mma_step<PREC>(a[m], b[p][m], q[p]);
+            }
+            a[m] = buf_load<T>(r1, vc, m * kstep);
         }
     }
 #pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sQ[p][G<PREC>::drow(kb, v) * LDQ + jc] = q[p][v];
+    __syncthreads();
+    // out = Q T1^T, Q rows from LDS into the plane's dead data registers
+#pragma unroll
     for (int p = 0; p < NP; ++p) {
         if (z0 + p < n3) {                               // uniform over the block
-            T* Q = sQ[p & 1];
-            Acc q = Acc{0, 0, 0, 0};
+            T(&aq)[NKS] = b[p];
 #pragma unroll
-            for (int s = 0; s < NKS; ++s)
-                if (s < ks2) q = mma_step<PREC>(a[s], b[p][s], q);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) Q[G<PREC>::drow(kb, v) * LDQ + jc] = q[v];
-            __syncthreads();
-            T(&aq)[NKS] = b[p];                          // the plane's data is dead: its registers take Q
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                aq[s] = Q[cl * LDQ + 4 * s + kb];
-                if constexpr (!PRE) a[s] = buf_load<T>(r1, vc, s * kstep);   // (NP = 1: a is dead)
-            }
+            for (int s = 0; s < NKS; ++s) aq[s] = sQ[p][cl * LDQ + 4 * s + kb];
             Acc r = Acc{0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                if (s < ks1) {
-                    if constexpr (PRE) r = mma_step<PREC>(aq[s], c[s], r);
-                    else r = mma_step<PREC>(aq[s], a[s], r);
-                }
-            }
+            for (int s = 0; s < NKS; ++s)
+                if (s < ks1) r = mma_step<PREC>(aq[s], a[s], r);
             if (jc < n1) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -272,9 +280,8 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;
-    constexpr bool PRE = PREC != 1 || KB <= 6;
-    static_assert(NP == 1 || PRE, "several column blocks per block keep both matrices in registers");
-    __shared__ T sY[NP > 1 ? 2 : 1][16 * KB * FLD];
+    constexpr int DL = 60 / (NP + 2) - 1;
+    __shared__ T sY[NP][16 * KB * FLD];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
     const int C = n1 * n2;
@@ -283,65 +290,81 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), rf = buf_rsrc(T3ft), rb = buf_rsrc(T3bt);
     const unsigned va = (unsigned)((kb * LDP + i3r) * sizeof(T));
     constexpr unsigned kstep = 4 * LDP * sizeof(T);
-    T a[NKS], c[PRE ? NKS : 1], b[NP][NKS];
+    T a[NKS], b[NP][NKS];
+    Acc y[NP];
 #pragma unroll
-    for (int s = 0; s < NKS; ++s) {                      // contraction index j3 = 4 s + kb
-        a[s] = buf_load<T>(rf, va, s * kstep);
-        if constexpr (PRE) c[s] = buf_load<T>(rb, va, s * kstep);
-    }
-    // every read of `in` by this block (all its column blocks) precedes its
-    // first write: in may be out
+    for (int p = 0; p < NP; ++p) y[p] = Acc{0, 0, 0, 0};
+    // eigenvalue sums of the scaling, loaded first (the loop's scheduling
+    // barriers keep later loads behind it)
+    double l12[NP], l3v[4];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
-        const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
-#pragma unroll
-        for (int s = 0; s < NKS; ++s) {
-            if (4 * s + 3 < n3)                          // whole step inside the array
-                b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
-            else if (s < ks3)                            // last step: rows clamped
-                b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
-            else
-                b[p][s] = T(0);                          // step skipped
+        const int g = (blockIdx.x * NP + p) * 16 + cl;
+        l12[p] = 0.0;
+        if (g < C) {
+            const int i2 = g / n1, i1 = g - i2 * n1;
+            l12[p] = l1[i1] + l2[i2];
         }
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i3 = 16 * t + G<PREC>::drow(kb, v);
+        l3v[v] = i3 < n3 ? l3[i3] : 1.0;
+    }
+    // forward products of every column block, pipelined as in the xy pass; step
+    // s of T3f's register takes step s of T3b once used.  Every read of `in` by
+    // this block (all its column blocks) precedes its first write: in may be out.
+#pragma unroll
+    for (int s = 0; s < NKS + DL; ++s) {                 // contraction index j3 = 4 s + kb
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < NKS) {
+            a[s] = buf_load<T>(rf, va, s * kstep);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
+                const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
+                if (4 * s + 3 < n3)                      // whole step inside the array
+                    b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
+                else if (s < ks3)                        // last step: rows clamped
+                    b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
+                else
+                    b[p][s] = T(0);                      // step skipped
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (s >= DL) {
+            const int m = s - DL;
+            if (m < ks3) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) y[p] = mma_step<PREC>(a[m], b[p][m], y[p]);
+            }
+            a[m] = buf_load<T>(rb, va, m * kstep);
+        }
+    }
+    // scaling by the eigenvalue sums, Y through LDS
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const bool gin = (blockIdx.x * NP + p) * 16 + cl < C;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i3 = 16 * t + G<PREC>::drow(kb, v);
+            sY[p][i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)y[p][v] / (l12[p] + l3v[v])) : T(0);
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int gb = (blockIdx.x * NP + p) * 16;
         if (gb < C) {                                    // uniform over the block
             const int g = gb + cl;
-            const bool gin = g < C;
-            T* Y = sY[p & 1];
-            Acc y = Acc{0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s)
-                if (s < ks3) y = mma_step<PREC>(a[s], b[p][s], y);
-            double l12 = 0.0;
-            if (gin) {
-                const int i2 = g / n1, i1 = g - i2 * n1;
-                l12 = l1[i1] + l2[i2];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i3 = 16 * t + G<PREC>::drow(kb, v);
-                Y[i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)y[v] / (l12 + l3[i3])) : T(0);
-            }
-            __syncthreads();
             T(&by)[NKS] = b[p];                          // the block's data is dead: its registers take Y
 #pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                by[s] = Y[(4 * s + kb) * FLD + cl];
-                if constexpr (!PRE) a[s] = buf_load<T>(rb, va, s * kstep);   // (NP = 1: a is dead)
-            }
+            for (int s = 0; s < NKS; ++s) by[s] = sY[p][(4 * s + kb) * FLD + cl];
             Acc z = Acc{0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < NKS; ++s) {
-                if (s < ks3) {
-                    if constexpr (PRE) z = mma_step<PREC>(c[s], by[s], z);
-                    else z = mma_step<PREC>(a[s], by[s], z);
-                }
-            }
-            if (gin) {
+            for (int s = 0; s < NKS; ++s)
+                if (s < ks3) z = mma_step<PREC>(a[s], by[s], z);
+            if (g < C) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int i3 = 16 * t + G<PREC>::drow(kb, v);
