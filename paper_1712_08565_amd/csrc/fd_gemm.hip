@@ -173,6 +173,11 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
 // skipped.
 constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
 
+// Workgroup barrier that waits only for this wave's LDS operations: global loads
+// in flight (the pipelined operands) stay in flight across it, where the release
+// fence of __syncthreads() would drain them.
+__device__ inline void lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int PREC>
 __device__ inline typename G<PREC>::Acc mma_step(typename G<PREC>::T a, typename G<PREC>::T b,
                                                  typename G<PREC>::Acc c) {
@@ -247,7 +252,7 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int v = 0; v < 4; ++v) sQ[p][G<PREC>::drow(kb, v) * LDQ + jc] = q[p][v];
-    __syncthreads();
+    lds_sync();                                      // (the second matrix stays in flight)
     // out = Q T1^T, Q rows from LDS into the plane's dead data registers
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -351,7 +356,7 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
             sY[p][i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)y[p][v] / (l12[p] + l3v[v])) : T(0);
         }
     }
-    __syncthreads();
+    lds_sync();                                      // (the second matrix stays in flight)
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const int gb = (blockIdx.x * NP + p) * 16;
