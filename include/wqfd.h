@@ -272,9 +272,11 @@ void fd_destroy(fd_pc P);
  * K~ x = b (transpose = 0) or K~^T x = b (transpose = 1), preconditioner
  * P^{-1} (FP64), as in Section 4.  x holds x0 on entry and the solution on
  * exit.  Stops when |b - K~ x|_2 / |b|_2 <= rtol (recurrence residual, then
- * confirmed with the true residual).  ws: device, at least
+ * confirmed with the true residual; a failed confirmation restarts the
+ * recurrence from the true residual).  ws: device, at least
  * krylov_ws_bytes(A) bytes.  Synchronises once per iteration (one small
- * device-to-host copy).  *iters, *relres: host outputs.
+ * device-to-host copy).  *iters, *relres: host outputs (*relres: the true
+ * relative residual on success, the last recurrence value on WQ_ENOCONV).
  * Errors: WQ_EINVAL, WQ_ENOMEM, WQ_ENOCONV, WQ_EBREAKDOWN, WQ_ENONFINITE, WQ_EHIP.
  * ------------------------------------------------------------------------ */
 /* krylov_ws_bytes: device workspace bytes krylov_solve needs for A's N (nine
@@ -313,6 +315,14 @@ int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double r
  * has WQ_F64 prepared; *outer and *inner_total count those steps too.  This
  * returns how many ir_solve calls of the calling thread have switched so far. */
 int ir_fallback_count(void);
+
+/* Restarts of krylov_solve's BiCGStab (ir_solve's inner solves stop on the
+ * recurrence residual and never restart): when the recurrence residual passes
+ * the tolerance but the true
+ * residual b - A x does not (reading R8 of the Krylov stopping test, Section 4),
+ * the recurrence restarts from the true residual instead of stopping.  This
+ * returns how many such restarts the calling thread's solves have made so far. */
+int krylov_restart_count(void);
 
 /* ------------------------------------------------------------------------ *
  * Host-only inspection of the set-up (no device work; for checks and tools).

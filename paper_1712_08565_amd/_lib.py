@@ -65,6 +65,7 @@ SIGNATURES = [
     ("ir_solve", C.c_int, [_vp, _vp, C.c_int, _vp, _vp, C.c_double, C.c_double, C.c_int, C.c_int, _vp,
                            C.c_size_t, _ip, _ip, _dp, _vp]),
     ("ir_fallback_count", C.c_int, []),
+    ("krylov_restart_count", C.c_int, []),
     ("wq_space_1d", C.c_int, [C.c_int, C.c_int, _vp, _i32p, _i32p, _vp, _vp, _vp]),
     ("fd_eig_1d", C.c_int, [C.c_int, C.c_int, _vp, _vp, _vp]),
     ("wq_geometry_host", C.c_int, [C.c_int, _i32p, C.POINTER(C.c_void_p), _vp, _vp, _vp, _vp, _vp]),

@@ -1229,6 +1229,8 @@ size_t ir_ws_bytes(wq_op A) {
 
 int ir_fallback_count(void) { return g_ir_fallbacks; }
 
+int krylov_restart_count(void) { return wqfd::bicgstab_restart_count(); }
+
 int ir_solve(wq_op A, fd_pc P, int fd_prec, const double* b, double* x, double rtol, double tau_inner, int max_outer,
              int maxit_inner, void* ws, size_t ws_bytes, int* outer, int* inner_total, double* relres,
              wq_stream_t s_) {

@@ -26,6 +26,9 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
              void* ws, int* iters, double* relres, std::string& err, hipStream_t s, const LinOp* A_acc = nullptr,
              bool confirm = true);
 
+// failed true-residual confirmations that restarted a recurrence, calling thread
+int bicgstab_restart_count();
+
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s);
 size_t norm2_ws_bytes();
 // sum of x[0..N) into *out (host); part_ws: norm2_ws_bytes() of device memory

@@ -309,6 +309,8 @@ __global__ __launch_bounds__(kT) void axpy_kernel(const D* __restrict__ d, doubl
         x[i] += scale * (double)d[i];
 }
 
+thread_local int g_restarts = 0;                 // failed confirmations that restarted (this thread)
+
 // thread-local pinned host block for the scalar read-back: slots 0-15 and
 // 16-31 alternate between iterations, 32-47 the confirmation, 48 the restart value
 double* host_scalars() {
@@ -367,6 +369,8 @@ Vecs<T> carve(void* ws, size_t N) {
 }
 
 }  // namespace
+
+int bicgstab_restart_count() { return g_restarts; }
 
 size_t krylov_bytes(size_t N, bool fp32) { return fp32 ? vec_bytes<float>(N) : vec_bytes<double>(N); }
 
@@ -510,6 +514,7 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
             if (tr <= tol) return 0;
             if (it == maxit) break;
             // restart from the true residual: r = r_true, rho = (r^, r_true), p = r
+            ++g_restarts;
             hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.t, V.r, (T*)nullptr, N);
             double* hr = h + 48;                        // (pinned: read by the copy below)
             *hr = hc[S_AUX2];

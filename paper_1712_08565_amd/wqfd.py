@@ -17,7 +17,7 @@ from ._lib import (WQ_BF16, WQ_F32, WQ_F64, WQ_FD_NOALLOC_BYTES, WQ_K_IDENTITY, 
 __all__ = ["WqOp", "FdPc", "wq_setup", "wq_dims", "wq_quad_points", "wq_detj", "wq_set_coef", "wq_apply",
            "wq_apply_T", "wq_apply_acc", "wq_set_alpha", "wq_apply_mass", "wq_rhs", "wq_grad_K", "wq_grad_f", "wq_grad_Kf",
            "wq_grad_alpha", "wq_alpha_mean", "fd_setup", "fd_apply", "fd_apply_noalloc", "fd_set_shift", "fd_factors",
-           "krylov_solve", "ir_solve", "ir_fallback_count", "WqEval", "wq_eval_setup", "wq_eval_slab", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
+           "krylov_solve", "ir_solve", "ir_fallback_count", "krylov_restart_count", "WqEval", "wq_eval_setup", "wq_eval_slab", "WQ_F64", "WQ_F32", "WQ_BF16", "WQ_K_IDENTITY", "WQ_K_SCALAR",
            "WQ_K_SYM6", "WQError"]
 
 _DT = {WQ_F64: torch.float64, WQ_F32: torch.float32, WQ_BF16: torch.float32}
@@ -424,6 +424,12 @@ def ir_solve(A: WqOp, P: FdPc, b: torch.Tensor, x: Optional[torch.Tensor] = None
     check(lib().ir_solve(A.handle, P.handle, fd_prec, _p(b), _p(x), rtol, tau_inner, max_outer, maxit_inner, _p(ws),
                          wsb, C.byref(outer), C.byref(inner), C.byref(rel), _stream(stream)), "ir_solve")
     return x, outer.value, inner.value, rel.value
+
+
+def krylov_restart_count() -> int:
+    """Number of BiCGStab restarts from the true residual (a converged recurrence
+    residual whose true residual missed the tolerance) in this thread's solves."""
+    return int(lib().krylov_restart_count())
 
 
 def ir_fallback_count() -> int:

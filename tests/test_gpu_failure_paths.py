@@ -1,5 +1,6 @@
 """Failure handling and the deterministic mode, forced from the host (no kernel
-is made to fault): the iteration limit (WQ_ENOCONV, last iterate returned), a
+is made to fault): the iteration limit (WQ_ENOCONV, last iterate returned),
+failed true-residual confirmations (a tolerance below the rounding floor), a
 non-finite right-hand side (WQ_ENONFINITE, in BiCGStab and in the refinement
 loop), a zero right-hand side (x = 0 at once), the refinement loop's stagnation
 fallback to FP64 inner solves (forced by an inner tolerance that makes the FP32
@@ -43,6 +44,30 @@ def test_iteration_limit_returns_last_iterate():
     with pytest.raises(wqfd.WQError) as e:
         wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-12, maxit=2)
     assert e.value.code == WQ_ENOCONV and "iteration limit" in str(e.value)
+
+
+def test_failed_confirmations_restart_without_losing_the_iterate():
+    """A tolerance below the rounding floor: the recurrence residual passes it
+    (it keeps falling geometrically), the true residual b - A x never does, so
+    each confirmation fails and the recurrence restarts from the true residual
+    (with a speculative half-iteration already queued) until the iteration
+    limit.  The returned iterate stays as accurate as a converged solve's."""
+    import torch
+    from paper_1712_08565_amd import wqfd
+    wl, dp = setup()
+    xr, itr, _ = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-13)
+    c0 = wqfd.krylov_restart_count()
+    x, it, res = wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-19, maxit=3 * itr + 20, raise_on_noconv=False)
+    restarts = wqfd.krylov_restart_count() - c0
+    d = (torch.linalg.norm(x - xr) / torch.linalg.norm(xr)).item()
+    print(f"[failure] {itr} iterations to 1e-13; {it} at rtol 1e-19 with {restarts} restarts, relres {res:.1e}, "
+          f"|x - x_ref| / |x_ref| {d:.1e}", flush=True)
+    assert it == 3 * itr + 20 and restarts >= 1 and res < 1e-12 and bool(torch.isfinite(x).all()), (it, res)
+    assert d <= 1e-9, d
+    # a converged solve does not restart
+    c1 = wqfd.krylov_restart_count()
+    wqfd.krylov_solve(dp.A, dp.P, dp.b, rtol=1e-10)
+    assert wqfd.krylov_restart_count() == c1
 
 
 def test_non_finite_right_hand_side_is_reported():
