@@ -19,6 +19,8 @@
 // epilogue.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "buffer.h"
 #include "device.h"
 #include "fd_gemm.h"
@@ -187,6 +189,29 @@ __device__ inline typename G<PREC>::Acc mma_step(typename G<PREC>::T a, typename
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Accumulator and product of one wave: a 16 x 16 block (v_mfma_f64_16x16x4f64 or
+// v_mfma_f32_16x16x4f32), or, SMALL (FP64 only), four 4 x 4 blocks
+// (v_mfma_f64_4x4x4f64, a quarter of the matrix-core time) for a block of the
+// output with at most 4 rows or columns inside the array.  Lane layout of the
+// four-block product, lane = 16 kb + cl: A_b[i][k] at i = cl & 3, b = cl >> 2,
+// k = kb; B_b[k][j] at j = cl & 3, b = cl >> 2, k = kb; D_b[i][j] at lane
+// 16 i + 4 b + j.  With the A operand the same in all four blocks (rows i of
+// a 4-row block) the lane holds D row kb, column cl; with B the same in all four
+// (columns j of a 4-column block) it holds row 4 (cl >> 2) + kb, column cl & 3.
+template <int PREC, bool SMALL>
+struct WaveMM {
+    using T = typename G<PREC>::T;
+    using Acc = typename G<PREC>::Acc;
+    __device__ static Acc zero() { return Acc{0, 0, 0, 0}; }
+    __device__ static Acc mma(T a, T b, Acc c) { return mma_step<PREC>(a, b, c); }
+};
+template <>
+struct WaveMM<1, true> {
+    using Acc = double;
+    __device__ static Acc zero() { return 0.0; }
+    __device__ static Acc mma(double a, double b, double c) { return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0); }
+};
+
 template <int PREC, int KB, int NP>
 __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T* __restrict__ in,
                                                       typename G<PREC>::T* __restrict__ out,
@@ -194,84 +219,117 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
                                                       const typename G<PREC>::T* __restrict__ T2t, int n1, int n2,
                                                       int n3) {
     using T = typename G<PREC>::T;
-    using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;                         // padded matrix row
     constexpr int LDQ = 16 * KB + 1;                     // odd row length of the Q block
     constexpr int DL = 10;                               // load lead in steps (measured: 6-19 within 3%, 10 best)
     __shared__ T sQ[NP][16 * LDQ];
-    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
     const int r0 = blockIdx.x * 16;                      // first i2 of this block
     const int z0 = blockIdx.y * NP;                      // first z-plane of this block
-    const unsigned psz = (unsigned)(n1 * n2);
-    const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;  // contraction steps of the two products
-    const int i2a = r0 + cl, jc = 16 * t + cl;           // A row (i2) and B column (j1, then i1)
-    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), r1 = buf_rsrc(T1t), r2 = buf_rsrc(T2t);
-    const int jcc = min(jc, n1 - 1);                     // clamped data column
-    const unsigned vo = (unsigned)((kb * n1 + jcc) * sizeof(T));
-    const unsigned va = (unsigned)((kb * LDP + i2a) * sizeof(T)), vc = (unsigned)((kb * LDP + jc) * sizeof(T));
-    constexpr unsigned kstep = 4 * LDP * sizeof(T);      // bytes between contraction steps of a matrix
-    T a[NKS], b[NP][NKS];
-    Acc q[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) q[p] = Acc{0, 0, 0, 0};
-    // Q = T2 X for every plane of the block: the loads of step s (T2 and the data)
-    // are issued DL steps ahead of the products of step s, in an order pinned by
-    // scheduling barriers, so the loads in flight stay under the 6-bit load
-    // counter and a product waits for its own step only; once step s of T2 is
-    // used, its register takes step s of T1 for the second product.
-#pragma unroll
-    for (int s = 0; s < NKS + DL; ++s) {
-        __builtin_amdgcn_sched_barrier(0);
-        if (s < NKS) {
-            a[s] = buf_load<T>(r2, va, s * kstep);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int zp = min(z0 + p, n3 - 1);     // (a plane past the end is not stored)
-                if (4 * s + 3 < n2)                      // whole step inside the plane
-                    b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
-                else if (s < ks2)                        // last step: rows clamped
-                    b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
-                                          (unsigned)(zp * psz * sizeof(T)));
-                else
-                    b[p][s] = T(0);                      // step skipped
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        if (s >= DL) {
-            const int m = s - DL;
-            if (m < ks2) {
-#pragma unroll
-                for (int p = 0; p < NP; ++p) q[p] = mma_step<PREC>(a[m], b[p][m], q[p]);
-            }
-            a[m] = buf_load<T>(r1, vc, m * kstep);
-        }
+    const int tl = (n1 - 1) >> 4;                        // last wave with columns inside the plane
+    if (t > tl) {                                        // no column of this wave is used
+        lds_sync();
+        return;
     }
+    // a row block (whole workgroup) or column block (this wave) with at most 4
+    // entries inside the plane runs on the four-block product (FP64)
+    const bool rr = PREC == 1 && n2 - r0 <= 4, rc = PREC == 1 && t == tl && n1 - 16 * tl <= 4;
+    auto body = [&](auto small_tag) {
+        constexpr bool SMALL = decltype(small_tag)::value;
+        using MM = WaveMM<PREC, SMALL>;
+        using Acc = typename MM::Acc;
+        const unsigned psz = (unsigned)(n1 * n2);
+        const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;  // contraction steps of the two products
+        const int arow = rr ? (cl & 3) : cl;             // A operand row in the row block
+        const int jc = 16 * t + (rc ? (cl & 3) : cl);   // B operand column (j1, then i1)
+        const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), r1 = buf_rsrc(T1t), r2 = buf_rsrc(T2t);
+        const int jcc = min(jc, n1 - 1);                 // clamped data column
+        const unsigned vo = (unsigned)((kb * n1 + jcc) * sizeof(T));
+        const unsigned va = (unsigned)((kb * LDP + r0 + arow) * sizeof(T)), vc = (unsigned)((kb * LDP + jc) * sizeof(T));
+        constexpr unsigned kstep = 4 * LDP * sizeof(T);  // bytes between contraction steps of a matrix
+        T a[NKS], b[NP][NKS];
+        Acc q[NP];
 #pragma unroll
-    for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NP; ++p) q[p] = MM::zero();
+        // Q = T2 X for every plane of the block: the loads of step s (T2 and the
+        // data) are issued DL steps ahead of the products of step s, in an order
+        // pinned by scheduling barriers, so the loads in flight stay under the
+        // 6-bit load counter and a product waits for its own step only; once step
+        // s of T2 is used, its register takes step s of T1 for the second product.
 #pragma unroll
-        for (int v = 0; v < 4; ++v) sQ[p][G<PREC>::drow(kb, v) * LDQ + jc] = q[p][v];
-    lds_sync();                                      // (the second matrix stays in flight)
-    // out = Q T1^T, Q rows from LDS into the plane's dead data registers
+        for (int s = 0; s < NKS + DL; ++s) {
+            __builtin_amdgcn_sched_barrier(0);
+            if (s < NKS) {
+                a[s] = buf_load<T>(r2, va, s * kstep);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        if (z0 + p < n3) {                               // uniform over the block
-            T(&aq)[NKS] = b[p];
+                for (int p = 0; p < NP; ++p) {
+                    const int zp = min(z0 + p, n3 - 1);     // (a plane past the end is not stored)
+                    if (4 * s + 3 < n2)                      // whole step inside the plane
+                        b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
+                    else if (s < ks2)                        // last step: rows clamped
+                        b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
+                                              (unsigned)(zp * psz * sizeof(T)));
+                    else
+                        b[p][s] = T(0);                      // step skipped
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (s >= DL) {
+                const int m = s - DL;
+                if (m < ks2) {
 #pragma unroll
-            for (int s = 0; s < NKS; ++s) aq[s] = sQ[p][cl * LDQ + 4 * s + kb];
-            Acc r = Acc{0, 0, 0, 0};
+                    for (int p = 0; p < NP; ++p) q[p] = MM::mma(a[m], b[p][m], q[p]);
+                }
+                a[m] = buf_load<T>(r1, vc, m * kstep);
+            }
+        }
+        // Q rows and column of this lane's results
+        const int qrow = rr ? kb : 4 * (cl >> 2) + kb;   // (four-block product)
 #pragma unroll
-            for (int s = 0; s < NKS; ++s)
-                if (s < ks1) r = mma_step<PREC>(aq[s], a[s], r);
-            if (jc < n1) {
+        for (int p = 0; p < NP; ++p) {
+            if constexpr (SMALL) {
+                sQ[p][qrow * LDQ + jc] = q[p];
+            } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i2 = r0 + G<PREC>::drow(kb, v);
-                    if (i2 < n2) out[(size_t)(z0 + p) * psz + (size_t)i2 * n1 + jc] = r[v];
+                for (int v = 0; v < 4; ++v) sQ[p][G<PREC>::drow(kb, v) * LDQ + jc] = q[p][v];
+            }
+        }
+        lds_sync();                                      // (the second matrix stays in flight)
+        // out = Q T1^T, Q rows from LDS into the plane's dead data registers
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            if (z0 + p < n3) {                           // uniform over the block
+                T(&aq)[NKS] = b[p];
+#pragma unroll
+                for (int s = 0; s < NKS; ++s) aq[s] = sQ[p][arow * LDQ + 4 * s + kb];
+                Acc r = MM::zero();
+#pragma unroll
+                for (int s = 0; s < NKS; ++s)
+                    if (s < ks1) r = MM::mma(aq[s], a[s], r);
+                if (jc < n1) {
+                    T* op = out + (size_t)(z0 + p) * psz + jc;
+                    if constexpr (SMALL) {
+                        if (r0 + qrow < n2) op[(size_t)(r0 + qrow) * n1] = r;
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i2 = r0 + G<PREC>::drow(kb, v);
+                            if (i2 < n2) op[(size_t)i2 * n1] = r[v];
+                        }
+                    }
                 }
             }
         }
+    };
+    if constexpr (PREC == 1) {
+        if (rr || rc)
+            body(std::true_type{});
+        else
+            body(std::false_type{});
+    } else {
+        body(std::false_type{});
     }
 }
 
@@ -282,101 +340,126 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
                                                      const double* __restrict__ l1, const double* __restrict__ l2,
                                                      const double* __restrict__ l3, int n1, int n2, int n3) {
     using T = typename G<PREC>::T;
-    using Acc = typename G<PREC>::Acc;
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;
     constexpr int DL = 10;
     __shared__ T sY[NP][16 * KB * FLD];
-    const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
-    const int C = n1 * n2;
-    const int i3r = 16 * t + cl;                         // row of T3 (A operand)
-    const int ks3 = (n3 + 3) >> 2;
-    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), rf = buf_rsrc(T3ft), rb = buf_rsrc(T3bt);
-    const unsigned va = (unsigned)((kb * LDP + i3r) * sizeof(T));
-    constexpr unsigned kstep = 4 * LDP * sizeof(T);
-    T a[NKS], b[NP][NKS];
-    Acc y[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) y[p] = Acc{0, 0, 0, 0};
-    // eigenvalue sums of the scaling, loaded first (the loop's scheduling
-    // barriers keep later loads behind it)
-    double l12[NP], l3v[4];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int g = (blockIdx.x * NP + p) * 16 + cl;
-        l12[p] = 0.0;
-        if (g < C) {
-            const int i2 = g / n1, i1 = g - i2 * n1;
-            l12[p] = l1[i1] + l2[i2];
-        }
+    const int tl = (n3 - 1) >> 4;                        // last wave with rows inside the array
+    if (t > tl) {                                        // no row of this wave is used
+        lds_sync();
+        return;
     }
+    // a row block with at most 4 rows inside the array runs on the four-block
+    // product (FP64): lanes hold row 16 t + kb, column cl.  Not for KB = 7: there
+    // the kernel with both bodies needs one wave per SIMD fewer (130 VGPRs
+    // against 125) and measured slower.
+    const bool rs = PREC == 1 && KB != 7 && t == tl && n3 - 16 * tl <= 4;
+    auto body = [&](auto small_tag) {
+        constexpr bool SMALL = decltype(small_tag)::value;
+        using MM = WaveMM<PREC, SMALL>;
+        using Acc = typename MM::Acc;
+        constexpr int NV = SMALL ? 1 : 4;                // results per lane
+        const int C = n1 * n2;
+        const int i3r = 16 * t + (SMALL ? (cl & 3) : cl);   // row of T3 (A operand)
+        const int ks3 = (n3 + 3) >> 2;
+        const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), rf = buf_rsrc(T3ft), rb = buf_rsrc(T3bt);
+        const unsigned va = (unsigned)((kb * LDP + i3r) * sizeof(T));
+        constexpr unsigned kstep = 4 * LDP * sizeof(T);
+        auto row_of = [&](int v) { return 16 * t + (SMALL ? kb : G<PREC>::drow(kb, v)); };
+        auto get = [](const Acc& c, int v) -> T {
+            if constexpr (SMALL) return c; else return c[v];
+        };
+        T a[NKS], b[NP][NKS];
+        Acc y[NP];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int i3 = 16 * t + G<PREC>::drow(kb, v);
-        l3v[v] = i3 < n3 ? l3[i3] : 1.0;
-    }
-    // forward products of every column block, pipelined as in the xy pass; step
-    // s of T3f's register takes step s of T3b once used.  Every read of `in` by
-    // this block (all its column blocks) precedes its first write: in may be out.
+        for (int p = 0; p < NP; ++p) y[p] = MM::zero();
+        // eigenvalue sums of the scaling, loaded first (the loop's scheduling
+        // barriers keep later loads behind it)
+        double l12[NP], l3v[NV];
 #pragma unroll
-    for (int s = 0; s < NKS + DL; ++s) {                 // contraction index j3 = 4 s + kb
-        __builtin_amdgcn_sched_barrier(0);
-        if (s < NKS) {
-            a[s] = buf_load<T>(rf, va, s * kstep);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
-                const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
-                if (4 * s + 3 < n3)                      // whole step inside the array
-                    b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
-                else if (s < ks3)                        // last step: rows clamped
-                    b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
-                else
-                    b[p][s] = T(0);                      // step skipped
-            }
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        if (s >= DL) {
-            const int m = s - DL;
-            if (m < ks3) {
-#pragma unroll
-                for (int p = 0; p < NP; ++p) y[p] = mma_step<PREC>(a[m], b[p][m], y[p]);
-            }
-            a[m] = buf_load<T>(rb, va, m * kstep);
-        }
-    }
-    // scaling by the eigenvalue sums, Y through LDS
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const bool gin = (blockIdx.x * NP + p) * 16 + cl < C;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i3 = 16 * t + G<PREC>::drow(kb, v);
-            sY[p][i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)y[p][v] / (l12[p] + l3v[v])) : T(0);
-        }
-    }
-    lds_sync();                                      // (the second matrix stays in flight)
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int gb = (blockIdx.x * NP + p) * 16;
-        if (gb < C) {                                    // uniform over the block
-            const int g = gb + cl;
-            T(&by)[NKS] = b[p];                          // the block's data is dead: its registers take Y
-#pragma unroll
-            for (int s = 0; s < NKS; ++s) by[s] = sY[p][(4 * s + kb) * FLD + cl];
-            Acc z = Acc{0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < NKS; ++s)
-                if (s < ks3) z = mma_step<PREC>(a[s], by[s], z);
+        for (int p = 0; p < NP; ++p) {
+            const int g = (blockIdx.x * NP + p) * 16 + cl;
+            l12[p] = 0.0;
             if (g < C) {
+                const int i2 = g / n1, i1 = g - i2 * n1;
+                l12[p] = l1[i1] + l2[i2];
+            }
+        }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i3 = 16 * t + G<PREC>::drow(kb, v);
-                    if (i3 < n3) out[(size_t)i3 * C + g] = z[v];
+        for (int v = 0; v < NV; ++v) l3v[v] = row_of(v) < n3 ? l3[row_of(v)] : 1.0;
+        // forward products of every column block, pipelined as in the xy pass;
+        // step s of T3f's register takes step s of T3b once used.  Every read of
+        // `in` by this block (all its column blocks) precedes its first write: in
+        // may be out.
+#pragma unroll
+        for (int s = 0; s < NKS + DL; ++s) {             // contraction index j3 = 4 s + kb
+            __builtin_amdgcn_sched_barrier(0);
+            if (s < NKS) {
+                a[s] = buf_load<T>(rf, va, s * kstep);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
+                    const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
+                    if (4 * s + 3 < n3)                      // whole step inside the array
+                        b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
+                    else if (s < ks3)                        // last step: rows clamped
+                        b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
+                    else
+                        b[p][s] = T(0);                      // step skipped
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (s >= DL) {
+                const int m = s - DL;
+                if (m < ks3) {
+#pragma unroll
+                    for (int p = 0; p < NP; ++p) y[p] = MM::mma(a[m], b[p][m], y[p]);
+                }
+                a[m] = buf_load<T>(rb, va, m * kstep);
+            }
+        }
+        // scaling by the eigenvalue sums, Y through LDS
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const bool gin = (blockIdx.x * NP + p) * 16 + cl < C;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const int i3 = row_of(v);
+                sY[p][i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)get(y[p], v) / (l12[p] + l3v[v])) : T(0);
+            }
+        }
+        lds_sync();                                      // (the second matrix stays in flight)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const int gb = (blockIdx.x * NP + p) * 16;
+            if (gb < C) {                                // uniform over the block
+                const int g = gb + cl;
+                T(&by)[NKS] = b[p];                      // the block's data is dead: its registers take Y
+#pragma unroll
+                for (int s = 0; s < NKS; ++s) by[s] = sY[p][(4 * s + kb) * FLD + cl];
+                Acc z = MM::zero();
+#pragma unroll
+                for (int s = 0; s < NKS; ++s)
+                    if (s < ks3) z = MM::mma(a[s], by[s], z);
+                if (g < C) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const int i3 = row_of(v);
+                        if (i3 < n3) out[(size_t)i3 * C + g] = get(z, v);
+                    }
                 }
             }
         }
+    };
+    if constexpr (PREC == 1) {
+        if (rs)
+            body(std::true_type{});
+        else
+            body(std::false_type{});
+    } else {
+        body(std::false_type{});
     }
 }
 
