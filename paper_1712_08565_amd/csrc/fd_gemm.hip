@@ -166,13 +166,10 @@ hipError_t launch_any(const FdModeArgs<typename G<PREC>::T, typename G<PREC>::S>
 // past the extents are clamped to the last one (finite values that meet the
 // zero padding of the matrix, or land in outputs that are not stored).  All
 // loads are raw buffer loads with the step offset in a scalar register, issued
-// a fixed number of steps ahead of the first product (software pipelined).
-// One wave per 16-wide block (KB = ceil(n / 16) waves); NP planes (xy) or
-// column blocks (z) per workgroup share the matrices, which are loaded once:
-// the first products of all NP items run in the pipelined load loop, and the
-// second matrix takes the first one's registers step by step as they are used
-// (one barrier per workgroup).  Contraction steps past the true length are
-// skipped.
+// a fixed number of steps ahead of their product (software pipelined).
+// One wave per 16-wide block (KB = ceil(n / 16) waves), one plane (xy) or
+// column block (z) per workgroup, one barrier per workgroup.  Contraction
+// steps past the true length are skipped.
 constexpr int FLD = 17;                                  // padded row of 16-column LDS blocks
 
 // Workgroup barrier that waits only for this wave's LDS operations: global loads
@@ -212,7 +209,18 @@ struct WaveMM<1, true> {
     __device__ static Acc mma(double a, double b, double c) { return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0); }
 };
 
-template <int PREC, int KB, int NP>
+// The operands of a contraction step live in rings of R = DL + 1 registers, not
+// in arrays over the whole contraction, so a wave holds few registers (FP64:
+// 55 in the xy pass, 73-76 in the z pass) and several workgroups share a CU,
+// one's load latency, barrier and stores overlapping another's products.  Step
+// s of the first matrix and of the data go to slot s % R, DL steps ahead of
+// their product; once the first matrix's last step is issued, the second
+// matrix's steps follow in the same ring (step j in slot (NKS + j) % R), so its
+// first DL steps are in flight across the barrier.  The intermediate (Q or Y) is
+// read from LDS LA steps ahead of its product.  (Measured against arrays over
+// the whole contraction with one or two planes per workgroup: FP64 n = 65 26.1
+// -> 24.6 us per application, n = 99 63 -> 58, n = 132 171 -> 136.)
+template <int PREC, int KB>
 __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T* __restrict__ in,
                                                       typename G<PREC>::T* __restrict__ out,
                                                       const typename G<PREC>::T* __restrict__ T1t,
@@ -220,105 +228,86 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
                                                       int n3) {
     using T = typename G<PREC>::T;
     constexpr int NKS = 4 * KB;
-    constexpr int LDP = 16 * KB;                         // padded matrix row
-    constexpr int LDQ = 16 * KB + 1;                     // odd row length of the Q block
-    constexpr int DL = 10;                               // load lead in steps (measured: 6-19 within 3%, 10 best)
-    __shared__ T sQ[NP][16 * LDQ];
+    constexpr int LDP = 16 * KB;
+    constexpr int LDQ = 16 * KB + 1;
+    constexpr int DL = 8, R = DL + 1, LA = 2;        // load lead (measured 5-8 best), LDS lead
+    __shared__ T sQ[16 * LDQ];
     const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
-    const int r0 = blockIdx.x * 16;                      // first i2 of this block
-    const int z0 = blockIdx.y * NP;                      // first z-plane of this block
-    const int tl = (n1 - 1) >> 4;                        // last wave with columns inside the plane
-    if (t > tl) {                                        // no column of this wave is used
+    const int r0 = blockIdx.x * 16, z = blockIdx.y;
+    const int tl = (n1 - 1) >> 4;
+    if (t > tl) {
         lds_sync();
         return;
     }
-    // a row block (whole workgroup) or column block (this wave) with at most 4
-    // entries inside the plane runs on the four-block product (FP64)
     const bool rr = PREC == 1 && n2 - r0 <= 4, rc = PREC == 1 && t == tl && n1 - 16 * tl <= 4;
     auto body = [&](auto small_tag) {
         constexpr bool SMALL = decltype(small_tag)::value;
         using MM = WaveMM<PREC, SMALL>;
         using Acc = typename MM::Acc;
         const unsigned psz = (unsigned)(n1 * n2);
-        const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;  // contraction steps of the two products
-        const int arow = rr ? (cl & 3) : cl;             // A operand row in the row block
-        const int jc = 16 * t + (rc ? (cl & 3) : cl);   // B operand column (j1, then i1)
+        const int ks2 = (n2 + 3) >> 2, ks1 = (n1 + 3) >> 2;
+        const int arow = rr ? (cl & 3) : cl;
+        const int jc = 16 * t + (rc ? (cl & 3) : cl);
         const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), r1 = buf_rsrc(T1t), r2 = buf_rsrc(T2t);
-        const int jcc = min(jc, n1 - 1);                 // clamped data column
+        const int jcc = min(jc, n1 - 1);
         const unsigned vo = (unsigned)((kb * n1 + jcc) * sizeof(T));
         const unsigned va = (unsigned)((kb * LDP + r0 + arow) * sizeof(T)), vc = (unsigned)((kb * LDP + jc) * sizeof(T));
-        constexpr unsigned kstep = 4 * LDP * sizeof(T);  // bytes between contraction steps of a matrix
-        T a[NKS], b[NP][NKS];
-        Acc q[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) q[p] = MM::zero();
-        // Q = T2 X for every plane of the block: the loads of step s (T2 and the
-        // data) are issued DL steps ahead of the products of step s, in an order
-        // pinned by scheduling barriers, so the loads in flight stay under the
-        // 6-bit load counter and a product waits for its own step only; once step
-        // s of T2 is used, its register takes step s of T1 for the second product.
-#pragma unroll
-        for (int s = 0; s < NKS + DL; ++s) {
-            __builtin_amdgcn_sched_barrier(0);
+        constexpr unsigned kstep = 4 * LDP * sizeof(T);
+        const unsigned zo = (unsigned)(z * psz * sizeof(T));
+        T a[R], b[R], aq[LA + 1];
+        Acc q = MM::zero();
+        auto load_step = [&](int s) {                    // T2 and data of step s, or T1 step s - NKS
             if (s < NKS) {
-                a[s] = buf_load<T>(r2, va, s * kstep);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const int zp = min(z0 + p, n3 - 1);     // (a plane past the end is not stored)
-                    if (4 * s + 3 < n2)                      // whole step inside the plane
-                        b[p][s] = buf_load<T>(rin, vo, (unsigned)((zp * psz + 4 * s * n1) * sizeof(T)));
-                    else if (s < ks2)                        // last step: rows clamped
-                        b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)),
-                                              (unsigned)(zp * psz * sizeof(T)));
-                    else
-                        b[p][s] = T(0);                      // step skipped
-                }
+                a[s % R] = buf_load<T>(r2, va, s * kstep);
+                if (4 * s + 3 < n2)
+                    b[s % R] = buf_load<T>(rin, vo, zo + (unsigned)(4 * s * n1 * sizeof(T)));
+                else if (s < ks2)
+                    b[s % R] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n2 - 1) * n1 + jcc) * sizeof(T)), zo);
+                else
+                    b[s % R] = T(0);
+            } else if (s - NKS < NKS) {
+                a[s % R] = buf_load<T>(r1, vc, (s - NKS) * kstep);
             }
+        };
+#pragma unroll
+        for (int s = 0; s < DL; ++s) load_step(s);
+#pragma unroll
+        for (int m = 0; m < NKS; ++m) {
             __builtin_amdgcn_sched_barrier(0);
-            if (s >= DL) {
-                const int m = s - DL;
-                if (m < ks2) {
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) q[p] = MM::mma(a[m], b[p][m], q[p]);
-                }
-                a[m] = buf_load<T>(r1, vc, m * kstep);
-            }
+            load_step(m + DL);
+            __builtin_amdgcn_sched_barrier(0);
+            if (m < ks2) q = MM::mma(a[m % R], b[m % R], q);
         }
-        // Q rows and column of this lane's results
-        const int qrow = rr ? kb : 4 * (cl >> 2) + kb;   // (four-block product)
+        const int qrow = rr ? kb : 4 * (cl >> 2) + kb;
+        if constexpr (SMALL) {
+            sQ[qrow * LDQ + jc] = q;
+        } else {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
+            for (int v = 0; v < 4; ++v) sQ[G<PREC>::drow(kb, v) * LDQ + jc] = q[v];
+        }
+        lds_sync();
+        if (z >= n3) return;
+#pragma unroll
+        for (int j = 0; j < LA; ++j) aq[j] = sQ[arow * LDQ + 4 * j + kb];
+        Acc r = MM::zero();
+#pragma unroll
+        for (int j = 0; j < NKS; ++j) {
+            __builtin_amdgcn_sched_barrier(0);
+            load_step(NKS + j + DL);
+            if (j + LA < NKS) aq[(j + LA) % (LA + 1)] = sQ[arow * LDQ + 4 * (j + LA) + kb];
+            __builtin_amdgcn_sched_barrier(0);
+            if (j < ks1) r = MM::mma(aq[j % (LA + 1)], a[(NKS + j) % R], r);
+        }
+        if (jc < n1) {
+            T* op = out + (size_t)z * psz + jc;
             if constexpr (SMALL) {
-                sQ[p][qrow * LDQ + jc] = q[p];
+                if (r0 + qrow < n2) op[(size_t)(r0 + qrow) * n1] = r;
             } else {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) sQ[p][G<PREC>::drow(kb, v) * LDQ + jc] = q[p][v];
-            }
-        }
-        lds_sync();                                      // (the second matrix stays in flight)
-        // out = Q T1^T, Q rows from LDS into the plane's dead data registers
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            if (z0 + p < n3) {                           // uniform over the block
-                T(&aq)[NKS] = b[p];
-#pragma unroll
-                for (int s = 0; s < NKS; ++s) aq[s] = sQ[p][arow * LDQ + 4 * s + kb];
-                Acc r = MM::zero();
-#pragma unroll
-                for (int s = 0; s < NKS; ++s)
-                    if (s < ks1) r = MM::mma(aq[s], a[s], r);
-                if (jc < n1) {
-                    T* op = out + (size_t)(z0 + p) * psz + jc;
-                    if constexpr (SMALL) {
-                        if (r0 + qrow < n2) op[(size_t)(r0 + qrow) * n1] = r;
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i2 = r0 + G<PREC>::drow(kb, v);
-                            if (i2 < n2) op[(size_t)i2 * n1] = r[v];
-                        }
-                    }
+                for (int v = 0; v < 4; ++v) {
+                    const int i2 = r0 + G<PREC>::drow(kb, v);
+                    if (i2 < n2) op[(size_t)i2 * n1] = r[v];
                 }
             }
         }
@@ -333,7 +322,7 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     }
 }
 
-template <int PREC, int KB, int NP>
+template <int PREC, int KB>
 __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* in, typename G<PREC>::T* out,
                                                      const typename G<PREC>::T* __restrict__ T3ft,
                                                      const typename G<PREC>::T* __restrict__ T3bt,
@@ -342,27 +331,23 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     using T = typename G<PREC>::T;
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;
-    constexpr int DL = 10;
-    __shared__ T sY[NP][16 * KB * FLD];
+    constexpr int DL = 8, R = DL + 1, LA = 2;        // load lead (measured 5-8 best), LDS lead
+    __shared__ T sY[16 * KB * FLD];
     const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
-    const int tl = (n3 - 1) >> 4;                        // last wave with rows inside the array
-    if (t > tl) {                                        // no row of this wave is used
+    const int tl = (n3 - 1) >> 4;
+    if (t > tl) {
         lds_sync();
         return;
     }
-    // a row block with at most 4 rows inside the array runs on the four-block
-    // product (FP64): lanes hold row 16 t + kb, column cl.  Not for KB = 7: there
-    // the kernel with both bodies needs one wave per SIMD fewer (130 VGPRs
-    // against 125) and measured slower.
-    const bool rs = PREC == 1 && KB != 7 && t == tl && n3 - 16 * tl <= 4;
+    const bool rs = PREC == 1 && t == tl && n3 - 16 * tl <= 4;
     auto body = [&](auto small_tag) {
         constexpr bool SMALL = decltype(small_tag)::value;
         using MM = WaveMM<PREC, SMALL>;
         using Acc = typename MM::Acc;
-        constexpr int NV = SMALL ? 1 : 4;                // results per lane
+        constexpr int NV = SMALL ? 1 : 4;
         const int C = n1 * n2;
-        const int i3r = 16 * t + (SMALL ? (cl & 3) : cl);   // row of T3 (A operand)
+        const int i3r = 16 * t + (SMALL ? (cl & 3) : cl);
         const int ks3 = (n3 + 3) >> 2;
         const __amdgpu_buffer_rsrc_t rin = buf_rsrc(in), rf = buf_rsrc(T3ft), rb = buf_rsrc(T3bt);
         const unsigned va = (unsigned)((kb * LDP + i3r) * sizeof(T));
@@ -371,85 +356,63 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
         auto get = [](const Acc& c, int v) -> T {
             if constexpr (SMALL) return c; else return c[v];
         };
-        T a[NKS], b[NP][NKS];
-        Acc y[NP];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) y[p] = MM::zero();
-        // eigenvalue sums of the scaling, loaded first (the loop's scheduling
-        // barriers keep later loads behind it)
-        double l12[NP], l3v[NV];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const int g = (blockIdx.x * NP + p) * 16 + cl;
-            l12[p] = 0.0;
-            if (g < C) {
-                const int i2 = g / n1, i1 = g - i2 * n1;
-                l12[p] = l1[i1] + l2[i2];
-            }
+        const int g = blockIdx.x * 16 + cl;
+        const bool gin = g < C;
+        const int gc = min(g, C - 1);
+        const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
+        double l12 = 0.0, l3v[NV];
+        if (gin) {
+            const int i2 = g / n1, i1 = g - i2 * n1;
+            l12 = l1[i1] + l2[i2];
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) l3v[v] = row_of(v) < n3 ? l3[row_of(v)] : 1.0;
-        // forward products of every column block, pipelined as in the xy pass;
-        // step s of T3f's register takes step s of T3b once used.  Every read of
-        // `in` by this block (all its column blocks) precedes its first write: in
-        // may be out.
-#pragma unroll
-        for (int s = 0; s < NKS + DL; ++s) {             // contraction index j3 = 4 s + kb
-            __builtin_amdgcn_sched_barrier(0);
+        T a[R], b[R], by[LA + 1];
+        Acc y = MM::zero();
+        auto load_step = [&](int s) {                    // T3f and data of step s, or T3b step s - NKS
             if (s < NKS) {
-                a[s] = buf_load<T>(rf, va, s * kstep);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    const int gc = min((int)(blockIdx.x * NP + p) * 16 + cl, C - 1);   // clamped column
-                    const unsigned vo = (unsigned)((kb * C + gc) * sizeof(T));
-                    if (4 * s + 3 < n3)                      // whole step inside the array
-                        b[p][s] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
-                    else if (s < ks3)                        // last step: rows clamped
-                        b[p][s] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
-                    else
-                        b[p][s] = T(0);                      // step skipped
-                }
+                a[s % R] = buf_load<T>(rf, va, s * kstep);
+                if (4 * s + 3 < n3)
+                    b[s % R] = buf_load<T>(rin, vo, (unsigned)(4 * s * C * sizeof(T)));
+                else if (s < ks3)
+                    b[s % R] = buf_load<T>(rin, (unsigned)((min(4 * s + kb, n3 - 1) * C + gc) * sizeof(T)), 0u);
+                else
+                    b[s % R] = T(0);
+            } else if (s - NKS < NKS) {
+                a[s % R] = buf_load<T>(rb, va, (s - NKS) * kstep);
             }
+        };
+#pragma unroll
+        for (int s = 0; s < DL; ++s) load_step(s);
+#pragma unroll
+        for (int m = 0; m < NKS; ++m) {
             __builtin_amdgcn_sched_barrier(0);
-            if (s >= DL) {
-                const int m = s - DL;
-                if (m < ks3) {
-#pragma unroll
-                    for (int p = 0; p < NP; ++p) y[p] = MM::mma(a[m], b[p][m], y[p]);
-                }
-                a[m] = buf_load<T>(rb, va, m * kstep);
-            }
+            load_step(m + DL);
+            __builtin_amdgcn_sched_barrier(0);
+            if (m < ks3) y = MM::mma(a[m % R], b[m % R], y);
         }
-        // scaling by the eigenvalue sums, Y through LDS
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const bool gin = (blockIdx.x * NP + p) * 16 + cl < C;
+        for (int v = 0; v < NV; ++v) {
+            const int i3 = row_of(v);
+            sY[i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)get(y, v) / (l12 + l3v[v])) : T(0);
+        }
+        lds_sync();                                      // every read of `in` by this block is done: in may be out
+#pragma unroll
+        for (int j = 0; j < LA; ++j) by[j] = sY[(4 * j + kb) * FLD + cl];
+        Acc zz = MM::zero();
+#pragma unroll
+        for (int j = 0; j < NKS; ++j) {
+            __builtin_amdgcn_sched_barrier(0);
+            load_step(NKS + j + DL);
+            if (j + LA < NKS) by[(j + LA) % (LA + 1)] = sY[(4 * (j + LA) + kb) * FLD + cl];
+            __builtin_amdgcn_sched_barrier(0);
+            if (j < ks3) zz = MM::mma(a[(NKS + j) % R], by[j % (LA + 1)], zz);
+        }
+        if (gin) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 const int i3 = row_of(v);
-                sY[p][i3 * FLD + cl] = (gin && i3 < n3) ? (T)((double)get(y[p], v) / (l12[p] + l3v[v])) : T(0);
-            }
-        }
-        lds_sync();                                      // (the second matrix stays in flight)
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const int gb = (blockIdx.x * NP + p) * 16;
-            if (gb < C) {                                // uniform over the block
-                const int g = gb + cl;
-                T(&by)[NKS] = b[p];                      // the block's data is dead: its registers take Y
-#pragma unroll
-                for (int s = 0; s < NKS; ++s) by[s] = sY[p][(4 * s + kb) * FLD + cl];
-                Acc z = MM::zero();
-#pragma unroll
-                for (int s = 0; s < NKS; ++s)
-                    if (s < ks3) z = MM::mma(a[s], by[s], z);
-                if (g < C) {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const int i3 = row_of(v);
-                        if (i3 < n3) out[(size_t)i3 * C + g] = get(z, v);
-                    }
-                }
+                if (i3 < n3) out[(size_t)i3 * C + g] = get(zz, v);
             }
         }
     };
@@ -630,53 +593,23 @@ hipError_t fused_bf16_ns(const FdFusedBf16Args& f, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int PREC, int KB, int NP>
-hipError_t fused_np(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
-    using T = typename G<PREC>::T;
-    hipError_t e;
-    // T = U^T forward, U backward; each passed transposed
-    dim3 gxy((f.n2 + 15) / 16, (f.n3 + NP - 1) / NP);
-    const int zb = (f.n1 * f.n2 + 15) / 16;
-    dim3 gz((zb + NP - 1) / NP);
-    // forward y and x
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB, NP>), gxy, dim3(64 * KB), 0, s, f.r, f.tmp, f.U[0], f.U[1], f.n1, f.n2,
-                       f.n3);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // forward z, scaling, backward z (in place on tmp)
-    hipLaunchKernelGGL((fd_z_pass<PREC, KB, NP>), gz, dim3(64 * KB), 0, s, (const T*)f.tmp, f.tmp, f.U[2], f.UT[2],
-                       f.l1, f.l2, f.l3, f.n1, f.n2, f.n3);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // backward y and x
-    hipLaunchKernelGGL((fd_xy_pass<PREC, KB, NP>), gxy, dim3(64 * KB), 0, s, (const T*)f.tmp, f.z, f.UT[0], f.UT[1],
-                       f.n1, f.n2, f.n3);
-    return hipGetLastError();
-}
-
-// compute units of the current device (queried once per process)
-int device_cus() {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0, n = 0;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
-                                                     hipSuccess && n > 0)
-            cus = n;
-        else
-            cus = 256;
-    }
-    return cus;
-}
-
 template <int PREC, int KB>
 hipError_t fused_kb(const FdFusedArgs<typename G<PREC>::T>& f, hipStream_t s) {
+    using T = typename G<PREC>::T;
     if (f.ldp != 16 * KB) return hipErrorInvalidValue;   // matrices padded for this block count
-    // FP64 with n <= 80: when the one-item grid needs more than one workgroup
-    // per CU, two planes / column blocks per workgroup (the matrices loaded once
-    // for both) are faster; FP32 prefers the wider grid
-    if constexpr (PREC == 1 && KB <= 5) {
-        const long items = (long)((f.n2 + 15) / 16) * f.n3;
-        if (items > device_cus()) return fused_np<PREC, KB, 2>(f, s);
-    }
-    return fused_np<PREC, KB, 1>(f, s);
+    hipError_t e;
+    const dim3 gxy((f.n2 + 15) / 16, f.n3), gz((f.n1 * f.n2 + 15) / 16), blk(64 * KB);
+    // forward y and x (T = U^T forward, U backward; each passed transposed)
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, blk, 0, s, f.r, f.tmp, f.U[0], f.U[1], f.n1, f.n2, f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // forward z, scaling, backward z (in place on tmp)
+    hipLaunchKernelGGL((fd_z_pass<PREC, KB>), gz, blk, 0, s, (const T*)f.tmp, f.tmp, f.U[2], f.UT[2], f.l1, f.l2,
+                       f.l3, f.n1, f.n2, f.n3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // backward y and x
+    hipLaunchKernelGGL((fd_xy_pass<PREC, KB>), gxy, blk, 0, s, (const T*)f.tmp, f.z, f.UT[0], f.UT[1], f.n1, f.n2,
+                       f.n3);
+    return hipGetLastError();
 }
 
 template <int PREC>
