@@ -18,11 +18,12 @@ pytestmark = pytest.mark.gpu
 
 # the five after "nu" have extents a few DOFs past a multiple of 16 (a mostly
 # empty last 16-block in every direction, as on the benchmark rings), M = 4..8;
-# the last two have at most 4 DOFs in two or three directions (every block of
-# those directions on the four-block 4 x 4 x 4 product)
+# the last two have 4 DOFs (3 elements, the fewest fd_setup takes) in two or
+# three directions (every block of those directions on the four-block 4 x 4 x 4
+# product)
 @pytest.mark.parametrize("els", [(5, 19, 40), (40, 19, 5), (70, 13, 30), (13, 97, 9), (9, 130, 17), "nu",
                                  (64, 66, 63), (80, 83, 82), (97, 96, 99), (113, 115, 112), (128, 131, 130),
-                                 (2, 2, 3), (3, 14, 2)])
+                                 (3, 3, 3), (3, 14, 3)])
 def test_fd_parity_box(els):
     import torch
     from paper_1712_08565_amd import wqfd
