@@ -108,10 +108,15 @@ __global__ __launch_bounds__(kT) void sum_partial(const double* __restrict__ x, 
     if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-// single block: sum the partials of K dots and update the scalar block
+// single block: sum the partials of K dots and update the scalar block; with
+// hsc (coherent pinned host memory, its device address) the block is also
+// written there and then, once those stores have completed, the marker `mark`
+// into hsc[kMark]: the host waits for the marker instead of an event, with no
+// copy launch and no end-of-kernel cache write-back for a host wait
+constexpr int kMark = 15;
 template <int K>
 __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
-                                                int slot0, int op) {
+                                                int slot0, int op, double* __restrict__ hsc, double mark) {
     __shared__ double sh[kT / 64];
     double res[3] = {0, 0, 0};
     for (int k = 0; k < K; ++k) {
@@ -138,6 +143,11 @@ __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part,
             sc[S_RHO] = res[0];
             sc[S_RR] = res[1];
             break;
+    }
+    if (hsc) {
+        for (int k = 0; k < kSlots; ++k) hsc[k] = sc[k];
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the scalars' stores have completed
+        hsc[kMark] = mark;
     }
 }
 
@@ -313,12 +323,30 @@ thread_local int g_restarts = 0;                 // failed confirmations that re
 
 // thread-local pinned host block for the scalar read-back: slots 0-15 and
 // 16-31 alternate between iterations, 32-47 the confirmation, 48 the restart value
+// (coherent: the reduction kernel's stores to it are not held in the GPU's
+// caches, so they are visible to the host once the kernel has completed)
 double* host_scalars() {
     static thread_local double* h = nullptr;
     if (!h) {
-        if (hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) h = nullptr;
+        if (hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocCoherent) != hipSuccess) h = nullptr;
     }
     return h;
+}
+
+// Waits until the reduction kernel has written marker value `want` (the host
+// reads coherent pinned memory).  Now and then the stream is queried: an error
+// there, or the stream done without the marker, ends the wait with an error.
+hipError_t wait_marker(const double* mark, double want, hipStream_t s) {
+    const volatile double* m = mark;
+    for (unsigned k = 1;; ++k) {
+        if (*m == want) return hipSuccess;
+        if ((k & 255) == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) return q;
+            return *m == want ? hipSuccess : hipErrorUnknown;   // (stream done without the marker)
+        }
+    }
 }
 
 // thread-local event marking the end of an iteration's scalar read-back
@@ -401,7 +429,8 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     const int nb = nblocks(N);
     const dim3 g(nb), blk(kT);
     double* h = host_scalars();
-    if (!h) {
+    double* hdev = nullptr;                          // its device address
+    if (!h || hipHostGetDevicePointer((void**)&hdev, h, 0) != hipSuccess || !hdev) {
         err = "could not allocate pinned host memory";
         return WQ_EHIP_CODE;
     }
@@ -418,7 +447,7 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
         hipLaunchKernelGGL(copy2<T>, g, blk, 0, s, V.r, V.rh, (T*)nullptr, N);
     }
     hipLaunchKernelGGL((dot_partial<T, 3>), g, blk, 0, s, V.rh, V.r, V.r, V.r, b, b, N, V.part);
-    hipLaunchKernelGGL((dot_final<3>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_RHO, (int)F_STORE);
+    hipLaunchKernelGGL((dot_final<3>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_RHO, (int)F_STORE, nullptr, 0.0);
     // S_RHO = (r^, r), S_RHO_OLD = (r, r), S_ALPHA = (b, b): moved to their slots and the
     // recurrence's initial scalars set on the device, then one read-back
     hipLaunchKernelGGL(init_scalars, dim3(1), dim3(1), 0, s, V.sc);
@@ -477,17 +506,26 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     // two residuals, with a factor 4 margin) not to reach the tolerance, so that a
     // solve normally ends without a discarded half
     double rel1 = std::sqrt(rr0) / nbn, rel2 = 0.0;
+    // the iterations' scalars arrive in two alternating host slots, each with its
+    // iteration number as marker (cleared here: the slots are reused by every solve)
+    h[kMark] = h[16 + kMark] = -1.0;
     for (int it = 1; it <= maxit; ++it) {
         double* hb = h + 16 * (it & 1);             // the scalars of this iteration (two host slots)
         hipLaunchKernelGGL(upd_xr<T>, g, blk, 0, s, x, V.r, V.ph, V.sh, V.s, V.t, V.rh, V.sc, V.part, nb, N, V.part2);
-        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part2, nb, V.sc, 0, (int)F_RHO_RR);
+        // the reduction kernel writes the scalars to the pinned host block itself
+        hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part2, nb, V.sc, 0, (int)F_RHO_RR,
+                           hdev + 16 * (it & 1), (double)it);
         KR_TRY(hipGetLastError());
-        KR_TRY(hipMemcpyAsync(hb, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
-        KR_TRY(hipEventRecord(ev, s));
         const double q = rel2 > 0.0 ? std::min(1.0, rel1 / rel2) : 1.0;
         const bool spec = it < maxit && rel1 * q > 4.0 * tol;
         if (spec) KR_TRY(first_half(0));            // speculative: the next iteration's first half
-        KR_TRY(hipEventSynchronize(ev));
+        {
+            const hipError_t e = wait_marker(hb + kMark, (double)it, s);
+            if (e != hipSuccess) {
+                err = e == hipErrorUnknown ? "iteration scalars not received from the device" : hipGetErrorString(e);
+                return WQ_EHIP_CODE;
+            }
+        }
         *iters = it;
         const double rel = std::sqrt(hb[S_RR]) / nbn;
         *relres = rel;
@@ -505,7 +543,8 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
             hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.t, N);
             hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.t, V.rh, V.t, (const T*)nullptr,
                                (const T*)nullptr, N, V.part);
-            hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_AUX, (int)F_STORE);
+            hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_AUX, (int)F_STORE,
+                               nullptr, 0.0);
             double* hc = h + 32;
             KR_TRY(hipMemcpyAsync(hc, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
             KR_TRY(hipStreamSynchronize(s));
@@ -547,7 +586,7 @@ int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& er
     const int nb = nblocks(N);
     hipLaunchKernelGGL((dot_partial<double, 1>), dim3(nb), dim3(kT), 0, s, x, x, (const double*)nullptr,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, N, part);
-    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE);
+    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE, nullptr, 0.0);
     double* h = host_scalars();
     KR_TRY(hipMemcpyAsync(h, sc, sizeof(double), hipMemcpyDeviceToHost, s));
     KR_TRY(hipStreamSynchronize(s));
@@ -563,7 +602,7 @@ int sum_all(const double* x, size_t N, void* part_ws, double* out, std::string& 
     double* sc = part + 3 * kMaxBlocks;
     const int nb = nblocks(N);
     hipLaunchKernelGGL(sum_partial, dim3(nb), dim3(kT), 0, s, x, N, part);
-    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE);
+    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE, nullptr, 0.0);
     double h = 0.0;
     KR_TRY(hipMemcpyAsync(&h, sc, sizeof(double), hipMemcpyDeviceToHost, s));
     KR_TRY(hipStreamSynchronize(s));
