@@ -108,12 +108,19 @@ __global__ __launch_bounds__(kT) void sum_partial(const double* __restrict__ x, 
     if (threadIdx.x == 0) part[blockIdx.x] = r;
 }
 
-// single block: sum the partials of K dots and update the scalar block; with
-// hsc (coherent pinned host memory, its device address) the block is also
-// written there and then, once those stores have completed, the marker `mark`
+// The scalar block sc is also written to hsc (coherent pinned host memory, its
+// device address) and then, once those stores have completed, the marker `mark`
 // into hsc[kMark]: the host waits for the marker instead of an event, with no
-// copy launch and no end-of-kernel cache write-back for a host wait
+// copy launch and no end-of-kernel cache write-back for a host wait.
 constexpr int kMark = 15;
+__device__ inline void to_host(const double* sc, double* hsc, double mark) {
+    for (int k = 0; k < kSlots; ++k) hsc[k] = sc[k];
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the scalars' stores have completed
+    hsc[kMark] = mark;
+}
+
+// single block: sum the partials of K dots and update the scalar block (and,
+// with hsc, hand it to the host)
 template <int K>
 __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part, int nb, double* __restrict__ sc,
                                                 int slot0, int op, double* __restrict__ hsc, double mark) {
@@ -144,11 +151,7 @@ __global__ __launch_bounds__(kT) void dot_final(const double* __restrict__ part,
             sc[S_RR] = res[1];
             break;
     }
-    if (hsc) {
-        for (int k = 0; k < kSlots; ++k) hsc[k] = sc[k];
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // the scalars' stores have completed
-        hsc[kMark] = mark;
-    }
+    if (hsc) to_host(sc, hsc, mark);
 }
 
 // Sum of nb partials, identical in every block (same partition and order), so
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(kT) void upd_xr(T* __restrict__ x, T* __restrict__ 
 
 // Initial scalars of the recurrence from the first reduction (rho = (r^, r) in
 // S_RHO, (r, r) in S_RHO_OLD, (b, b) in S_ALPHA): rho_old = alpha = omega = 1.
-__global__ void init_scalars(double* sc) {
+__global__ void init_scalars(double* sc, double* hsc, double mark) {
     const double rr = sc[S_RHO_OLD], bb = sc[S_ALPHA];
     for (int k = 0; k < kSlots; ++k)
         if (k != S_RHO) sc[k] = 0.0;
@@ -285,6 +288,7 @@ __global__ void init_scalars(double* sc) {
     sc[S_OMEGA] = 1.0;
     sc[S_RR] = rr;
     sc[S_BB] = bb;
+    to_host(sc, hsc, mark);
 }
 
 // y = b - y (true residual) ; copy
@@ -321,16 +325,33 @@ __global__ __launch_bounds__(kT) void axpy_kernel(const D* __restrict__ d, doubl
 
 thread_local int g_restarts = 0;                 // failed confirmations that restarted (this thread)
 
-// thread-local pinned host block for the scalar read-back: slots 0-15 and
-// 16-31 alternate between iterations, 32-47 the confirmation, 48 the restart value
-// (coherent: the reduction kernel's stores to it are not held in the GPU's
-// caches, so they are visible to the host once the kernel has completed)
-double* host_scalars() {
+// Thread-local pinned host block for the scalar read-back, 16 doubles a slot:
+// slots 0 and 1 alternate between iterations (marker: the iteration), slot 2
+// the confirmation, slot 3 the restart value, slot 4 the initial scalars,
+// slot 5 norms (markers: a per-thread sequence number).  Coherent: the
+// reduction kernels' stores to it are not held in the GPU's caches, so they are
+// visible to the host once they have completed.  hdev: its device address.
+bool host_block(double** h_out, double** hdev_out) {
     static thread_local double* h = nullptr;
+    static thread_local double* hdev = nullptr;
     if (!h) {
-        if (hipHostMalloc((void**)&h, 64 * sizeof(double), hipHostMallocCoherent) != hipSuccess) h = nullptr;
+        double* p = nullptr;
+        double* d = nullptr;
+        if (hipHostMalloc((void**)&p, 96 * sizeof(double), hipHostMallocCoherent) != hipSuccess) return false;
+        if (hipHostGetDevicePointer((void**)&d, p, 0) != hipSuccess || !d) return false;
+        for (int i = 0; i < 96; ++i) p[i] = -1.0;
+        h = p;
+        hdev = d;
     }
-    return h;
+    *h_out = h;
+    *hdev_out = hdev;
+    return true;
+}
+
+// marker values of the one-off read-backs (distinct within a thread)
+double next_mark() {
+    static thread_local double m = 0.0;
+    return m += 1.0;
 }
 
 // Waits until the reduction kernel has written marker value `want` (the host
@@ -349,12 +370,6 @@ hipError_t wait_marker(const double* mark, double want, hipStream_t s) {
     }
 }
 
-// thread-local event marking the end of an iteration's scalar read-back
-hipEvent_t iteration_event() {
-    static thread_local hipEvent_t ev = nullptr;
-    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) ev = nullptr;
-    return ev;
-}
 
 #define KR_TRY(x)                                   \
     do {                                            \
@@ -428,12 +443,16 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     Vecs<T> V = carve<T>(ws, N);
     const int nb = nblocks(N);
     const dim3 g(nb), blk(kT);
-    double* h = host_scalars();
-    double* hdev = nullptr;                          // its device address
-    if (!h || hipHostGetDevicePointer((void**)&hdev, h, 0) != hipSuccess || !hdev) {
+    double *h = nullptr, *hdev = nullptr;
+    if (!host_block(&h, &hdev)) {
         err = "could not allocate pinned host memory";
         return WQ_EHIP_CODE;
     }
+    // a failed wait: the stream's error, or the stream done without the marker
+    auto wait_fail = [&](hipError_t e) {
+        err = e == hipErrorUnknown ? "scalars not received from the device" : hipGetErrorString(e);
+        return WQ_EHIP_CODE;
+    };
     *iters = 0;
     *relres = 0.0;
     // r = b - A x0 ; r^ = r ; scalars
@@ -450,11 +469,11 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     hipLaunchKernelGGL((dot_final<3>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_RHO, (int)F_STORE, nullptr, 0.0);
     // S_RHO = (r^, r), S_RHO_OLD = (r, r), S_ALPHA = (b, b): moved to their slots and the
     // recurrence's initial scalars set on the device, then one read-back
-    hipLaunchKernelGGL(init_scalars, dim3(1), dim3(1), 0, s, V.sc);
-    KR_TRY(hipMemcpyAsync(h, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
+    const double m0 = next_mark();
+    hipLaunchKernelGGL(init_scalars, dim3(1), dim3(1), 0, s, V.sc, hdev + 64, m0);
     // Each iteration is enqueued in two halves.  The first (p, p^ = M p, v = A p^,
     // alpha, s, s^ = M s, t = A s^, the partials of omega) touches neither x nor r;
-    // the second (omega, x and r, rho) ends with the scalars' copy to the host.
+    // the second (omega, x and r, rho) ends with the scalars handed to the host.
     // The next iteration's first half is enqueued before the host waits for the
     // current scalars (when the residual trend predicts that the current one does
     // not converge), so the device keeps working through the read-back.  If
@@ -479,15 +498,12 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
     // the first iteration's first half is enqueued before the host waits for the
     // initial scalars (it touches neither x nor r, so an early return leaves them as
     // they are)
-    hipEvent_t ev = iteration_event();
-    if (!ev) {
-        err = "could not create the iteration event";
-        return WQ_EHIP_CODE;
-    }
-    KR_TRY(hipEventRecord(ev, s));
     if (maxit >= 1) KR_TRY(first_half(1));
-    KR_TRY(hipEventSynchronize(ev));
-    const double bb = h[S_BB], rr0 = h[S_RR];
+    {
+        const hipError_t e = wait_marker(h + 64 + kMark, m0, s);
+        if (e != hipSuccess) return wait_fail(e);
+    }
+    const double bb = h[64 + S_BB], rr0 = h[64 + S_RR];
     if (!std::isfinite(bb) || !std::isfinite(rr0)) {
         err = "non-finite value in the right-hand side or initial residual";
         return -8;
@@ -521,10 +537,7 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
         if (spec) KR_TRY(first_half(0));            // speculative: the next iteration's first half
         {
             const hipError_t e = wait_marker(hb + kMark, (double)it, s);
-            if (e != hipSuccess) {
-                err = e == hipErrorUnknown ? "iteration scalars not received from the device" : hipGetErrorString(e);
-                return WQ_EHIP_CODE;
-            }
+            if (e != hipSuccess) return wait_fail(e);
         }
         *iters = it;
         const double rel = std::sqrt(hb[S_RR]) / nbn;
@@ -543,11 +556,16 @@ int bicgstab(const LinOp& A, const LinOp& M, size_t N, const T* b, T* x, bool x0
             hipLaunchKernelGGL(resid<T>, g, blk, 0, s, b, V.t, N);
             hipLaunchKernelGGL((dot_partial<T, 2>), g, blk, 0, s, V.t, V.t, V.rh, V.t, (const T*)nullptr,
                                (const T*)nullptr, N, V.part);
+            // (the marker comes last in stream order: all queued work, the speculative
+            // half included, is done once it is seen)
+            const double mc = next_mark();
             hipLaunchKernelGGL((dot_final<2>), dim3(1), blk, 0, s, V.part, nb, V.sc, (int)S_AUX, (int)F_STORE,
-                               nullptr, 0.0);
+                               hdev + 32, mc);
             double* hc = h + 32;
-            KR_TRY(hipMemcpyAsync(hc, V.sc, kSlots * sizeof(double), hipMemcpyDeviceToHost, s));
-            KR_TRY(hipStreamSynchronize(s));
+            {
+                const hipError_t e = wait_marker(hc + kMark, mc, s);
+                if (e != hipSuccess) return wait_fail(e);
+            }
             const double tr = std::sqrt(hc[S_AUX]) / nbn;
             *relres = tr;
             if (tr <= tol) return 0;
@@ -579,18 +597,27 @@ template int bicgstab<double>(const LinOp&, const LinOp&, size_t, const double*,
 template int bicgstab<float>(const LinOp&, const LinOp&, size_t, const float*, float*, bool, double, int, void*,
                              int*, double*, std::string&, hipStream_t, const LinOp*, bool);
 
-// FP64 norm of a vector (two-pass), synchronising.
+// FP64 norm of a vector (two-pass); returns once the stream's work up to it is done.
 int norm2(const double* x, size_t N, void* part_ws, double* out, std::string& err, hipStream_t s) {
     double* part = reinterpret_cast<double*>(part_ws);
     double* sc = part + 3 * kMaxBlocks;
     const int nb = nblocks(N);
     hipLaunchKernelGGL((dot_partial<double, 1>), dim3(nb), dim3(kT), 0, s, x, x, (const double*)nullptr,
                        (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, N, part);
-    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE, nullptr, 0.0);
-    double* h = host_scalars();
-    KR_TRY(hipMemcpyAsync(h, sc, sizeof(double), hipMemcpyDeviceToHost, s));
-    KR_TRY(hipStreamSynchronize(s));
-    *out = std::sqrt(h[0]);
+    double *h = nullptr, *hdev = nullptr;
+    if (!host_block(&h, &hdev)) {
+        err = "could not allocate pinned host memory";
+        return WQ_EHIP_CODE;
+    }
+    const double m = next_mark();
+    hipLaunchKernelGGL((dot_final<1>), dim3(1), dim3(kT), 0, s, part, nb, sc, 0, (int)F_STORE, hdev + 80, m);
+    KR_TRY(hipGetLastError());
+    const hipError_t e = wait_marker(h + 80 + kMark, m, s);      // (all queued work is done then)
+    if (e != hipSuccess) {
+        err = e == hipErrorUnknown ? "norm not received from the device" : hipGetErrorString(e);
+        return WQ_EHIP_CODE;
+    }
+    *out = std::sqrt(h[80]);
     return 0;
 }
 
