@@ -274,8 +274,12 @@ void fd_destroy(fd_pc P);
  * exit.  Stops when |b - K~ x|_2 / |b|_2 <= rtol (recurrence residual, then
  * confirmed with the true residual; a failed confirmation restarts the
  * recurrence from the true residual).  ws: device, at least
- * krylov_ws_bytes(A) bytes.  Synchronises once per iteration (one small
- * device-to-host copy).  *iters, *relres: host outputs (*relres: the true
+ * krylov_ws_bytes(A) bytes.  Waits once per iteration for a small scalar
+ * block that the device writes into pinned host memory (the calling thread
+ * polls it); returns once the stream's work up to the last read-back is done
+ * (work enqueued ahead of it, such as the next iteration's first half, may
+ * still run on s; it writes only the workspace).  *iters, *relres: host
+ * outputs (*relres: the true
  * relative residual on success, the last recurrence value on WQ_ENOCONV).
  * Errors: WQ_EINVAL, WQ_ENOMEM, WQ_ENOCONV, WQ_EBREAKDOWN, WQ_ENONFINITE, WQ_EHIP.
  * ------------------------------------------------------------------------ */
