@@ -211,7 +211,7 @@ struct WaveMM<1, true> {
 
 // The operands of a contraction step live in rings of R = DL + 1 registers, not
 // in arrays over the whole contraction, so a wave holds few registers (FP64:
-// 55 in the xy pass, 73-76 in the z pass) and several workgroups share a CU,
+// 47-52 in the xy pass, 60-66 in the z pass) and several workgroups share a CU,
 // one's load latency, barrier and stores overlapping another's products.  Step
 // s of the first matrix and of the data go to slot s % R, DL steps ahead of
 // their product; once the first matrix's last step is issued, the second
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;
     constexpr int LDQ = 16 * KB + 1;
-    constexpr int DL = 8, R = DL + 1, LA = 2;        // load lead (measured 5-8 best), LDS lead
+    constexpr int DL = 6, R = DL + 1, LA = 4;        // load lead, LDS lead (measured: 6 and 4 best)
     __shared__ T sQ[16 * LDQ];
     const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(64 * KB) void fd_z_pass(const typename G<PREC>::T* 
     using T = typename G<PREC>::T;
     constexpr int NKS = 4 * KB;
     constexpr int LDP = 16 * KB;
-    constexpr int DL = 8, R = DL + 1, LA = 2;        // load lead (measured 5-8 best), LDS lead
+    constexpr int DL = 6, R = DL + 1, LA = 4;        // load lead, LDS lead (measured: 6 and 4 best)
     __shared__ T sY[16 * KB * FLD];
     const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
