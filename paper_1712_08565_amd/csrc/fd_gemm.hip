@@ -234,7 +234,18 @@ __global__ __launch_bounds__(64 * KB) void fd_xy_pass(const typename G<PREC>::T*
     __shared__ T sQ[16 * LDQ];
     const int lane = threadIdx.x & 63, t = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int cl = lane & 15, kb = lane >> 4;
-    const int r0 = blockIdx.x * 16, z = blockIdx.y;
+    // workgroup -> (row block, plane): consecutive workgroups are dealt
+    // round-robin to the eight XCDs, so hand each XCD a contiguous run of
+    // (row block, plane) items: the row blocks of a plane, which all read the
+    // whole plane, then mostly share one XCD's L2
+    int r0, z;
+    {
+        const int nrb = gridDim.x, nblk = gridDim.x * gridDim.y, b = blockIdx.x + blockIdx.y * gridDim.x;
+        const int base = nblk / 8, rem = nblk % 8, xcd = b % 8, slot = b / 8;
+        const int lin = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
+        r0 = (lin % nrb) * 16;
+        z = lin / nrb;
+    }
     const int tl = (n1 - 1) >> 4;
     if (t > tl) {
         lds_sync();
@@ -463,7 +474,18 @@ __global__ __launch_bounds__(128 * NSM) void fd_xy_pass_bf16(const float* __rest
     __shared__ __align__(16) float sQ[16 * LDQ];
     const int lane = threadIdx.x & 63, t = threadIdx.x >> 6;
     const int cl = lane & 15, kb = lane >> 4;
-    const int r0 = blockIdx.x * 16, z = blockIdx.y;
+    // workgroup -> (row block, plane): consecutive workgroups are dealt
+    // round-robin to the eight XCDs, so hand each XCD a contiguous run of
+    // (row block, plane) items: the row blocks of a plane, which all read the
+    // whole plane, then mostly share one XCD's L2
+    int r0, z;
+    {
+        const int nrb = gridDim.x, nblk = gridDim.x * gridDim.y, b = blockIdx.x + blockIdx.y * gridDim.x;
+        const int base = nblk / 8, rem = nblk % 8, xcd = b % 8, slot = b / 8;
+        const int lin = (xcd < rem ? xcd * (base + 1) : rem * (base + 1) + (xcd - rem) * base) + slot;
+        r0 = (lin % nrb) * 16;
+        z = lin / nrb;
+    }
     const size_t pbase = (size_t)z * n1 * n2;
     const int kb1 = (n1 + 15) >> 4;                      // waves with columns j1 / i1
     const int ns1 = (n1 + 31) >> 5, ns2 = (n2 + 31) >> 5;
